@@ -325,7 +325,7 @@ static int all_finite(const double *v, int n)
 }
 
 int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h,
-                   const orc_opts *o, int *iters)
+                   const orc_opts *o, int *iters, double *x_be)
 {
     int ns = m->ns, N = ns + 1;
     double xk[ORC_NS_MAX + 1], f[ORC_NS_MAX + 1], d[ORC_NS_MAX + 1];
@@ -358,6 +358,7 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
             int neg = 0;
             for (int s = 0; s < ns; ++s) if (xk[s] < -o->y_neg) neg = 1;
             if (neg) break;
+            if (x_be) memcpy(x_be, xk, sizeof(double) * N);
             double T;
             if (orc_invert_T(m, xk, e0, xk[ns], &T) != 0) break;
             xk[ns] = T;
@@ -390,7 +391,7 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         long nsub = 1L << L_forced;
         *level = L_forced;
         for (long j = 0; j < nsub; ++j)
-            if (orc_be_substep(m, rho, e0, x, h, o, iters) != 0) return ORC_FAILED;
+            if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) != 0) return ORC_FAILED;
     } else {
         /* Time is counted in ticks of dt 2^-L_max, so every sub-step boundary is exact. */
         const long long end = 1LL << o->L_max;
@@ -398,7 +399,7 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         int l = 0;
         while (t < end) {
             double h = ldexp(dt, -l);
-            if (orc_be_substep(m, rho, e0, x, h, o, iters) == 0) {
+            if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) == 0) {
                 t += 1LL << (o->L_max - l);
                 if (l > 0 && (t & ((1LL << (o->L_max - l + 1)) - 1)) == 0) --l;
             } else {

@@ -92,9 +92,10 @@ void orc_lu_solve(int n, const double *LU, const int *piv, double *b);
 /* Solve e(Y, T) = e0 for T, starting from T_start.  Returns 0 on success. */
 int orc_invert_T(const orc_mech *m, const double *Y, double e0, double T_start, double *T_out);
 
-/* One backward-Euler sub-step of size h from x (in/out).  Returns 0 on success. */
+/* One backward-Euler sub-step of size h from x (in/out).  Returns 0 on success.  x_be (may
+ * be NULL) receives the converged Newton iterate before the temperature inversion. */
 int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h,
-                   const orc_opts *o, int *iters);
+                   const orc_opts *o, int *iters, double *x_be);
 
 /* One cell over dt.  L_forced < 0: adaptive dyadic sub-stepping (halve on failure, double
  * after a success when aligned); L_forced >= 0: exactly 2^L_forced equal sub-steps.

@@ -66,7 +66,7 @@ def lib():
         L.orc_lu_factor.argtypes = [i, vp, vp]; L.orc_lu_factor.restype = i
         L.orc_lu_solve.argtypes = [i, vp, vp, vp]
         L.orc_invert_T.argtypes = [vp, vp, d, d, vp]; L.orc_invert_T.restype = i
-        L.orc_be_substep.argtypes = [vp, d, d, vp, d, vp, vp]; L.orc_be_substep.restype = i
+        L.orc_be_substep.argtypes = [vp, d, d, vp, d, vp, vp, vp]; L.orc_be_substep.restype = i
         L.orc_advance.argtypes = [vp, l, vp, vp, vp, vp, d, vp, i, vp, vp, vp, i]
         L.orc_energy_batch.argtypes = [vp, l, vp, vp, vp]
         L.orc_residual_ld.argtypes = [vp, d, vp, vp, d, vp, vp]; L.orc_residual_ld.restype = d
@@ -154,11 +154,13 @@ class OracleMech:
         return rc, float(T[0])
 
     def be_substep(self, rho: float, e0: float, x, h: float, opts: Optional[Opts] = None):
+        """One sub-step: (rc, x after T inversion, Newton iterations, Newton root)."""
         x = np.array(x, dtype=np.float64)
+        xbe = np.zeros_like(x)
         it = np.zeros(1, np.int32)
         rc = lib().orc_be_substep(self.ref, float(rho), float(e0), _p(x), float(h),
-                                  C.byref(opts or default_opts()), _p(it))
-        return rc, x, int(it[0])
+                                  C.byref(opts or default_opts()), _p(it), _p(xbe))
+        return rc, x, int(it[0]), xbe
 
     def residual(self, rho: float, x_prev, x, h: float, opts: Optional[Opts] = None):
         G = np.zeros(self.ns + 1)
