@@ -1,0 +1,186 @@
+/*
+ * kin.h -- C ABI of libkin, the MI355X (gfx950) implicit chemical-kinetics library.
+ *
+ * The library advances batches of independent cells, each a constant-density,
+ * constant-internal-energy 0-D reactor, over one time step dt by Newton-iterated backward
+ * Euler with dyadic sub-step halving.  This is the chemistry half of the operator-split
+ * reactive Euler solver of Le & Cambier (arXiv:1110.4903): the operator split itself
+ * (Sec. 2, Eq. "operator_splitting") hands the chemistry one sub-step per flow step, each
+ * cell is independent (Sec. 4.2), and the per-cell work is the point-implicit system
+ * (I - dt dOmega/dQ) dQ = dt Omega of Sec. 3.2 (Eq. "kinetics") with rates built from the
+ * Arrhenius law, the equilibrium constant and third-body sums of Sec. 3.2.
+ *
+ * Conventions
+ *   - Plain C types only; every pointer is either host memory or device memory as stated.
+ *   - Units at the boundary are SI: rho kg/m^3, T K, e J/kg, dt s.  Mechanism data are in
+ *     the usual CGS kinetics units (mol, cm^3, s) and NASA-7 dimensionless coefficients.
+ *   - Cell arrays are structure-of-arrays: rho[n], T[n], e0[n], and Y species-major
+ *     [Ns][n] (cell index fastest), which is also the layout kept in device memory.
+ *   - Every call returns a kin_status; KIN_OK is 0.  The message of the calling thread's
+ *     last failure is available from kin_last_error().  No C++ exception crosses the ABI.
+ *   - A per-cell numerical failure is not a call error: it is reported in the cell's status.
+ *   - Thread safety: a context is guarded by an internal mutex; calls on one context from
+ *     several host threads are serialised.  Work is enqueued on the caller's HIP stream.
+ *   - KIN_EDEVICE means a HIP runtime error; the context must then be destroyed.
+ */
+#ifndef KIN_H
+#define KIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KIN_OK = 0,
+    KIN_EINVAL = 1,     /* invalid argument or mechanism */
+    KIN_ENOMEM = 2,     /* the request exceeds the context's device-memory budget */
+    KIN_EBUSY = 3,      /* the object is still referenced */
+    KIN_ENOTFOUND = 4,  /* unknown mechanism or instance id */
+    KIN_EDEVICE = 5,    /* HIP runtime failure; destroy the context */
+    KIN_ECOMPILE = 6    /* run-time compilation of a mechanism kernel failed */
+} kin_status;
+
+typedef enum { KIN_FP64 = 0, KIN_FP32_LU = 1 } kin_precision;
+typedef enum { KIN_MEM_HOST = 0, KIN_MEM_DEVICE = 1 } kin_mem;
+
+/* Kernel layouts: one cell per lane with the Newton matrix in registers, or one cell per
+ * 64-wide wavefront with one matrix row per lane and the Jacobian staged in LDS. */
+typedef enum { KIN_LAYOUT_AUTO = 0, KIN_LAYOUT_LANE = 1, KIN_LAYOUT_WAVE = 2 } kin_layout;
+
+/* Per-cell status codes written by kin_advance. */
+enum {
+    KIN_CELL_OK = 0,         /* accepted as one sub-step of dt */
+    KIN_CELL_OK_HALVED = 1,  /* accepted after at least one sub-step halving */
+    KIN_CELL_FAILED = 2,     /* halving passed L_max; the cell keeps its input state */
+    KIN_CELL_BAD_INPUT = 3   /* non-finite input, rho <= 0 or T outside [200, 6000] K */
+};
+
+typedef struct kin_ctx kin_ctx;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    uint64_t hbm_budget;     /* bytes of instance state the context may hold; 0 = no limit */
+    const char *tune_cache;  /* autotuner cache file (JSON); NULL = $KIN_TUNE_CACHE or none */
+} kin_ctx_opts;
+
+/* Mechanism description (host memory, copied by kin_mech_upload; the caller keeps it).
+ * Reactions have up to three reactant and three product entries (index, coefficient);
+ * unused entries have index -1.  A reaction with tb[r] >= 0 multiplies its net rate by the
+ * third-body concentration sum_s eff[tb[r]][s] X_s (Sec. 3.2, rate-of-progress equation). */
+typedef struct {
+    int32_t ns;                /* species, 1..63 */
+    int32_t ne;                /* elements, >= 1 */
+    int32_t nr;                /* reactions, >= 1 */
+    int32_t ntb;               /* rows of eff */
+    const double *M;           /* [ns] molar mass, g/mol */
+    const int8_t *elem;        /* [ns][ne] atoms of each element */
+    const double *nasa;        /* [ns][2][7]: set 0 for T < T_mid, set 1 otherwise */
+    const double *T_mid;       /* [ns] K */
+    const int32_t *reac_idx;   /* [nr][3] */
+    const int32_t *reac_nu;    /* [nr][3], 1..3 where used */
+    const int32_t *prod_idx;   /* [nr][3] */
+    const int32_t *prod_nu;    /* [nr][3] */
+    const double *A;           /* [nr] pre-exponential factor, CGS units, > 0 */
+    const double *b;           /* [nr] temperature exponent */
+    const double *Ta;          /* [nr] activation temperature E/R, K */
+    const int32_t *reversible; /* [nr] 1: reverse rate from the equilibrium constant; 0: none */
+    const int32_t *tb;         /* [nr] -1 or row of eff */
+    const double *eff;         /* [ntb][ns] third-body efficiencies, >= 0 */
+} kin_mech_desc;
+
+/* Newton / sub-stepping controls.  Defaults (kin_default_solver_opts): rtol 1e-12,
+ * atol_Y 1e-20, atol_T 1e-9 K, y_neg 1e-10, k_max 10, L_max 40, layout AUTO, L_forced -1,
+ * max_iters 100000. */
+typedef struct {
+    double rtol;       /* Newton converged when |dx_i| <= atol_i + rtol |x_i| for all i */
+    double atol_Y;
+    double atol_T;
+    double y_neg;      /* a converged iterate with some Y_s < -y_neg is rejected */
+    int32_t k_max;     /* Newton iterations per sub-step attempt */
+    int32_t L_max;     /* deepest halving level, sub-step dt 2^-L, 0..62 */
+    int32_t layout;    /* kin_layout */
+    int32_t L_forced;  /* -1: adaptive; >= 0: exactly 2^L_forced equal sub-steps */
+    int32_t max_iters; /* Newton iterations per cell before it is declared FAILED */
+} kin_solver_opts;
+
+void kin_default_solver_opts(kin_solver_opts *s);
+
+/* Message of the calling thread's last non-OK status ("" if none). */
+const char *kin_last_error(void);
+
+/* Create a context on a device.  o may be NULL (device 0, no budget, no tune cache). */
+kin_status kin_create(kin_ctx **out, const kin_ctx_opts *o);
+
+/* Free every device allocation and compiled module of the context.  Safe on NULL. */
+void kin_destroy(kin_ctx *ctx);
+
+/* Validate and copy a mechanism to the device; returns its id.  Validation: counts in
+ * range, indices in range, coefficients 1..3, every reaction element-balanced, A > 0,
+ * finite parameters, cp > 0 over [200, 6000] K, efficiencies >= 0.  Species count decides
+ * the default layout (lane layout when ns <= 15); a mechanism that will run the lane
+ * layout gets its kernels compiled here (hipRTC, gfx950). */
+kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_id);
+
+/* KIN_EBUSY while instances still use the mechanism. */
+kin_status kin_mech_release(kin_ctx *ctx, int32_t mech_id);
+
+/* Copy n_cells cell states into a new device-resident instance of a mechanism.  rho, T,
+ * Y (and e0) live in host or device memory as `where` says; device copies are enqueued on
+ * `stream` (a hipStream_t, NULL = the null stream), host copies complete before return.
+ * e0_or_null: per-cell internal energy e0 (J/kg) the step conserves; NULL computes
+ * e0 = e(Y, T) on the device.  KIN_ENOMEM if the context budget would be exceeded. */
+kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, const double *rho,
+                            const double *T, const double *Y, const double *e0_or_null,
+                            kin_mem where, void *stream, int32_t *inst_id);
+
+/* Overwrite an existing instance's state (same cell count) without allocating. */
+kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, const double *T,
+                           const double *Y, const double *e0_or_null, kin_mem where,
+                           void *stream);
+
+/* Advance n instances by their dts[n] on `stream`, asynchronously.  Each instance's T and Y
+ * are replaced by the step's result (a failed cell keeps its state) and its status, level
+ * (deepest halving level) and iters (Newton iterations including failed tries) are written.
+ * s may be NULL for the defaults.  With n > 1 all instances go out in one graph launch. */
+kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
+                       kin_precision prec, const kin_solver_opts *s, void *stream);
+
+/* Copy an instance's state and diagnostics into caller buffers (any pointer may be NULL).
+ * Host destinations: synchronous.  Device destinations: enqueued on `stream`. */
+kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, int32_t *status,
+                        int32_t *level, int32_t *iters, kin_mem where, void *stream);
+
+/* Wait for `stream` (NULL = the null stream). */
+kin_status kin_sync(kin_ctx *ctx, void *stream);
+
+kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id);
+
+/* Device bytes an instance of n_cells cells of a mechanism occupies. */
+kin_status kin_footprint(const kin_ctx *ctx, int32_t mech_id, int64_t n_cells,
+                         kin_precision prec, uint64_t *bytes);
+
+typedef enum {
+    KIN_Q_BYTES_IN_USE = 0,   /* out: uint64 */
+    KIN_Q_LAYOUT = 1,         /* arg: mech id; out: int32 kin_layout chosen */
+    KIN_Q_BLOCK = 2,          /* arg: mech id; out: int32 threads per block of that layout */
+    KIN_Q_NUM_CU = 3,         /* out: int32 */
+    KIN_Q_DEVICE_PTRS = 4,    /* arg: instance id; out: 7 x uint64 rho, e0, T, Y, status, level, iters */
+    KIN_Q_JIT_SECONDS = 5     /* arg: mech id; out: double compile time of its lane kernels */
+} kin_query_what;
+
+kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
+
+/* Set a mechanism's layout and block size (what the autotuner decides). */
+kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
+
+/* Generate the lane-layout source for a mechanism and compile it for gfx950 with hipRTC,
+ * without a device.  log (may be NULL) receives up to log_len bytes of compiler output. */
+kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -9,14 +9,16 @@
  *    implicit system (I - h df/dx) dx = -G is iterated as Newton's method on backward Euler,
  *    G = x - x_prev - h f(x), starting from x_prev (the paper's point-implicit step is the
  *    first Newton iteration);
- *  - convergence when max_i |dx_i| / (atol_i + rtol |x_i|) <= 1 after the update;
+ *  - convergence when |dx_i| <= atol_i + rtol |x_i| for every i after the update (each
+ *    Newton iteration is counted when it starts);
  *  - failure of a sub-step: no convergence within k_max iterations, a non-finite value, an
  *    exactly zero pivot, T outside [200, 6000] K, a converged iterate with a mass fraction
  *    below -y_neg, or no root of e(Y, T) = e0 in [200, 6000] K;
  *  - sub-stepping is dyadic: sub-step h = dt 2^-l starts at l = 0; a failed sub-step is
  *    retried from the last accepted state at l + 1; after an accepted sub-step l drops by
  *    one when the elapsed time is a multiple of the doubled step; l > L_max fails the cell,
- *    which keeps its input state;
+ *    which keeps its input state, and so does a cell that has used max_iters Newton
+ *    iterations before the end of its step;
  *  - after each accepted sub-step T is reset to the root of e(Y, T) = e0;
  *  - R is the universal gas constant and P_a one standard atmosphere.
  */
@@ -69,6 +71,7 @@ void orc_default_opts(orc_opts *o)
     o->y_neg = 1e-10;
     o->k_max = 10;
     o->L_max = 40;
+    o->max_iters = 100000;
 }
 
 int orc_num_threads(void)
@@ -334,6 +337,7 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
     int rc = -1;
     memcpy(xk, x, sizeof(double) * N);
     for (int k = 0; k < o->k_max; ++k) {
+        ++*iters;
         orc_rhs(m, rho, xk, f);
         orc_jacobian(m, rho, xk, A);
         if (!all_finite(f, N) || !all_finite(A, N * N)) break;
@@ -345,16 +349,14 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
         if (orc_lu_factor(N, A, piv) != 0) break;
         orc_lu_solve(N, A, piv, d);
         for (int i = 0; i < N; ++i) xk[i] += d[i];
-        ++*iters;
         if (!all_finite(xk, N)) break;
         if (xk[ns] < ORC_T_MIN || xk[ns] > ORC_T_MAX) break;
-        double worst = 0;
+        int conv = 1;
         for (int i = 0; i < N; ++i) {
             double atol = (i < ns) ? o->atol_Y : o->atol_T;
-            double r = fabs(d[i]) / (atol + o->rtol * fabs(xk[i]));
-            if (r > worst) worst = r;
+            if (!(fabs(d[i]) <= atol + o->rtol * fabs(xk[i]))) conv = 0;
         }
-        if (worst <= 1.0) {
+        if (conv) {
             int neg = 0;
             for (int s = 0; s < ns; ++s) if (xk[s] < -o->y_neg) neg = 1;
             if (neg) break;
@@ -390,14 +392,17 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         double h = ldexp(dt, -L_forced);
         long nsub = 1L << L_forced;
         *level = L_forced;
-        for (long j = 0; j < nsub; ++j)
+        for (long j = 0; j < nsub; ++j) {
+            if (*iters >= o->max_iters) return ORC_FAILED;
             if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) != 0) return ORC_FAILED;
+        }
     } else {
         /* Time is counted in ticks of dt 2^-L_max, so every sub-step boundary is exact. */
         const long long end = 1LL << o->L_max;
         long long t = 0;
         int l = 0;
         while (t < end) {
+            if (*iters >= o->max_iters) return ORC_FAILED;
             double h = ldexp(dt, -l);
             if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) == 0) {
                 t += 1LL << (o->L_max - l);

@@ -54,6 +54,7 @@ typedef struct {
     double rtol, atol_Y, atol_T;
     double y_neg;           /* a converged iterate with some Y_s < -y_neg is rejected */
     int k_max, L_max;
+    int max_iters;          /* Newton iterations per cell before it is declared failed */
 } orc_opts;
 
 /* Per-cell status codes. */

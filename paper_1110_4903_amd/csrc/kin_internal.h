@@ -1,0 +1,111 @@
+// kin_internal.h -- host-side structures shared by the libkin translation units.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "kin.h"
+
+namespace kin {
+
+constexpr int kNsMax = 63;          // N = Ns + 1 <= 64: one matrix row per wavefront lane
+constexpr int kLaneNsMax = 15;      // lane layout holds the whole matrix in registers
+constexpr double kRu = 8.31446261815324;          // J/(mol K)
+constexpr double kRuCgs = 8.31446261815324e7;     // erg/(mol K)
+constexpr double kPatmCgs = 1.01325e6;            // dyn/cm^2 (one standard atmosphere)
+
+// One species taking part in a reaction, with its reactant, product and net coefficients.
+struct Part {
+    int sp;
+    int nu_r;   // nu'  (reactant side)
+    int nu_p;   // nu'' (product side)
+    int nu;     // nu'' - nu'
+};
+
+struct Rxn {
+    double A, lnA, b, Ta;
+    int rev;     // 1: reverse rate through the equilibrium constant
+    int tb;      // -1 or row of the efficiency table
+    int dnu;     // sum nu'' - sum nu' over species
+    int nreac, nprod, npart;
+    int reac_sp[3], reac_nu[3];  // merged by species
+    int prod_sp[3], prod_nu[3];
+    Part part[6];
+};
+
+// Validated, preprocessed copy of a kin_mech_desc.
+struct MechHost {
+    int ns = 0, ne = 0, nr = 0, ntb = 0;
+    std::vector<double> M, nasa, Tmid;
+    std::vector<int8_t> elem;
+    std::vector<Rxn> rx;
+    std::vector<double> eff;
+    bool single_range(int s) const;  // both NASA sets identical
+};
+
+// Validate d and build the preprocessed copy.  Returns KIN_OK or KIN_EINVAL with msg set.
+kin_status mech_from_desc(const kin_mech_desc *d, MechHost &m, std::string &msg);
+
+// Source of the lane-layout module for a mechanism: generated mechanism functions followed
+// by the hand-written template.  block = threads per block.  consts receives the table of
+// FP64 constants the generated code reads as K[i].
+std::string lane_source(const MechHost &m, int block, std::vector<double> &consts);
+
+// Compile HIP source for gfx950 with hipRTC.  Returns KIN_OK and the code object, or
+// KIN_ECOMPILE with the log in msg.
+kin_status rtc_compile(const std::string &src, const char *name, std::vector<char> &code,
+                       std::string &msg, double *seconds);
+
+void set_error(const std::string &msg);
+
+}  // namespace kin
+
+namespace kin {
+
+// Mechanism tables in device memory, read by the table-driven kernels (wave layout and the
+// initial-energy kernel).  All pointers point into one allocation.
+constexpr int kRxi = 32;     // ints per reaction in rxi
+constexpr int kChunk = 64;   // reactions evaluated per wavefront pass
+struct WaveTables {
+    int ns, nr, ntb, nchunk;
+    double lnPaR;         // ln(P_atm / R) in CGS units
+    const double *nasa;   // [ns][14]
+    const double *Tmid;   // [ns]
+    const double *M;      // [ns] g/mol
+    const double *rxd;    // [nr][4]: ln A, b, Ta, sum nu
+    const int *rxi;       // [nr][kRxi]: rev, tb, nreac, nprod, reac sp[3], reac nu[3],
+                          //   prod sp[3], prod nu[3], npart, part sp[6], part net nu[6]
+    const double *eff;    // [ntb][ns]
+    const int *sp_ptr;    // [ns][nchunk + 1] start of each chunk's entries of species s
+    const int *sp_list;   // entries r * 16 + (nu + 8) of reactions with nonzero net nu
+};
+
+// Arguments of one advance launch (both layouts); mirrors the device-side argument struct.
+struct AdvanceArgs {
+    long long n;
+    long long ld;
+    double dt;
+    const double *rho;
+    const double *e0;
+    double *T;
+    double *Y;
+    int *status;
+    int *level;
+    int *iters;
+    double rtol, atol_Y, atol_T, y_neg;
+    int k_max, L_max, L_forced, max_iters;
+    const double *K;   // lane layout: the mechanism's constant table
+};
+
+// Host launchers of the precompiled kernels (kin_wave.hip).
+int wave_npad(int n);
+hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,
+                         const double *Y, double *e0, hipStream_t stream);
+hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, int waves_per_block,
+                       int grid, hipStream_t stream);
+size_t wave_lds_bytes(const WaveTables &t, bool fp32_lu);
+
+}  // namespace kin

@@ -1,0 +1,272 @@
+// kin_lane_template.h -- device code of the lane layout: one cell per lane, the (Ns+1)^2
+// Newton matrix held in registers.  Compiled at mechanism upload (hipRTC, gfx950) after the
+// generated mechanism code, which defines KIN_NS, KIN_N, KIN_BLOCK and
+//   kin_eval(rho, x, f, J)        f = dx/dt and J = df/dx of the constant-(rho, e) cell
+//   kin_energy_cv(Y, T, e, cv)    mixture internal energy (J/kg) and c_v (J/kg/K)
+// Every array below is indexed only by compile-time constants after unrolling, so the
+// compiler keeps it in VGPRs.  Partial pivoting is done with selects (v_cndmask), since a
+// register file cannot be indexed by a per-lane pivot row.
+//
+// Method (Le & Cambier, arXiv:1110.4903, Sec. 3.2, Eq. "kinetics"): the point-implicit
+// system (I - h J) dx = -G with G = x - x_prev - h f(x), iterated as Newton's method on
+// backward Euler; the dense solve is Gaussian elimination with partial pivoting (Sec. 4.2).
+
+struct KinLaneArgs {
+    long long n;          // cells in this launch
+    long long ld;         // leading dimension of Y (cells per species row)
+    double dt;
+    const double *rho;
+    const double *e0;
+    double *T;
+    double *Y;
+    int *status;
+    int *level;
+    int *iters;
+    double rtol, atol_Y, atol_T, y_neg;
+    int k_max, L_max, L_forced, max_iters;
+    const double *K;      // the mechanism's constant table (KIN_NCONST values)
+};
+
+// The constant table is read through a pointer the compiler cannot see through, once per
+// use site: the scalar loads of K[] then stay next to their uses instead of being hoisted
+// out of the Newton loop, which would pin hundreds of constants in SGPRs.
+__device__ __forceinline__ kin_cptr kin_launder(const double *p)
+{
+    asm volatile("" : "+s"(p));
+    return (kin_cptr)p;
+}
+
+#define KIN_T_MIN 200.0
+#define KIN_T_MAX 6000.0
+
+// Solve e(Y, T) = e0 for T: Newton on c_v > 0 from T0, bisection on [200, 6000] K if
+// Newton leaves the range or does not settle in 20 steps.
+__device__ __forceinline__ bool kin_invert_T(const double *Kp, const double (&x)[KIN_N], double e0,
+                                             double T0, double &T_out)
+{
+    double T = T0;
+    for (int it = 0; it < 20; ++it) {
+        double e, cv;
+        kin_energy_cv(kin_launder(Kp), x, T, e, cv);
+        if (!(cv > 0.0)) break;
+        const double dT = (e - e0) / cv;
+        T -= dT;
+        if (!__builtin_isfinite(T) || T < KIN_T_MIN || T > KIN_T_MAX) break;
+        if (fabs(dT) <= 1e-13 * T) { T_out = T; return true; }
+    }
+    double lo = KIN_T_MIN, hi = KIN_T_MAX, e, cv;
+    kin_energy_cv(kin_launder(Kp), x, lo, e, cv);
+    const double flo = e - e0;
+    kin_energy_cv(kin_launder(Kp), x, hi, e, cv);
+    const double fhi = e - e0;
+    if (!(flo <= 0.0 && fhi >= 0.0)) return false;
+    for (int it = 0; it < 200 && hi - lo > 1e-13 * lo; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        kin_energy_cv(kin_launder(Kp), x, mid, e, cv);
+        if (e - e0 > 0.0) hi = mid; else lo = mid;
+    }
+    T_out = 0.5 * (lo + hi);
+    return true;
+}
+
+// In-register LU with partial pivoting (first row of largest |a_ik|), applied to the
+// right-hand side as it goes, then back substitution.  R is the factorisation type.
+// Returns false on an exactly zero pivot.
+template <typename R>
+__device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N])
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < KIN_N; ++k) {
+        R amax = fabs(A[k][k]);
+        int p = k;
+#pragma unroll
+        for (int i = k + 1; i < KIN_N; ++i) {
+            const R v = fabs(A[i][k]);
+            const bool gt = v > amax;
+            amax = gt ? v : amax;
+            p = gt ? i : p;
+        }
+        ok = ok && (amax != R(0));
+        // Row exchange by selects; skipped for the whole wavefront when no lane pivots off
+        // the diagonal (the common case for I - hJ at moderate h).
+        if (__any(p != k)) {
+#pragma unroll
+            for (int j = k; j < KIN_N; ++j) {
+                const R rk = A[k][j];
+                R pv = rk;
+#pragma unroll
+                for (int i = k + 1; i < KIN_N; ++i) pv = (p == i) ? A[i][j] : pv;
+#pragma unroll
+                for (int i = k + 1; i < KIN_N; ++i) A[i][j] = (p == i) ? rk : A[i][j];
+                A[k][j] = pv;
+            }
+            const R rk = b[k];
+            R pv = rk;
+#pragma unroll
+            for (int i = k + 1; i < KIN_N; ++i) pv = (p == i) ? b[i] : pv;
+#pragma unroll
+            for (int i = k + 1; i < KIN_N; ++i) b[i] = (p == i) ? rk : b[i];
+            b[k] = pv;
+        }
+        const R inv = R(1) / A[k][k];
+#pragma unroll
+        for (int i = k + 1; i < KIN_N; ++i) {
+            const R l = A[i][k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < KIN_N; ++j) A[i][j] = fma(-l, A[k][j], A[i][j]);
+            b[i] = fma(-l, b[k], b[i]);
+        }
+    }
+#pragma unroll
+    for (int i = KIN_N - 1; i >= 0; --i) {
+        R s = b[i];
+#pragma unroll
+        for (int j = i + 1; j < KIN_N; ++j) s = fma(-A[i][j], b[j], s);
+        b[i] = s / A[i][i];
+    }
+    return ok;
+}
+
+// One backward-Euler sub-step of size h from x (in/out on success).  F32: the Newton matrix
+// and right-hand side are row-equilibrated in FP64, rounded to FP32, factored and solved in
+// FP32; the correction is promoted back to FP64 (residual, rates and exponentials stay FP64).
+template <bool F32>
+__device__ __forceinline__ bool kin_substep(const double rho, const double e0, double (&x)[KIN_N],
+                                            const double h, const KinLaneArgs &a, int &iters)
+{
+    double xk[KIN_N];
+#pragma unroll
+    for (int i = 0; i < KIN_N; ++i) xk[i] = x[i];
+    for (int k = 0; k < a.k_max; ++k) {
+        ++iters;
+        double f[KIN_N];
+        double A[KIN_N][KIN_N];
+        kin_eval(kin_launder(a.K), rho, xk, f, A);
+        double b[KIN_N];
+        double chk = 0.0;
+#pragma unroll
+        for (int i = 0; i < KIN_N; ++i) {
+            b[i] = -((xk[i] - x[i]) - h * f[i]);
+            chk += b[i] - b[i];
+#pragma unroll
+            for (int j = 0; j < KIN_N; ++j) {
+                A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
+                chk += A[i][j] - A[i][j];
+            }
+        }
+        if (!(chk == 0.0)) return false;  // some entry of A or G is not finite
+        double d[KIN_N];
+        if (F32) {
+            float Af[KIN_N][KIN_N], bf[KIN_N];
+#pragma unroll
+            for (int i = 0; i < KIN_N; ++i) {
+                double m = 0.0;
+#pragma unroll
+                for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(A[i][j]));
+                const double s = 1.0 / m;
+#pragma unroll
+                for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(A[i][j] * s);
+                bf[i] = (float)(b[i] * s);
+            }
+            if (!kin_lu_solve<float>(Af, bf)) return false;
+#pragma unroll
+            for (int i = 0; i < KIN_N; ++i) d[i] = (double)bf[i];
+        } else {
+            if (!kin_lu_solve<double>(A, b)) return false;
+#pragma unroll
+            for (int i = 0; i < KIN_N; ++i) d[i] = b[i];
+        }
+        bool conv = true;
+        double chk2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < KIN_N; ++i) {
+            xk[i] += d[i];
+            chk2 += xk[i] - xk[i];
+            const double atol = (i < KIN_NS) ? a.atol_Y : a.atol_T;
+            conv = conv && (fabs(d[i]) <= atol + a.rtol * fabs(xk[i]));
+        }
+        if (!(chk2 == 0.0)) return false;
+        if (xk[KIN_NS] < KIN_T_MIN || xk[KIN_NS] > KIN_T_MAX) return false;
+        if (conv) {
+            bool neg = false;
+#pragma unroll
+            for (int s = 0; s < KIN_NS; ++s) neg = neg || (xk[s] < -a.y_neg);
+            if (neg) return false;
+            double T;
+            if (!kin_invert_T(a.K, xk, e0, xk[KIN_NS], T)) return false;
+            xk[KIN_NS] = T;
+#pragma unroll
+            for (int i = 0; i < KIN_N; ++i) x[i] = xk[i];
+            return true;
+        }
+    }
+    return false;
+}
+
+template <bool F32>
+__device__ __forceinline__ void kin_cell(const KinLaneArgs &a, const long long i)
+{
+    const double rho = a.rho[i];
+    const double e0 = a.e0[i];
+    double x[KIN_N];
+#pragma unroll
+    for (int s = 0; s < KIN_NS; ++s) x[s] = a.Y[s * a.ld + i];
+    x[KIN_NS] = a.T[i];
+    double chk = rho - rho + e0 - e0 + a.dt - a.dt;
+#pragma unroll
+    for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
+    if (!(chk == 0.0) || !(rho > 0.0) || !(a.dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
+        x[KIN_NS] > KIN_T_MAX) {
+        a.status[i] = 3;
+        a.level[i] = 0;
+        a.iters[i] = 0;
+        return;
+    }
+    // Dyadic sub-stepping, time counted in ticks of dt 2^-Lc so that every sub-step boundary
+    // is exact.  Adaptive (L_forced < 0): start at h = dt, halve on failure and retry from
+    // the last accepted state, double after an accepted sub-step that ends on a boundary of
+    // the doubled step.  Replay (L_forced >= 0): 2^L_forced equal sub-steps, no adaptation.
+    const bool adapt = a.L_forced < 0;
+    const int Lc = adapt ? a.L_max : a.L_forced;
+    const unsigned long long end = 1ull << Lc;
+    unsigned long long t = 0;
+    int l = adapt ? 0 : a.L_forced;
+    int iters = 0, level = l, st = 0;
+    bool failed = false;
+    while (t < end) {
+        if (iters >= a.max_iters) { st = 2; break; }
+        const double h = ldexp(a.dt, -l);
+        if (kin_substep<F32>(rho, e0, x, h, a, iters)) {
+            t += 1ull << (Lc - l);
+            if (adapt && l > 0 && (t & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
+        } else {
+            if (!adapt) { st = 2; break; }
+            failed = true;
+            ++l;
+            if (l > level) level = l;
+            if (l > a.L_max) { level = a.L_max; st = 2; break; }
+        }
+    }
+    if (st == 0 && failed) st = 1;
+    if (st != 2) {
+#pragma unroll
+        for (int s = 0; s < KIN_NS; ++s) a.Y[s * a.ld + i] = x[s];
+        a.T[i] = x[KIN_NS];
+    }
+    a.status[i] = st;
+    a.level[i] = level;
+    a.iters[i] = iters;
+}
+
+extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f64(KinLaneArgs a)
+{
+    const long long i = (long long)blockIdx.x * KIN_BLOCK + threadIdx.x;
+    if (i < a.n) kin_cell<false>(a, i);
+}
+
+extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f32lu(KinLaneArgs a)
+{
+    const long long i = (long long)blockIdx.x * KIN_BLOCK + threadIdx.x;
+    if (i < a.n) kin_cell<true>(a, i);
+}

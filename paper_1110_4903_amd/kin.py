@@ -1,0 +1,266 @@
+"""ctypes binding of libkin.so (include/kin.h).  Argument marshalling only: every step of the
+kinetics update runs in the library's HIP kernels.
+
+Device arrays may be passed as torch tensors (their data_ptr() is handed over with
+KIN_MEM_DEVICE and the current torch stream); host arrays as numpy arrays.  Importing this
+module loads the shared library and raises ImportError if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libkin.so")
+
+OK, EINVAL, ENOMEM, EBUSY, ENOTFOUND, EDEVICE, ECOMPILE = range(7)
+FP64, FP32_LU = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_WAVE = 0, 1, 2
+CELL_OK, CELL_OK_HALVED, CELL_FAILED, CELL_BAD_INPUT = 0, 1, 2, 3
+Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS = range(6)
+
+EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destroy",
+           "kin_mech_upload", "kin_mech_release", "kin_state_upload", "kin_state_reset",
+           "kin_advance", "kin_download", "kin_sync", "kin_instance_release", "kin_footprint",
+           "kin_query", "kin_set_layout", "kin_jit_check")
+
+if not os.path.exists(SO):
+    raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
+_lib = C.CDLL(SO)
+
+
+class KinError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libkin status {status}: {msg}")
+        self.status = status
+
+
+class CtxOpts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget", C.c_uint64), ("tune_cache", C.c_char_p)]
+
+
+class MechDesc(C.Structure):
+    _fields_ = [("ns", C.c_int32), ("ne", C.c_int32), ("nr", C.c_int32), ("ntb", C.c_int32),
+                ("M", C.c_void_p), ("elem", C.c_void_p), ("nasa", C.c_void_p), ("T_mid", C.c_void_p),
+                ("reac_idx", C.c_void_p), ("reac_nu", C.c_void_p), ("prod_idx", C.c_void_p),
+                ("prod_nu", C.c_void_p), ("A", C.c_void_p), ("b", C.c_void_p), ("Ta", C.c_void_p),
+                ("reversible", C.c_void_p), ("tb", C.c_void_p), ("eff", C.c_void_p)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
+                ("y_neg", C.c_double), ("k_max", C.c_int32), ("L_max", C.c_int32),
+                ("layout", C.c_int32), ("L_forced", C.c_int32), ("max_iters", C.c_int32)]
+
+
+_vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+_lib.kin_default_solver_opts.argtypes = [_vp]
+_lib.kin_default_solver_opts.restype = None
+_lib.kin_last_error.restype = C.c_char_p
+_lib.kin_create.argtypes = [_vp, _vp]
+_lib.kin_destroy.argtypes = [_vp]
+_lib.kin_destroy.restype = None
+_lib.kin_mech_upload.argtypes = [_vp, _vp, _vp]
+_lib.kin_mech_release.argtypes = [_vp, _i32]
+_lib.kin_state_upload.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
+_lib.kin_state_reset.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, C.c_int, _vp]
+_lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
+_lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
+_lib.kin_sync.argtypes = [_vp, _vp]
+_lib.kin_instance_release.argtypes = [_vp, _i32]
+_lib.kin_footprint.argtypes = [_vp, _i32, _i64, C.c_int, _vp]
+_lib.kin_query.argtypes = [_vp, _i32, _i64, _vp]
+_lib.kin_set_layout.argtypes = [_vp, _i32, _i32, _i32]
+_lib.kin_jit_check.argtypes = [_vp, C.c_char_p, _sz]
+for _f in EXPORTS:
+    if _f not in ("kin_default_solver_opts", "kin_last_error", "kin_destroy"):
+        getattr(_lib, _f).restype = C.c_int
+
+
+def _check(status: int):
+    if status != OK:
+        raise KinError(status, _lib.kin_last_error().decode(errors="replace"))
+
+
+def solver_opts(**kw) -> SolverOpts:
+    o = SolverOpts()
+    _lib.kin_default_solver_opts(C.byref(o))
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+class _MechArrays:
+    """Contiguous, correctly typed copies of a synth.Mechanism and the descriptor over them."""
+
+    def __init__(self, mech):
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        self.keep = dict(M=f64(mech.M), elem=np.ascontiguousarray(mech.comp, dtype=np.int8),
+                         nasa=f64(mech.nasa), T_mid=f64(mech.T_mid),
+                         reac_idx=i32(mech.reac_idx), reac_nu=i32(mech.reac_nu),
+                         prod_idx=i32(mech.prod_idx), prod_nu=i32(mech.prod_nu),
+                         A=f64(mech.A), b=f64(mech.b), Ta=f64(mech.Ta),
+                         reversible=i32(mech.reversible), tb=i32(mech.tb),
+                         eff=f64(mech.eff if mech.eff.size else np.zeros((1, mech.ns))))
+        d = MechDesc()
+        d.ns, d.ne, d.nr, d.ntb = mech.ns, mech.ne, mech.nr, mech.ntb
+        for k, v in self.keep.items():
+            setattr(d, k, v.ctypes.data)
+        self.desc = d
+
+
+def jit_check(mech) -> str:
+    """Generate and compile a mechanism's lane-layout kernels with hipRTC (no device needed)."""
+    arr = _MechArrays(mech)
+    buf = C.create_string_buffer(1 << 16)
+    _check(_lib.kin_jit_check(C.byref(arr.desc), buf, len(buf)))
+    return buf.value.decode(errors="replace")
+
+
+def _ptr(x):
+    """(address, memory kind) of a numpy array (host) or torch tensor (device)."""
+    if x is None:
+        return None, None
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous or x.dtype not in (np.float64, np.int32):
+            raise ValueError("host arrays must be C-contiguous float64/int32")
+        return x.ctypes.data, MEM_HOST
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("device tensors must be contiguous")
+        return x.data_ptr(), (MEM_DEVICE if x.is_cuda else MEM_HOST)
+    raise TypeError(f"unsupported array type {type(x)}")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+class Context:
+    """A libkin context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_cache: Optional[str] = None):
+        self._h = C.c_void_p()
+        o = CtxOpts(device, hbm_budget, tune_cache.encode() if tune_cache else None)
+        _check(_lib.kin_create(C.byref(self._h), C.byref(o)))
+        self.mech_ns = {}
+        self.inst_info = {}
+
+    def close(self):
+        if self._h:
+            _lib.kin_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- mechanisms -------------------------------------------------------------------------
+    def mech_upload(self, mech) -> int:
+        arr = _MechArrays(mech)
+        mid = C.c_int32()
+        _check(_lib.kin_mech_upload(self._h, C.byref(arr.desc), C.byref(mid)))
+        self.mech_ns[mid.value] = mech.ns
+        return mid.value
+
+    def mech_release(self, mech_id: int):
+        _check(_lib.kin_mech_release(self._h, mech_id))
+
+    def set_layout(self, mech_id: int, layout: int, block: int):
+        _check(_lib.kin_set_layout(self._h, mech_id, layout, block))
+
+    # -- instances --------------------------------------------------------------------------
+    def state_upload(self, mech_id: int, rho, T, Y, e0=None, stream=None) -> int:
+        ns = self.mech_ns[mech_id]
+        n = int(rho.shape[0])
+        if tuple(Y.shape) != (ns, n) or T.shape[0] != n:
+            raise ValueError(f"expected rho[{n}], T[{n}], Y[{ns}][{n}]")
+        (pr, kind), (pt, k2), (py, k3) = _ptr(rho), _ptr(T), _ptr(Y)
+        pe, k4 = _ptr(e0)
+        if len({kind, k2, k3} | ({k4} if e0 is not None else set())) != 1:
+            raise ValueError("all state arrays must live in the same memory")
+        iid = C.c_int32()
+        _check(_lib.kin_state_upload(self._h, mech_id, n, pr, pt, py, pe, kind,
+                                     _stream_handle(stream), C.byref(iid)))
+        self.inst_info[iid.value] = (mech_id, n, ns)
+        return iid.value
+
+    def state_reset(self, inst_id: int, rho, T, Y, e0=None, stream=None):
+        (pr, kind), (pt, _), (py, _) = _ptr(rho), _ptr(T), _ptr(Y)
+        pe, _ = _ptr(e0)
+        _check(_lib.kin_state_reset(self._h, inst_id, pr, pt, py, pe, kind, _stream_handle(stream)))
+
+    def advance(self, inst_ids: Sequence[int], dts: Sequence[float], prec: int = FP64,
+                opts: Optional[SolverOpts] = None, stream=None):
+        ids = np.ascontiguousarray(inst_ids, dtype=np.int32)
+        dd = np.ascontiguousarray(dts, dtype=np.float64)
+        if ids.shape != dd.shape:
+            raise ValueError("one dt per instance")
+        _check(_lib.kin_advance(self._h, ids.ctypes.data, dd.ctypes.data, int(ids.shape[0]), prec,
+                                C.byref(opts) if opts is not None else None, _stream_handle(stream)))
+
+    def download(self, inst_id: int):
+        """Host copies (T, Y, status, level, iters) of an instance."""
+        _, n, ns = self.inst_info[inst_id]
+        T = np.empty(n)
+        Y = np.empty((ns, n))
+        st, lv, it = (np.empty(n, np.int32) for _ in range(3))
+        _check(_lib.kin_download(self._h, inst_id, T.ctypes.data, Y.ctypes.data, st.ctypes.data,
+                                 lv.ctypes.data, it.ctypes.data, MEM_HOST, None))
+        return T, Y, st, lv, it
+
+    def download_device(self, inst_id: int, T, Y, status=None, level=None, iters=None, stream=None):
+        """Device-to-device copy of an instance's state into torch tensors."""
+        ptrs = [(_ptr(a)[0] if a is not None else None) for a in (T, Y, status, level, iters)]
+        _check(_lib.kin_download(self._h, inst_id, *ptrs, MEM_DEVICE, _stream_handle(stream)))
+
+    def sync(self, stream=None):
+        _check(_lib.kin_sync(self._h, _stream_handle(stream)))
+
+    def instance_release(self, inst_id: int):
+        _check(_lib.kin_instance_release(self._h, inst_id))
+        self.inst_info.pop(inst_id, None)
+
+    def footprint(self, mech_id: int, n_cells: int, prec: int = FP64) -> int:
+        b = C.c_uint64()
+        _check(_lib.kin_footprint(self._h, mech_id, n_cells, prec, C.byref(b)))
+        return b.value
+
+    # -- queries ----------------------------------------------------------------------------
+    def query_int(self, what: int, arg: int = 0) -> int:
+        v = C.c_int32()
+        _check(_lib.kin_query(self._h, what, arg, C.byref(v)))
+        return v.value
+
+    def bytes_in_use(self) -> int:
+        v = C.c_uint64()
+        _check(_lib.kin_query(self._h, Q_BYTES_IN_USE, 0, C.byref(v)))
+        return v.value
+
+    def jit_seconds(self, mech_id: int) -> float:
+        v = C.c_double()
+        _check(_lib.kin_query(self._h, Q_JIT_SECONDS, mech_id, C.byref(v)))
+        return v.value
+
+    def device_ptrs(self, inst_id: int):
+        v = (C.c_uint64 * 7)()
+        _check(_lib.kin_query(self._h, Q_DEVICE_PTRS, inst_id, v))
+        return dict(zip(("rho", "e0", "T", "Y", "status", "level", "iters"), list(v)))
