@@ -98,6 +98,7 @@ struct AdvanceArgs {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
     const double *K;   // lane layout: the mechanism's constant table
+    unsigned long long *counter;  // next unclaimed cell (zero at launch)
 };
 
 // Host launchers of the precompiled kernels (kin_wave.hip).

@@ -25,6 +25,7 @@ struct KinLaneArgs {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
+    unsigned long long *counter;  // next unclaimed cell; zero at launch
 };
 
 // The constant table is read through a pointer the compiler cannot see through, once per
@@ -128,145 +129,209 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
     return ok;
 }
 
-// One backward-Euler sub-step of size h from x (in/out on success).  F32: the Newton matrix
-// and right-hand side are row-equilibrated in FP64, rounded to FP32, factored and solved in
-// FP32; the correction is promoted back to FP64 (residual, rates and exponentials stay FP64).
+// Outcome of one Newton iteration of a lane.
+enum { KIN_CONTINUE = 0, KIN_ACCEPTED = 1, KIN_ATTEMPT_FAILED = 2 };
+
+// One Newton iteration on the backward-Euler system of sub-step size h started from x:
+// updates the iterate xk.  F32: the Newton matrix and right-hand side are row-equilibrated
+// in FP64, rounded to FP32, factored and solved in FP32; the correction is promoted back to
+// FP64 (residual, rates and exponentials stay FP64).  On convergence the iterate is checked
+// for negative mass fractions and its temperature is reset to the root of e(Y, T) = e0.
 template <bool F32>
-__device__ __forceinline__ bool kin_substep(const double rho, const double e0, double (&x)[KIN_N],
-                                            const double h, const KinLaneArgs &a, int &iters)
+__device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const double rho,
+                                                    const double e0, const double (&x)[KIN_N],
+                                                    double (&xk)[KIN_N], const double h)
 {
-    double xk[KIN_N];
+    double f[KIN_N];
+    double A[KIN_N][KIN_N];
+    kin_eval(kin_launder(a.K), rho, xk, f, A);
+    double b[KIN_N];
+    double chk = 0.0;
 #pragma unroll
-    for (int i = 0; i < KIN_N; ++i) xk[i] = x[i];
-    for (int k = 0; k < a.k_max; ++k) {
-        ++iters;
-        double f[KIN_N];
-        double A[KIN_N][KIN_N];
-        kin_eval(kin_launder(a.K), rho, xk, f, A);
-        double b[KIN_N];
-        double chk = 0.0;
+    for (int i = 0; i < KIN_N; ++i) {
+        b[i] = -((xk[i] - x[i]) - h * f[i]);
+        chk += b[i] - b[i];
 #pragma unroll
-        for (int i = 0; i < KIN_N; ++i) {
-            b[i] = -((xk[i] - x[i]) - h * f[i]);
-            chk += b[i] - b[i];
-#pragma unroll
-            for (int j = 0; j < KIN_N; ++j) {
-                A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
-                chk += A[i][j] - A[i][j];
-            }
-        }
-        if (!(chk == 0.0)) return false;  // some entry of A or G is not finite
-        double d[KIN_N];
-        if (F32) {
-            float Af[KIN_N][KIN_N], bf[KIN_N];
-#pragma unroll
-            for (int i = 0; i < KIN_N; ++i) {
-                double m = 0.0;
-#pragma unroll
-                for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(A[i][j]));
-                const double s = 1.0 / m;
-#pragma unroll
-                for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(A[i][j] * s);
-                bf[i] = (float)(b[i] * s);
-            }
-            if (!kin_lu_solve<float>(Af, bf)) return false;
-#pragma unroll
-            for (int i = 0; i < KIN_N; ++i) d[i] = (double)bf[i];
-        } else {
-            if (!kin_lu_solve<double>(A, b)) return false;
-#pragma unroll
-            for (int i = 0; i < KIN_N; ++i) d[i] = b[i];
-        }
-        bool conv = true;
-        double chk2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < KIN_N; ++i) {
-            xk[i] += d[i];
-            chk2 += xk[i] - xk[i];
-            const double atol = (i < KIN_NS) ? a.atol_Y : a.atol_T;
-            conv = conv && (fabs(d[i]) <= atol + a.rtol * fabs(xk[i]));
-        }
-        if (!(chk2 == 0.0)) return false;
-        if (xk[KIN_NS] < KIN_T_MIN || xk[KIN_NS] > KIN_T_MAX) return false;
-        if (conv) {
-            bool neg = false;
-#pragma unroll
-            for (int s = 0; s < KIN_NS; ++s) neg = neg || (xk[s] < -a.y_neg);
-            if (neg) return false;
-            double T;
-            if (!kin_invert_T(a.K, xk, e0, xk[KIN_NS], T)) return false;
-            xk[KIN_NS] = T;
-#pragma unroll
-            for (int i = 0; i < KIN_N; ++i) x[i] = xk[i];
-            return true;
+        for (int j = 0; j < KIN_N; ++j) {
+            A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
+            chk += A[i][j] - A[i][j];
         }
     }
-    return false;
+    if (!(chk == 0.0)) return KIN_ATTEMPT_FAILED;  // some entry of A or G is not finite
+    double d[KIN_N];
+    if (F32) {
+        float Af[KIN_N][KIN_N], bf[KIN_N];
+#pragma unroll
+        for (int i = 0; i < KIN_N; ++i) {
+            double m = 0.0;
+#pragma unroll
+            for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(A[i][j]));
+            const double s = 1.0 / m;
+#pragma unroll
+            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(A[i][j] * s);
+            bf[i] = (float)(b[i] * s);
+        }
+        if (!kin_lu_solve<float>(Af, bf)) return KIN_ATTEMPT_FAILED;
+#pragma unroll
+        for (int i = 0; i < KIN_N; ++i) d[i] = (double)bf[i];
+    } else {
+        if (!kin_lu_solve<double>(A, b)) return KIN_ATTEMPT_FAILED;
+#pragma unroll
+        for (int i = 0; i < KIN_N; ++i) d[i] = b[i];
+    }
+    bool conv = true;
+    double chk2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < KIN_N; ++i) {
+        xk[i] += d[i];
+        chk2 += xk[i] - xk[i];
+        const double atol = (i < KIN_NS) ? a.atol_Y : a.atol_T;
+        conv = conv && (fabs(d[i]) <= atol + a.rtol * fabs(xk[i]));
+    }
+    if (!(chk2 == 0.0)) return KIN_ATTEMPT_FAILED;
+    if (xk[KIN_NS] < KIN_T_MIN || xk[KIN_NS] > KIN_T_MAX) return KIN_ATTEMPT_FAILED;
+    if (!conv) return KIN_CONTINUE;
+    bool neg = false;
+#pragma unroll
+    for (int s = 0; s < KIN_NS; ++s) neg = neg || (xk[s] < -a.y_neg);
+    if (neg) return KIN_ATTEMPT_FAILED;
+    double T;
+    if (!kin_invert_T(a.K, xk, e0, xk[KIN_NS], T)) return KIN_ATTEMPT_FAILED;
+    xk[KIN_NS] = T;
+    return KIN_ACCEPTED;
 }
 
+// Persistent lanes.  Every loop trip performs one Newton iteration for the cell each lane
+// holds, so lanes whose cells need many iterations (sub-step halving) do not hold back the
+// rest of their wavefront: a lane that finishes its cell stores it and takes the next cell
+// index from a global counter (one atomic per wavefront per refill).
+//
+// Sub-stepping is dyadic, time counted in ticks of dt 2^-Lc so that every sub-step boundary
+// is exact.  Adaptive (L_forced < 0): start at h = dt, halve on a failed attempt and retry
+// from the last accepted state, double after an accepted sub-step that ends on a boundary of
+// the doubled step; a level beyond L_max or more than max_iters Newton iterations fail the
+// cell, which keeps its input state.  Replay (L_forced >= 0): 2^L_forced equal sub-steps.
 template <bool F32>
-__device__ __forceinline__ void kin_cell(const KinLaneArgs &a, const long long i)
+__device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
 {
-    const double rho = a.rho[i];
-    const double e0 = a.e0[i];
-    double x[KIN_N];
-#pragma unroll
-    for (int s = 0; s < KIN_NS; ++s) x[s] = a.Y[s * a.ld + i];
-    x[KIN_NS] = a.T[i];
-    double chk = rho - rho + e0 - e0 + a.dt - a.dt;
-#pragma unroll
-    for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
-    if (!(chk == 0.0) || !(rho > 0.0) || !(a.dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
-        x[KIN_NS] > KIN_T_MAX) {
-        a.status[i] = 3;
-        a.level[i] = 0;
-        a.iters[i] = 0;
-        return;
-    }
-    // Dyadic sub-stepping, time counted in ticks of dt 2^-Lc so that every sub-step boundary
-    // is exact.  Adaptive (L_forced < 0): start at h = dt, halve on failure and retry from
-    // the last accepted state, double after an accepted sub-step that ends on a boundary of
-    // the doubled step.  Replay (L_forced >= 0): 2^L_forced equal sub-steps, no adaptation.
+    const int lane = (int)(threadIdx.x & 63u);
     const bool adapt = a.L_forced < 0;
     const int Lc = adapt ? a.L_max : a.L_forced;
     const unsigned long long end = 1ull << Lc;
+
+    long long i = -1;
+    bool need = true;    // the lane has no cell in progress
+    bool done = false;   // the counter ran past the last cell
+    double rho = 0.0, e0 = 0.0;
+    double x[KIN_N], xk[KIN_N];
+#pragma unroll
+    for (int s = 0; s < KIN_N; ++s) { x[s] = 0.0; xk[s] = 0.0; }
     unsigned long long t = 0;
-    int l = adapt ? 0 : a.L_forced;
-    int iters = 0, level = l, st = 0;
+    int l = 0, k = 0, iters = 0, level = 0;
     bool failed = false;
-    while (t < end) {
-        if (iters >= a.max_iters) { st = 2; break; }
-        const double h = ldexp(a.dt, -l);
-        if (kin_substep<F32>(rho, e0, x, h, a, iters)) {
-            t += 1ull << (Lc - l);
-            if (adapt && l > 0 && (t & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
-        } else {
-            if (!adapt) { st = 2; break; }
-            failed = true;
-            ++l;
-            if (l > level) level = l;
-            if (l > a.L_max) { level = a.L_max; st = 2; break; }
+
+    for (;;) {
+        // ---- hand new cells to lanes that need one ----------------------------------------
+        const unsigned long long want = __ballot(need && !done);
+        if (want) {
+            const int leader = __ffsll((long long)want) - 1;
+            const int cnt = __popcll(want);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)cnt);
+            base = __shfl(base, leader);
+            if (need && !done) {
+                const unsigned int lo = (unsigned int)want, hi = (unsigned int)(want >> 32);
+                const int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+                const unsigned long long ci = base + (unsigned long long)rank;
+                if (ci >= (unsigned long long)a.n) {
+                    done = true;
+                    i = -1;
+                } else {
+                    i = (long long)ci;
+                    need = false;
+                    rho = a.rho[i];
+                    e0 = a.e0[i];
+#pragma unroll
+                    for (int s = 0; s < KIN_NS; ++s) x[s] = a.Y[s * a.ld + i];
+                    x[KIN_NS] = a.T[i];
+                    double chk = rho - rho + e0 - e0 + a.dt - a.dt;
+#pragma unroll
+                    for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
+                    if (!(chk == 0.0) || !(rho > 0.0) || !(a.dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
+                        x[KIN_NS] > KIN_T_MAX) {
+                        a.status[i] = 3;
+                        a.level[i] = 0;
+                        a.iters[i] = 0;
+                        need = true;
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
+                        t = 0;
+                        l = adapt ? 0 : a.L_forced;
+                        level = l;
+                        k = 0;
+                        iters = 0;
+                        failed = false;
+                    }
+                }
+            }
+        }
+        if (!__any(!need)) {
+            if (!__any(!done)) break;   // every lane has run out of cells
+            continue;                   // only refills (bad inputs) this trip
+        }
+        if (!need) {
+            int outcome;
+            int st = -1;  // >= 0: the cell is finished with this status
+            if (k == 0 && iters >= a.max_iters) {
+                st = 2;
+                outcome = KIN_CONTINUE;
+            } else {
+                ++iters;
+                outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(a.dt, -l));
+                if (outcome == KIN_CONTINUE && ++k >= a.k_max) outcome = KIN_ATTEMPT_FAILED;
+            }
+            if (outcome == KIN_ACCEPTED) {
+#pragma unroll
+                for (int s = 0; s < KIN_N; ++s) x[s] = xk[s];
+                t += 1ull << (Lc - l);
+                if (adapt && l > 0 && (t & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
+                k = 0;
+                if (t >= end) st = failed ? 1 : 0;
+            } else if (outcome == KIN_ATTEMPT_FAILED) {
+#pragma unroll
+                for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
+                k = 0;
+                if (!adapt) {
+                    st = 2;
+                } else {
+                    failed = true;
+                    ++l;
+                    if (l > level) level = l;
+                    if (l > a.L_max) { level = a.L_max; st = 2; }
+                }
+            }
+            if (st >= 0) {
+                if (st != 2) {
+#pragma unroll
+                    for (int s = 0; s < KIN_NS; ++s) a.Y[s * a.ld + i] = x[s];
+                    a.T[i] = x[KIN_NS];
+                }
+                a.status[i] = st;
+                a.level[i] = level;
+                a.iters[i] = iters;
+                need = true;
+            }
         }
     }
-    if (st == 0 && failed) st = 1;
-    if (st != 2) {
-#pragma unroll
-        for (int s = 0; s < KIN_NS; ++s) a.Y[s * a.ld + i] = x[s];
-        a.T[i] = x[KIN_NS];
-    }
-    a.status[i] = st;
-    a.level[i] = level;
-    a.iters[i] = iters;
 }
 
 extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f64(KinLaneArgs a)
 {
-    const long long i = (long long)blockIdx.x * KIN_BLOCK + threadIdx.x;
-    if (i < a.n) kin_cell<false>(a, i);
+    kin_lane_run<false>(a);
 }
 
 extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f32lu(KinLaneArgs a)
 {
-    const long long i = (long long)blockIdx.x * KIN_BLOCK + threadIdx.x;
-    if (i < a.n) kin_cell<true>(a, i);
+    kin_lane_run<true>(a);
 }

@@ -42,6 +42,7 @@ struct Inst {
     size_t bytes = 0;
     double *rho = nullptr, *e0 = nullptr, *T = nullptr, *Y = nullptr;
     int *status = nullptr, *level = nullptr, *iters = nullptr;
+    unsigned long long *counter = nullptr;  // work counter of the advance kernels
 };
 
 // Code objects already compiled in this process, keyed by their source.
@@ -54,7 +55,7 @@ static uint64_t inst_bytes(int ns, long long n)
 {
     const size_t d = align256(sizeof(double) * (size_t)n);
     const size_t i = align256(sizeof(int) * (size_t)n);
-    return (uint64_t)(d * (3 + (size_t)ns) + 3 * i);
+    return (uint64_t)(d * (3 + (size_t)ns) + 3 * i + 256);
 }
 
 }  // namespace kin
@@ -400,6 +401,7 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     in->status = reinterpret_cast<int *>(ib);
     in->level = reinterpret_cast<int *>(ib + i);
     in->iters = reinterpret_cast<int *>(ib + 2 * i);
+    in->counter = reinterpret_cast<unsigned long long *>(ib + 3 * i);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((s = fill_state(ctx, *in, m, rho, T, Y, e0, where, st)) != KIN_OK) {
         hipFree(in->buf);
@@ -437,6 +439,7 @@ static AdvanceArgs make_args(const Inst &in, double dt, const kin_solver_opts &o
     a.status = in.status; a.level = in.level; a.iters = in.iters;
     a.rtol = o.rtol; a.atol_Y = o.atol_Y; a.atol_T = o.atol_T; a.y_neg = o.y_neg;
     a.k_max = o.k_max; a.L_max = o.L_max; a.L_forced = o.L_forced; a.max_iters = o.max_iters;
+    a.counter = in.counter;
     return a;
 }
 
@@ -446,20 +449,26 @@ static kin_status launch_one(kin_ctx *ctx, Mech &m, const Inst &in, double dt, k
     int layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
     AdvanceArgs a = make_args(in, dt, o);
     const bool f32 = prec == KIN_FP32_LU;
+    KIN_HIP(ctx, hipMemsetAsync(in.counter, 0, sizeof(unsigned long long), st));
     if (layout == KIN_LAYOUT_LANE) {
         if (m.h.ns > kLaneNsMax) return err(KIN_EINVAL, "lane layout needs ns <= 15");
         const int block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
         kin_status s = build_lane(ctx, m, block);
         if (s != KIN_OK) return s;
-        const long long grid = (in.n + block - 1) / block;
+        hipFunction_t fn = f32 ? m.lane_f32 : m.lane_f64;
+        int per_cu = 0;
+        KIN_HIP(ctx, hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0));
+        if (per_cu < 1) per_cu = 1;
+        // persistent lanes: one resident wave set; more blocks than fit would only wait
+        const long long grid = std::min<long long>((in.n + block - 1) / block, (long long)per_cu * ctx->num_cu);
         a.K = m.kconst;
         void *params[] = {&a};
-        KIN_HIP(ctx, hipModuleLaunchKernel(f32 ? m.lane_f32 : m.lane_f64, (unsigned)grid, 1, 1, block, 1, 1,
-                                           0, st, params, nullptr));
+        KIN_HIP(ctx, hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
     } else {
         const int wpb = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 2;
         const long long blocks = (in.n + wpb - 1) / wpb;
-        const int grid = (int)std::min<long long>(blocks, (long long)ctx->num_cu * 64);
+        if (blocks > 0x7fffffffLL) return err(KIN_EINVAL, "too many cells for one wave-layout launch");
+        const int grid = (int)blocks;
         KIN_HIP(ctx, launch_wave(m.tab, a, f32, wpb, grid, st));
     }
     return KIN_OK;

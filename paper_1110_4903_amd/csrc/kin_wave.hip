@@ -426,8 +426,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
     const int ns = t.ns, N = ns + 1;
     const Lds L = lds_map<NPAD>(smem + (size_t)wid * lds_doubles<NPAD>(N), N);
     const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max};
-    for (long long cell = (long long)blockIdx.x * wpb + wid; cell < a.n;
-         cell += (long long)gridDim.x * wpb) {
+    // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones
+    // retire, which balances cells that need very different numbers of Newton iterations
+    {
+        const long long cell = (long long)blockIdx.x * wpb + wid;
+        if (cell >= a.n) return;
         const double rho = a.rho[cell];
         const double e0 = a.e0[cell];
         double xs = 0.0;
@@ -437,17 +440,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
         const bool bad_in = __any(lane < N && !__builtin_isfinite(xs)) || !__builtin_isfinite(rho) ||
                             !(rho > 0.0) || !__builtin_isfinite(e0) || !__builtin_isfinite(a.dt) ||
                             !(a.dt >= 0.0) || T0 < kTmin || T0 > kTmax;
-        if (bad_in) {
-            if (lane == 0) { a.status[cell] = 3; a.level[cell] = 0; a.iters[cell] = 0; }
-            continue;
-        }
         // dyadic sub-stepping in ticks of dt 2^-Lc (see the lane layout for the rule)
         const bool adapt = a.L_forced < 0;
         const int Lc = adapt ? a.L_max : a.L_forced;
         const unsigned long long end = 1ull << Lc;
-        unsigned long long tt = 0;
+        unsigned long long tt = bad_in ? end : 0ull;
         int l = adapt ? 0 : a.L_forced;
-        int iters = 0, level = l, st = 0;
+        int iters = 0, level = bad_in ? 0 : l, st = bad_in ? 3 : 0;
         bool failed = false;
         while (tt < end) {
             if (iters >= a.max_iters) { st = 2; break; }
@@ -464,7 +463,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
             }
         }
         if (st == 0 && failed) st = 1;
-        if (st != 2) {
+        if (st < 2) {
             if (lane < ns) a.Y[(size_t)lane * a.ld + cell] = xs;
             else if (lane == ns) a.T[cell] = xs;
         }
