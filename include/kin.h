@@ -148,10 +148,20 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
 kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
                        kin_precision prec, const kin_solver_opts *s, void *stream);
 
-/* Copy an instance's state and diagnostics into caller buffers (any pointer may be NULL).
+/* Copy an instance's state (T[n], Y[Ns][n]), the conserved internal energy e0[n] and the
+ * per-cell diagnostics of the last advance into caller buffers; any pointer may be NULL.
+ * Re-uploading T, Y with this e0 resumes the run bitwise (checkpoint / restart).
  * Host destinations: synchronous.  Device destinations: enqueued on `stream`. */
-kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, int32_t *status,
-                        int32_t *level, int32_t *iters, kin_mem where, void *stream);
+kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,
+                        int32_t *status, int32_t *level, int32_t *iters, kin_mem where,
+                        void *stream);
+
+/* Per-cell sub-step schedule of the last advance: a 64-bit FNV-1a hash of the sequence of
+ * sub-step attempts, starting from 0xcbf29ce484222325 and folding in, per attempt at level l,
+ * h = (h ^ (2 l + accepted)) * 0x100000001b3.  Two runs whose hashes agree took the same
+ * sub-steps, so their results differ only by arithmetic, not by the step sizes taken. */
+kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched, kin_mem where,
+                                 void *stream);
 
 /* Wait for `stream` (NULL = the null stream). */
 kin_status kin_sync(kin_ctx *ctx, void *stream);

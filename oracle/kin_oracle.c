@@ -373,13 +373,20 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
     return rc;
 }
 
+static unsigned long long sched_step(unsigned long long h, int l, int accepted)
+{
+    return (h ^ (unsigned long long)(2 * l + accepted)) * ORC_SCHED_PRIME;
+}
+
 int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double *Y, long stride,
-                     double dt, const orc_opts *o, int L_forced, int *level, int *iters)
+                     double dt, const orc_opts *o, int L_forced, int *level, int *iters,
+                     unsigned long long *sched)
 {
     int ns = m->ns, N = ns + 1;
     double xn[ORC_NS_MAX + 1], x[ORC_NS_MAX + 1];
     *level = 0;
     *iters = 0;
+    *sched = ORC_SCHED_SEED;
     for (int s = 0; s < ns; ++s) xn[s] = Y[s * stride];
     xn[ns] = *T;
     if (!all_finite(xn, N) || !isfinite(rho) || !(rho > 0) || !isfinite(e0) || !isfinite(dt) ||
@@ -394,7 +401,9 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         *level = L_forced;
         for (long j = 0; j < nsub; ++j) {
             if (*iters >= o->max_iters) return ORC_FAILED;
-            if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) != 0) return ORC_FAILED;
+            int ok = orc_be_substep(m, rho, e0, x, h, o, iters, 0) == 0;
+            *sched = sched_step(*sched, L_forced, ok);
+            if (!ok) return ORC_FAILED;
         }
     } else {
         /* Time is counted in ticks of dt 2^-L_max, so every sub-step boundary is exact. */
@@ -404,7 +413,9 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         while (t < end) {
             if (*iters >= o->max_iters) return ORC_FAILED;
             double h = ldexp(dt, -l);
-            if (orc_be_substep(m, rho, e0, x, h, o, iters, 0) == 0) {
+            int ok = orc_be_substep(m, rho, e0, x, h, o, iters, 0) == 0;
+            *sched = sched_step(*sched, l, ok);
+            if (ok) {
                 t += 1LL << (o->L_max - l);
                 if (l > 0 && (t & ((1LL << (o->L_max - l + 1)) - 1)) == 0) --l;
             } else {
@@ -422,7 +433,7 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
 
 void orc_advance(const orc_mech *m, long n, const double *rho, const double *e0, double *T,
                  double *Y, double dt, const orc_opts *o, int L_forced, int *status, int *level,
-                 int *iters, int nthreads)
+                 int *iters, unsigned long long *sched, int nthreads)
 {
     if (nthreads <= 0) nthreads = orc_num_threads();
     long i;
@@ -435,10 +446,12 @@ void orc_advance(const orc_mech *m, long n, const double *rho, const double *e0,
             e = orc_mix_energy(m, y, T[i]);
         }
         int lv, it;
-        int st = orc_advance_cell(m, rho[i], e, &T[i], &Y[i], n, dt, o, L_forced, &lv, &it);
+        unsigned long long sh;
+        int st = orc_advance_cell(m, rho[i], e, &T[i], &Y[i], n, dt, o, L_forced, &lv, &it, &sh);
         if (status) status[i] = st;
         if (level) level[i] = lv;
         if (iters) iters[i] = it;
+        if (sched) sched[i] = sh;
     }
 }
 

@@ -100,16 +100,22 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
 
 /* One cell over dt.  L_forced < 0: adaptive dyadic sub-stepping (halve on failure, double
  * after a success when aligned); L_forced >= 0: exactly 2^L_forced equal sub-steps.
- * *level = deepest halving level used, *iters = Newton iterations including failed tries. */
+ * *level = deepest halving level used, *iters = Newton iterations including failed tries,
+ * *sched = 64-bit FNV-1a hash of the sequence of (level, accepted) sub-step attempts. */
 int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double *Y,
                      long stride, double dt, const orc_opts *o, int L_forced,
-                     int *level, int *iters);
+                     int *level, int *iters, unsigned long long *sched);
 
 /* Batch over cells (OpenMP over cells, nthreads <= 0 = runtime default).
  * T[n] and Y[ns][n] are updated in place; status/level/iters may be NULL. */
 void orc_advance(const orc_mech *m, long n, const double *rho, const double *e0,
                  double *T, double *Y, double dt, const orc_opts *o, int L_forced,
-                 int *status, int *level, int *iters, int nthreads);
+                 int *status, int *level, int *iters, unsigned long long *sched, int nthreads);
+
+/* Schedule hash: h0 = ORC_SCHED_SEED, then h = (h ^ (2 l + accepted)) * ORC_SCHED_PRIME per
+ * sub-step attempt at level l (FNV-1a over the attempt codes). */
+#define ORC_SCHED_SEED 0xcbf29ce484222325ULL
+#define ORC_SCHED_PRIME 0x100000001b3ULL
 
 /* e0[n] = e(Y, T) per cell. */
 void orc_energy_batch(const orc_mech *m, long n, const double *T, const double *Y, double *e0);

@@ -68,7 +68,7 @@ def lib():
         L.orc_lu_solve.argtypes = [i, vp, vp, vp]
         L.orc_invert_T.argtypes = [vp, vp, d, d, vp]; L.orc_invert_T.restype = i
         L.orc_be_substep.argtypes = [vp, d, d, vp, d, vp, vp, vp]; L.orc_be_substep.restype = i
-        L.orc_advance.argtypes = [vp, l, vp, vp, vp, vp, d, vp, i, vp, vp, vp, i]
+        L.orc_advance.argtypes = [vp, l, vp, vp, vp, vp, d, vp, i, vp, vp, vp, vp, i]
         L.orc_energy_batch.argtypes = [vp, l, vp, vp, vp]
         L.orc_residual_ld.argtypes = [vp, d, vp, vp, d, vp, vp]; L.orc_residual_ld.restype = d
         L.orc_term_scale.argtypes = [vp, d, vp, vp, d, vp]
@@ -186,17 +186,20 @@ class OracleMech:
         return e0
 
     def advance(self, rho, T, Y, dt: float, e0=None, opts: Optional[Opts] = None, L_forced: int = -1,
-                nthreads: int = 0):
-        """Advance cells one dt; returns (T, Y, status, level, iters) as new arrays."""
+                nthreads: int = 0, with_sched: bool = False):
+        """Advance cells one dt; returns (T, Y, status, level, iters[, sched]) as new arrays."""
         rho = np.ascontiguousarray(rho, np.float64)
         n = rho.shape[0]
         T = np.array(T, dtype=np.float64)
         Y = np.array(Y, dtype=np.float64).reshape(self.ns, n)
         e0p = None if e0 is None else np.ascontiguousarray(e0, np.float64)
         st, lv, it = (np.zeros(n, np.int32) for _ in range(3))
+        sh = np.zeros(n, np.uint64)
         lib().orc_advance(self.ref, n, _p(rho), None if e0p is None else _p(e0p), _p(T), _p(Y),
                           float(dt), C.byref(opts or default_opts()), int(L_forced),
-                          _p(st), _p(lv), _p(it), int(nthreads))
+                          _p(st), _p(lv), _p(it), _p(sh), int(nthreads))
+        if with_sched:
+            return T, Y, st, lv, it, sh
         return T, Y, st, lv, it
 
 

@@ -67,20 +67,35 @@ namespace kin {
 
 // Mechanism tables in device memory, read by the table-driven kernels (wave layout and the
 // initial-energy kernel).  All pointers point into one allocation.
-constexpr int kRxi = 32;     // ints per reaction in rxi
 constexpr int kChunk = 64;   // reactions evaluated per wavefront pass
+
+// Compact reaction record (32 bytes): counts, third-body row, merged reactant and product
+// lists and the participant list with net coefficients, all as small integers.
+struct RxnRec {
+    int8_t rev, nreac, nprod, npart;
+    int16_t tb;
+    int8_t reac_sp[3], reac_nu[3], prod_sp[3], prod_nu[3];
+    int8_t part_sp[6], part_nu[6];
+    int8_t pad2[2];
+};
+static_assert(sizeof(RxnRec) == 32, "reaction record must stay 32 bytes");
+
 struct WaveTables {
     int ns, nr, ntb, nchunk;
-    double lnPaR;         // ln(P_atm / R) in CGS units
-    const double *nasa;   // [ns][14]
-    const double *Tmid;   // [ns]
-    const double *M;      // [ns] g/mol
-    const double *rxd;    // [nr][4]: ln A, b, Ta, sum nu
-    const int *rxi;       // [nr][kRxi]: rev, tb, nreac, nprod, reac sp[3], reac nu[3],
-                          //   prod sp[3], prod nu[3], npart, part sp[6], part net nu[6]
-    const double *eff;    // [ntb][ns]
-    const int *sp_ptr;    // [ns][nchunk + 1] start of each chunk's entries of species s
-    const int *sp_list;   // entries r * 16 + (nu + 8) of reactions with nonzero net nu
+    double lnPaR;           // ln(P_atm / R) in CGS units
+    const double *nasa;     // [ns][14]
+    const double *Tmid;     // [ns]
+    const double *M;        // [ns] g/mol
+    const double *rxd;      // [nr][4]: ln A, b, Ta, sum nu
+    const RxnRec *rxc;      // [nr]
+    const double *effT;     // [ns][ntb] third-body efficiencies, transposed
+    const double *effM;     // [ntb][ns] efficiency / molar mass (eff_rk / M_k)
+    const int *tb_ptr;      // [nchunk + 1] third-body reactions of each chunk ...
+    const int *tb_list;     //   ... as reaction indices
+    const int *sp_ptr;      // [ns][nchunk + 1] per species and chunk: reactions with a nonzero
+    const int *sp_list;     //   net coefficient, rl * 16 + (nu + 8), rl local to the chunk
+    const int *ent_ptr;     // [ns][nchunk + 1] per species row and chunk: sparse Jacobian
+    const int *ent_list;    //   entries rl | slot << 6 | k << 9 | (nu + 8) << 15
 };
 
 // Arguments of one advance launch (both layouts); mirrors the device-side argument struct.
@@ -99,6 +114,7 @@ struct AdvanceArgs {
     int k_max, L_max, L_forced, max_iters;
     const double *K;   // lane layout: the mechanism's constant table
     unsigned long long *counter;  // next unclaimed cell (zero at launch)
+    unsigned long long *sched;    // per-cell sub-step schedule hash
 };
 
 // Host launchers of the precompiled kernels (kin_wave.hip).

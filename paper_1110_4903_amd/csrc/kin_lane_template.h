@@ -26,7 +26,11 @@ struct KinLaneArgs {
     int k_max, L_max, L_forced, max_iters;
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
     unsigned long long *counter;  // next unclaimed cell; zero at launch
+    unsigned long long *sched;    // per-cell sub-step schedule hash (FNV-1a of attempts)
 };
+
+#define KIN_SCHED_SEED 0xcbf29ce484222325ull
+#define KIN_SCHED_PRIME 0x100000001b3ull
 
 // The constant table is read through a pointer the compiler cannot see through, once per
 // use site: the scalar loads of K[] then stay next to their uses instead of being hoisted
@@ -226,7 +230,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     double x[KIN_N], xk[KIN_N];
 #pragma unroll
     for (int s = 0; s < KIN_N; ++s) { x[s] = 0.0; xk[s] = 0.0; }
-    unsigned long long t = 0;
+    unsigned long long t = 0, hsh = KIN_SCHED_SEED;
     int l = 0, k = 0, iters = 0, level = 0;
     bool failed = false;
 
@@ -262,6 +266,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                         a.status[i] = 3;
                         a.level[i] = 0;
                         a.iters[i] = 0;
+                        a.sched[i] = KIN_SCHED_SEED;
                         need = true;
                     } else {
 #pragma unroll
@@ -272,6 +277,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                         k = 0;
                         iters = 0;
                         failed = false;
+                        hsh = KIN_SCHED_SEED;
                     }
                 }
             }
@@ -291,6 +297,8 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(a.dt, -l));
                 if (outcome == KIN_CONTINUE && ++k >= a.k_max) outcome = KIN_ATTEMPT_FAILED;
             }
+            if (outcome != KIN_CONTINUE)
+                hsh = (hsh ^ (unsigned long long)(2 * l + (outcome == KIN_ACCEPTED))) * KIN_SCHED_PRIME;
             if (outcome == KIN_ACCEPTED) {
 #pragma unroll
                 for (int s = 0; s < KIN_N; ++s) x[s] = xk[s];
@@ -320,6 +328,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 a.status[i] = st;
                 a.level[i] = level;
                 a.iters[i] = iters;
+                a.sched[i] = hsh;
                 need = true;
             }
         }

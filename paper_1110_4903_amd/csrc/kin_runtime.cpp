@@ -43,6 +43,7 @@ struct Inst {
     double *rho = nullptr, *e0 = nullptr, *T = nullptr, *Y = nullptr;
     int *status = nullptr, *level = nullptr, *iters = nullptr;
     unsigned long long *counter = nullptr;  // work counter of the advance kernels
+    unsigned long long *sched = nullptr;    // per-cell sub-step schedule hash
 };
 
 // Code objects already compiled in this process, keyed by their source.
@@ -55,7 +56,7 @@ static uint64_t inst_bytes(int ns, long long n)
 {
     const size_t d = align256(sizeof(double) * (size_t)n);
     const size_t i = align256(sizeof(int) * (size_t)n);
-    return (uint64_t)(d * (3 + (size_t)ns) + 3 * i + 256);
+    return (uint64_t)(d * (4 + (size_t)ns) + 3 * i + 256);
 }
 
 }  // namespace kin
@@ -200,63 +201,78 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     const int ns = h.ns, nr = h.nr, ntb = h.ntb;
     const int nchunk = (nr + kChunk - 1) / kChunk;
     std::vector<double> rxd((size_t)nr * 4);
-    std::vector<int> rxi((size_t)nr * kRxi, 0);
+    std::vector<RxnRec> rxc(nr);
     for (int r = 0; r < nr; ++r) {
         const Rxn &x = h.rx[r];
         rxd[4 * r + 0] = x.lnA;
         rxd[4 * r + 1] = x.b;
         rxd[4 * r + 2] = x.Ta;
         rxd[4 * r + 3] = (double)x.dnu;
-        int *p = &rxi[(size_t)r * kRxi];
-        p[0] = x.rev; p[1] = x.tb; p[2] = x.nreac; p[3] = x.nprod;
+        RxnRec &p = rxc[r];
+        std::memset(&p, 0, sizeof p);
+        p.rev = (int8_t)x.rev; p.nreac = (int8_t)x.nreac; p.nprod = (int8_t)x.nprod;
+        p.npart = (int8_t)x.npart; p.tb = (int16_t)x.tb;
         for (int j = 0; j < 3; ++j) {
-            p[4 + j] = j < x.nreac ? x.reac_sp[j] : 0;
-            p[7 + j] = j < x.nreac ? x.reac_nu[j] : 0;
-            p[10 + j] = j < x.nprod ? x.prod_sp[j] : 0;
-            p[13 + j] = j < x.nprod ? x.prod_nu[j] : 0;
+            p.reac_sp[j] = (int8_t)(j < x.nreac ? x.reac_sp[j] : 0);
+            p.reac_nu[j] = (int8_t)(j < x.nreac ? x.reac_nu[j] : 0);
+            p.prod_sp[j] = (int8_t)(j < x.nprod ? x.prod_sp[j] : 0);
+            p.prod_nu[j] = (int8_t)(j < x.nprod ? x.prod_nu[j] : 0);
         }
-        p[16] = x.npart;
         for (int j = 0; j < 6; ++j) {
-            p[17 + j] = j < x.npart ? x.part[j].sp : 0;
-            p[23 + j] = j < x.npart ? x.part[j].nu : 0;
+            p.part_sp[j] = (int8_t)(j < x.npart ? x.part[j].sp : 0);
+            p.part_nu[j] = (int8_t)(j < x.npart ? x.part[j].nu : 0);
         }
     }
-    // species -> reactions with nonzero net coefficient, split by chunk
-    std::vector<int> sp_ptr((size_t)ns * (nchunk + 1));
-    std::vector<int> sp_list;
+    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effM((size_t)std::max(1, ntb * ns), 0.0);
+    for (int r = 0; r < ntb; ++r)
+        for (int k = 0; k < ns; ++k) {
+            effT[(size_t)k * ntb + r] = h.eff[(size_t)r * ns + k];
+            effM[(size_t)r * ns + k] = h.eff[(size_t)r * ns + k] / h.M[k];
+        }
+    std::vector<int> tb_ptr(nchunk + 1), tb_list;
+    for (int cb = 0; cb < nchunk; ++cb) {
+        tb_ptr[cb] = (int)tb_list.size();
+        for (int r = cb * kChunk; r < std::min(nr, (cb + 1) * kChunk); ++r)
+            if (h.rx[r].tb >= 0) tb_list.push_back(r);
+    }
+    tb_ptr[nchunk] = (int)tb_list.size();
+    // per species row and chunk: reactions with nonzero net coefficient, and sparse entries
+    std::vector<int> sp_ptr((size_t)ns * (nchunk + 1)), sp_list, ent_ptr((size_t)ns * (nchunk + 1)), ent_list;
     for (int s = 0; s < ns; ++s) {
         for (int cb = 0; cb < nchunk; ++cb) {
             sp_ptr[(size_t)s * (nchunk + 1) + cb] = (int)sp_list.size();
+            ent_ptr[(size_t)s * (nchunk + 1) + cb] = (int)ent_list.size();
             for (int r = cb * kChunk; r < std::min(nr, (cb + 1) * kChunk); ++r) {
                 const Rxn &x = h.rx[r];
+                const int rl = r - cb * kChunk;
+                int nu = 0;
+                for (int j = 0; j < x.npart; ++j) if (x.part[j].sp == s) nu = x.part[j].nu;
+                if (!nu) continue;
+                sp_list.push_back(rl * 16 + (nu + 8));
                 for (int j = 0; j < x.npart; ++j)
-                    if (x.part[j].sp == s && x.part[j].nu != 0) sp_list.push_back(r * 16 + (x.part[j].nu + 8));
+                    ent_list.push_back(rl | (j << 6) | (x.part[j].sp << 9) | ((nu + 8) << 15));
             }
         }
         sp_ptr[(size_t)s * (nchunk + 1) + nchunk] = (int)sp_list.size();
+        ent_ptr[(size_t)s * (nchunk + 1) + nchunk] = (int)ent_list.size();
     }
     if (sp_list.empty()) sp_list.push_back(0);
-    std::vector<double> eff = h.eff;
-    if (eff.empty()) eff.push_back(0.0);
+    if (ent_list.empty()) ent_list.push_back(0);
+    if (tb_list.empty()) tb_list.push_back(0);
     // one allocation, 256-byte aligned pieces
-    const size_t o_nasa = 0;
-    const size_t o_tmid = align256(o_nasa + sizeof(double) * h.nasa.size());
-    const size_t o_M = align256(o_tmid + sizeof(double) * ns);
-    const size_t o_rxd = align256(o_M + sizeof(double) * ns);
-    const size_t o_rxi = align256(o_rxd + sizeof(double) * rxd.size());
-    const size_t o_eff = align256(o_rxi + sizeof(int) * rxi.size());
-    const size_t o_ptr = align256(o_eff + sizeof(double) * eff.size());
-    const size_t o_list = align256(o_ptr + sizeof(int) * sp_ptr.size());
-    const size_t total = align256(o_list + sizeof(int) * sp_list.size());
+    struct Piece { const void *src; size_t bytes; size_t off; };
+    std::vector<Piece> pc = {
+        {h.nasa.data(), sizeof(double) * h.nasa.size(), 0}, {h.Tmid.data(), sizeof(double) * ns, 0},
+        {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
+        {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {effT.data(), sizeof(double) * effT.size(), 0},
+        {effM.data(), sizeof(double) * effM.size(), 0}, {tb_ptr.data(), sizeof(int) * tb_ptr.size(), 0},
+        {tb_list.data(), sizeof(int) * tb_list.size(), 0}, {sp_ptr.data(), sizeof(int) * sp_ptr.size(), 0},
+        {sp_list.data(), sizeof(int) * sp_list.size(), 0}, {ent_ptr.data(), sizeof(int) * ent_ptr.size(), 0},
+        {ent_list.data(), sizeof(int) * ent_list.size(), 0}};
+    size_t total = 0;
+    for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
-    std::memcpy(&host[o_nasa], h.nasa.data(), sizeof(double) * h.nasa.size());
-    std::memcpy(&host[o_tmid], h.Tmid.data(), sizeof(double) * ns);
-    std::memcpy(&host[o_M], h.M.data(), sizeof(double) * ns);
-    std::memcpy(&host[o_rxd], rxd.data(), sizeof(double) * rxd.size());
-    std::memcpy(&host[o_rxi], rxi.data(), sizeof(int) * rxi.size());
-    std::memcpy(&host[o_eff], eff.data(), sizeof(double) * eff.size());
-    std::memcpy(&host[o_ptr], sp_ptr.data(), sizeof(int) * sp_ptr.size());
-    std::memcpy(&host[o_list], sp_list.data(), sizeof(int) * sp_list.size());
+    for (const Piece &p : pc) std::memcpy(&host[p.off], p.src, p.bytes);
     KIN_HIP(ctx, hipMalloc(&m.dbuf, total));
     m.dbytes = total;
     KIN_HIP(ctx, hipMemcpy(m.dbuf, host.data(), total, hipMemcpyHostToDevice));
@@ -264,14 +280,19 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     WaveTables &t = m.tab;
     t.ns = ns; t.nr = nr; t.ntb = ntb; t.nchunk = nchunk;
     t.lnPaR = std::log(kPatmCgs / kRuCgs);
-    t.nasa = reinterpret_cast<const double *>(b + o_nasa);
-    t.Tmid = reinterpret_cast<const double *>(b + o_tmid);
-    t.M = reinterpret_cast<const double *>(b + o_M);
-    t.rxd = reinterpret_cast<const double *>(b + o_rxd);
-    t.rxi = reinterpret_cast<const int *>(b + o_rxi);
-    t.eff = reinterpret_cast<const double *>(b + o_eff);
-    t.sp_ptr = reinterpret_cast<const int *>(b + o_ptr);
-    t.sp_list = reinterpret_cast<const int *>(b + o_list);
+    t.nasa = reinterpret_cast<const double *>(b + pc[0].off);
+    t.Tmid = reinterpret_cast<const double *>(b + pc[1].off);
+    t.M = reinterpret_cast<const double *>(b + pc[2].off);
+    t.rxd = reinterpret_cast<const double *>(b + pc[3].off);
+    t.rxc = reinterpret_cast<const RxnRec *>(b + pc[4].off);
+    t.effT = reinterpret_cast<const double *>(b + pc[5].off);
+    t.effM = reinterpret_cast<const double *>(b + pc[6].off);
+    t.tb_ptr = reinterpret_cast<const int *>(b + pc[7].off);
+    t.tb_list = reinterpret_cast<const int *>(b + pc[8].off);
+    t.sp_ptr = reinterpret_cast<const int *>(b + pc[9].off);
+    t.sp_list = reinterpret_cast<const int *>(b + pc[10].off);
+    t.ent_ptr = reinterpret_cast<const int *>(b + pc[11].off);
+    t.ent_list = reinterpret_cast<const int *>(b + pc[12].off);
     return KIN_OK;
 }
 
@@ -397,7 +418,8 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     in->e0 = reinterpret_cast<double *>(b + d);
     in->T = reinterpret_cast<double *>(b + 2 * d);
     in->Y = reinterpret_cast<double *>(b + 3 * d);
-    char *ib = b + (3 + (size_t)m.h.ns) * d;
+    in->sched = reinterpret_cast<unsigned long long *>(b + (3 + (size_t)m.h.ns) * d);
+    char *ib = b + (4 + (size_t)m.h.ns) * d;
     in->status = reinterpret_cast<int *>(ib);
     in->level = reinterpret_cast<int *>(ib + i);
     in->iters = reinterpret_cast<int *>(ib + 2 * i);
@@ -440,6 +462,7 @@ static AdvanceArgs make_args(const Inst &in, double dt, const kin_solver_opts &o
     a.rtol = o.rtol; a.atol_Y = o.atol_Y; a.atol_T = o.atol_T; a.y_neg = o.y_neg;
     a.k_max = o.k_max; a.L_max = o.L_max; a.L_forced = o.L_forced; a.max_iters = o.max_iters;
     a.counter = in.counter;
+    a.sched = in.sched;
     return a;
 }
 
@@ -502,8 +525,9 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     return KIN_OK;
 }
 
-kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, int32_t *status,
-                        int32_t *level, int32_t *iters, kin_mem where, void *stream)
+kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,
+                        int32_t *status, int32_t *level, int32_t *iters, kin_mem where,
+                        void *stream)
 {
     kin_status s = enter(ctx);
     if (s != KIN_OK) return s;
@@ -517,9 +541,27 @@ kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, int
     const size_t nd = sizeof(double) * (size_t)in.n, ni = sizeof(int) * (size_t)in.n;
     if (T) KIN_HIP(ctx, hipMemcpyAsync(T, in.T, nd, kind, st));
     if (Y) KIN_HIP(ctx, hipMemcpyAsync(Y, in.Y, nd * ns, kind, st));
+    if (e0) KIN_HIP(ctx, hipMemcpyAsync(e0, in.e0, nd, kind, st));
     if (status) KIN_HIP(ctx, hipMemcpyAsync(status, in.status, ni, kind, st));
     if (level) KIN_HIP(ctx, hipMemcpyAsync(level, in.level, ni, kind, st));
     if (iters) KIN_HIP(ctx, hipMemcpyAsync(iters, in.iters, ni, kind, st));
+    if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
+    return KIN_OK;
+}
+
+kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched, kin_mem where,
+                                 void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!sched) return err(KIN_EINVAL, "NULL destination");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->insts.find(inst_id);
+    if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
+    const Inst &in = *it->second;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KIN_HIP(ctx, hipMemcpyAsync(sched, in.sched, sizeof(uint64_t) * (size_t)in.n,
+                                where == KIN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
     if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
     return KIN_OK;
 }

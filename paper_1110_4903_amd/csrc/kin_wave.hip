@@ -69,17 +69,18 @@ struct Lds {
     double *sol;   // [NPAD] solution exchange
     double *invM;  // [NPAD]
     double *cq;    // [9][kChunk] chunk buffer: q, dqT, D, dq[6]
-    double *prow;  // [NPAD + 1] pivot row (FP64 or FP32 view)
+    double *Mc;    // [ntb] third-body concentrations
+    double *prow;  // [NPAD + 2] pivot row (FP64 or FP32 view)
 };
 
 template <int NPAD>
-__device__ __forceinline__ size_t lds_doubles(int N)
+__host__ __device__ __forceinline__ size_t lds_doubles(int N, int ntb)
 {
-    return (size_t)N * (NPAD + 1) + 8 * NPAD + 9 * kChunk + NPAD + 2;
+    return (size_t)N * (NPAD + 1) + 8 * NPAD + 9 * kChunk + (size_t)((ntb + 1) & ~1) + NPAD + 2;
 }
 
 template <int NPAD>
-__device__ __forceinline__ Lds lds_map(double *base, int N)
+__device__ __forceinline__ Lds lds_map(double *base, int N, int ntb)
 {
     Lds L;
     double *p = base;
@@ -93,6 +94,7 @@ __device__ __forceinline__ Lds lds_map(double *base, int N)
     L.sol = p; p += NPAD;
     L.invM = p; p += NPAD;
     L.cq = p; p += 9 * kChunk;
+    L.Mc = p; p += (ntb + 1) & ~1;
     L.prow = p;
     return L;
 }
@@ -140,8 +142,19 @@ __device__ __forceinline__ bool invert_T(const WaveTables &t, int lane, double x
     return true;
 }
 
+__device__ __forceinline__ double cpow_nu(double c, int nu)
+{
+    return (nu == 1) ? c : (nu == 2 ? c * c : c * c * c);
+}
+
 // f = dx/dt and J = df/dx of the cell at x (lane i holds x_i).  Leaves J in L.J (rows
-// 0..N-1) and f in L.f; returns f_i of this lane.
+// 0..N-1) and f in L.f.
+//
+// Per pass of 64 reactions (one per lane) the rates, net progress, its T-derivative and its
+// derivatives with respect to the participating concentrations go to the chunk buffer; then
+// lane s, owner of Jacobian row s, gathers the chunk's contributions to its row from a
+// precomputed list of (reaction, participant, column, coefficient) entries, and lane k adds
+// column k of the dense third-body terms nu_rs (M_s / M_k) eff_rk (q_f - q_b).
 template <int NPAD>
 __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane, double rho, double xs)
 {
@@ -167,73 +180,74 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         L.invM[lane] = invM;
     }
     wave_sync();
+    // third-body concentrations [M]_r = sum_s eff_rs c_s, one reaction per lane
+    for (int r = lane; r < t.ntb; r += kW) {
+        double acc = 0.0;
+        for (int s = 0; s < ns; ++s) acc = fma(t.effT[(size_t)s * t.ntb + r], L.c[s], acc);
+        L.Mc[r] = acc;
+    }
+    wave_sync();
     double w = 0.0, jt = 0.0;
     double *const Q = L.cq, *const QT = L.cq + kChunk, *const DD = L.cq + 2 * kChunk;
     double *const DQ = L.cq + 3 * kChunk;
+    const double Ms = (lane < ns) ? t.M[lane] : 0.0;
     for (int cb = 0; cb < t.nchunk; ++cb) {
         const int r = cb * kChunk + lane;
         if (r < t.nr) {
-            const int *ri = t.rxi + (size_t)r * kRxi;
+            const RxnRec x = t.rxc[r];
             const double *rd = t.rxd + (size_t)r * 4;
-            const int rev = ri[0], tb = ri[1], nreac = ri[2], nprod = ri[3], npart = ri[16];
             const double b = rd[1], Ta = rd[2], dnu = rd[3];
             const double lkf = fma(-Ta, iT, fma(b, lT, rd[0]));
             const double kf = exp(lkf);
             const double dlkf = fma(Ta, iT, b) * iT;
+            double cr[3], cpd[3];
             double pf = kf;
-            for (int j = 0; j < nreac; ++j) {
-                const double cj = L.c[ri[4 + j]];
-                const int nu = ri[7 + j];
-                pf *= (nu == 1) ? cj : (nu == 2 ? cj * cj : cj * cj * cj);
+            for (int j = 0; j < x.nreac; ++j) {
+                cr[j] = L.c[x.reac_sp[j]];
+                pf *= cpow_nu(cr[j], x.reac_nu[j]);
             }
             double kb = 0.0, pb = 0.0, dlKc = 0.0;
-            if (rev) {
+            if (x.rev) {
                 double sg = 0.0, sh = 0.0;
-                for (int j = 0; j < npart; ++j) {
-                    const double nu = (double)ri[23 + j];
-                    sg = fma(nu, L.g[ri[17 + j]], sg);
-                    sh = fma(nu, L.h[ri[17 + j]], sh);
+                for (int j = 0; j < x.npart; ++j) {
+                    const double nu = (double)x.part_nu[j];
+                    sg = fma(nu, L.g[x.part_sp[j]], sg);
+                    sh = fma(nu, L.h[x.part_sp[j]], sh);
                 }
                 const double lKc = dnu * lPaRT - sg;
                 kb = exp(lkf - lKc);
                 dlKc = (sh - dnu) * iT;
                 pb = kb;
-                for (int j = 0; j < nprod; ++j) {
-                    const double cj = L.c[ri[10 + j]];
-                    const int nu = ri[13 + j];
-                    pb *= (nu == 1) ? cj : (nu == 2 ? cj * cj : cj * cj * cj);
+                for (int j = 0; j < x.nprod; ++j) {
+                    cpd[j] = L.c[x.prod_sp[j]];
+                    pb *= cpow_nu(cpd[j], x.prod_nu[j]);
                 }
             }
-            double Mc = 1.0;
-            if (tb >= 0) {
-                const double *a = t.eff + (size_t)tb * ns;
-                Mc = 0.0;
-                for (int s = 0; s < ns; ++s) Mc = fma(a[s], L.c[s], Mc);
-            }
+            const double Mc = (x.tb >= 0) ? L.Mc[x.tb] : 1.0;
             const double D = pf - pb;
             Q[lane] = Mc * D;
             QT[lane] = Mc * (pf * dlkf - pb * (dlkf - dlKc));
             DD[lane] = D;
-            for (int j = 0; j < npart; ++j) {
-                const int sp = ri[17 + j];
-                // d/dc_sp of kf prod c^nu' and of kb prod c^nu''
+            for (int j = 0; j < x.npart; ++j) {
+                const int sp = x.part_sp[j];
+                // d/dc_sp of kf prod c^nu' minus d/dc_sp of kb prod c^nu''
                 double gf = 0.0, gb = 0.0;
-                for (int side = 0; side < 2; ++side) {
-                    const int n = side ? nprod : nreac;
-                    if (side && !rev) break;
-                    const int *sps = ri + (side ? 10 : 4), *nus = ri + (side ? 13 : 7);
-                    for (int m = 0; m < n; ++m) {
-                        if (sps[m] != sp) continue;
-                        const int nu = nus[m];
-                        const double cm = L.c[sp];
-                        double d = (side ? kb : kf) * (double)nu * (nu == 1 ? 1.0 : (nu == 2 ? cm : cm * cm));
-                        for (int o = 0; o < n; ++o) {
-                            if (o == m) continue;
-                            const double co = L.c[sps[o]];
-                            const int no = nus[o];
-                            d *= (no == 1) ? co : (no == 2 ? co * co : co * co * co);
-                        }
-                        if (side) gb = d; else gf = d;
+                for (int m = 0; m < x.nreac; ++m) {
+                    if (x.reac_sp[m] != sp) continue;
+                    const int nu = x.reac_nu[m];
+                    double d = kf * (double)nu * (nu == 1 ? 1.0 : (nu == 2 ? cr[m] : cr[m] * cr[m]));
+                    for (int o = 0; o < x.nreac; ++o)
+                        if (o != m) d *= cpow_nu(cr[o], x.reac_nu[o]);
+                    gf = d;
+                }
+                if (x.rev) {
+                    for (int m = 0; m < x.nprod; ++m) {
+                        if (x.prod_sp[m] != sp) continue;
+                        const int nu = x.prod_nu[m];
+                        double d = kb * (double)nu * (nu == 1 ? 1.0 : (nu == 2 ? cpd[m] : cpd[m] * cpd[m]));
+                        for (int o = 0; o < x.nprod; ++o)
+                            if (o != m) d *= cpow_nu(cpd[o], x.prod_nu[o]);
+                        gb = d;
                     }
                 }
                 DQ[j * kChunk + lane] = Mc * (gf - gb);
@@ -241,26 +255,35 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         }
         wave_sync();
         if (lane < ns) {
-            const int *ptr = t.sp_ptr + (size_t)lane * (t.nchunk + 1);
-            const double Ms = t.M[lane];
-            double *Jrow = L.J + (size_t)lane * JS;
-            for (int e = ptr[cb]; e < ptr[cb + 1]; ++e) {
+            const int *sp = t.sp_ptr + (size_t)lane * (t.nchunk + 1);
+            for (int e = sp[cb]; e < sp[cb + 1]; ++e) {
                 const int ent = t.sp_list[e];
-                const int r2 = ent >> 4, rl = r2 - cb * kChunk;
+                const int rl = ent >> 4;
                 const double nu = (double)((ent & 15) - 8);
                 w = fma(nu, Q[rl], w);
                 jt = fma(nu, QT[rl], jt);
-                const int *ri = t.rxi + (size_t)r2 * kRxi;
-                const int npart = ri[16], tb = ri[1];
-                const double nuMs = nu * Ms;
-                for (int j = 0; j < npart; ++j) {
-                    const int k = ri[17 + j];
-                    Jrow[k] = fma(nuMs * L.invM[k], DQ[j * kChunk + rl], Jrow[k]);
-                }
-                if (tb >= 0) {
-                    const double *a = t.eff + (size_t)tb * ns;
-                    const double cD = nuMs * DD[rl];
-                    for (int k = 0; k < ns; ++k) Jrow[k] = fma(cD * L.invM[k], a[k], Jrow[k]);
+            }
+            const int *ep = t.ent_ptr + (size_t)lane * (t.nchunk + 1);
+            double *Jrow = L.J + (size_t)lane * JS;
+            for (int e = ep[cb]; e < ep[cb + 1]; ++e) {
+                const int ent = t.ent_list[e];
+                const int rl = ent & 63, slot = (ent >> 6) & 7, k = (ent >> 9) & 63;
+                const double nu = (double)(((ent >> 15) & 15) - 8);
+                Jrow[k] = fma(nu * Ms * L.invM[k], DQ[slot * kChunk + rl], Jrow[k]);
+            }
+        }
+        wave_sync();
+        // dense third-body part, one Jacobian column per lane
+        if (lane < ns) {
+            for (int e = t.tb_ptr[cb]; e < t.tb_ptr[cb + 1]; ++e) {
+                const int r2 = t.tb_list[e];
+                const RxnRec x = t.rxc[r2];
+                const double tk = DD[r2 - cb * kChunk] * t.effM[(size_t)x.tb * ns + lane];
+                for (int j = 0; j < x.npart; ++j) {
+                    if (!x.part_nu[j]) continue;
+                    const int s2 = x.part_sp[j];
+                    double *Jp = L.J + (size_t)s2 * JS + lane;
+                    *Jp = fma((double)x.part_nu[j] * t.M[s2], tk, *Jp);
                 }
             }
         }
@@ -269,12 +292,12 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     // species rows of f and the temperature column
     double fs = 0.0;
     if (lane < ns) {
-        const double ms = t.M[lane] * irc;
+        const double ms = Ms * irc;
         fs = w * ms;
         L.J[(size_t)lane * JS + ns] = jt * ms;
         L.f[lane] = fs;
     }
-    const double cv = wave_sum(xs * cvk * (lane < ns ? 1.0 : 0.0));
+    const double cv = wave_sum(lane < ns ? xs * cvk : 0.0);
     const double dcv = wave_sum(lane < ns ? xs * dcvk : 0.0);
     const double de = wave_sum(ek * fs);
     const double fT = -de / cv;
@@ -424,7 +447,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
     const int lane = threadIdx.x & (kW - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
     const int ns = t.ns, N = ns + 1;
-    const Lds L = lds_map<NPAD>(smem + (size_t)wid * lds_doubles<NPAD>(N), N);
+    const Lds L = lds_map<NPAD>(smem + (size_t)wid * lds_doubles<NPAD>(N, t.ntb), N, t.ntb);
     const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max};
     // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones
     // retire, which balances cells that need very different numbers of Newton iterations
@@ -448,10 +471,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
         int l = adapt ? 0 : a.L_forced;
         int iters = 0, level = bad_in ? 0 : l, st = bad_in ? 3 : 0;
         bool failed = false;
+        unsigned long long hsh = 0xcbf29ce484222325ull;  // FNV-1a of the sub-step attempts
         while (tt < end) {
             if (iters >= a.max_iters) { st = 2; break; }
             const double h = ldexp(a.dt, -l);
-            if (substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters)) {
+            const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters);
+            hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
+            if (ok) {
                 tt += 1ull << (Lc - l);
                 if (adapt && l > 0 && (tt & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
             } else {
@@ -467,7 +493,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
             if (lane < ns) a.Y[(size_t)lane * a.ld + cell] = xs;
             else if (lane == ns) a.T[cell] = xs;
         }
-        if (lane == 0) { a.status[cell] = st; a.level[cell] = level; a.iters[cell] = iters; }
+        if (lane == 0) {
+            a.status[cell] = st;
+            a.level[cell] = level;
+            a.iters[cell] = iters;
+            a.sched[cell] = hsh;
+        }
     }
 }
 
@@ -486,15 +517,15 @@ __global__ void energy_kernel(WaveTables t, long long n, long long ld, const dou
 }
 
 template <int NPAD>
-size_t lds_bytes_host(int N)
+size_t lds_bytes_host(int N, int ntb)
 {
-    return sizeof(double) * ((size_t)N * (NPAD + 1) + 8 * NPAD + 9 * kChunk + NPAD + 2);
+    return sizeof(double) * lds_doubles<NPAD>(N, ntb);
 }
 
 template <int NPAD, bool F32>
 hipError_t launch_t(const WaveTables &t, const AdvanceArgs &a, int wpb, int grid, hipStream_t s)
 {
-    const size_t lds = lds_bytes_host<NPAD>(t.ns + 1) * wpb;
+    const size_t lds = lds_bytes_host<NPAD>(t.ns + 1, t.ntb) * wpb;
     hipLaunchKernelGGL((wave_kernel<NPAD, F32>), dim3(grid), dim3(kW * wpb), lds, s, t, a, wpb);
     return hipGetLastError();
 }
@@ -512,12 +543,12 @@ size_t wave_lds_bytes(const WaveTables &t, bool)
 {
     const int N = t.ns + 1;
     switch (wave_npad(N)) {
-    case 16: return lds_bytes_host<16>(N);
-    case 24: return lds_bytes_host<24>(N);
-    case 32: return lds_bytes_host<32>(N);
-    case 40: return lds_bytes_host<40>(N);
-    case 48: return lds_bytes_host<48>(N);
-    default: return lds_bytes_host<64>(N);
+    case 16: return lds_bytes_host<16>(N, t.ntb);
+    case 24: return lds_bytes_host<24>(N, t.ntb);
+    case 32: return lds_bytes_host<32>(N, t.ntb);
+    case 40: return lds_bytes_host<40>(N, t.ntb);
+    case 48: return lds_bytes_host<48>(N, t.ntb);
+    default: return lds_bytes_host<64>(N, t.ntb);
     }
 }
 

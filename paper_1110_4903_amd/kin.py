@@ -26,7 +26,7 @@ Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS = rang
 EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destroy",
            "kin_mech_upload", "kin_mech_release", "kin_state_upload", "kin_state_reset",
            "kin_advance", "kin_download", "kin_sync", "kin_instance_release", "kin_footprint",
-           "kin_query", "kin_set_layout", "kin_jit_check")
+           "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule")
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -69,8 +69,9 @@ _lib.kin_mech_release.argtypes = [_vp, _i32]
 _lib.kin_state_upload.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
 _lib.kin_state_reset.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
-_lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
+_lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_sync.argtypes = [_vp, _vp]
+_lib.kin_download_schedule.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
 _lib.kin_instance_release.argtypes = [_vp, _i32]
 _lib.kin_footprint.argtypes = [_vp, _i32, _i64, C.c_int, _vp]
 _lib.kin_query.argtypes = [_vp, _i32, _i64, _vp]
@@ -223,13 +224,29 @@ class Context:
         T = np.empty(n)
         Y = np.empty((ns, n))
         st, lv, it = (np.empty(n, np.int32) for _ in range(3))
-        _check(_lib.kin_download(self._h, inst_id, T.ctypes.data, Y.ctypes.data, st.ctypes.data,
+        _check(_lib.kin_download(self._h, inst_id, T.ctypes.data, Y.ctypes.data, None, st.ctypes.data,
                                  lv.ctypes.data, it.ctypes.data, MEM_HOST, None))
         return T, Y, st, lv, it
 
-    def download_device(self, inst_id: int, T, Y, status=None, level=None, iters=None, stream=None):
+    def download_schedule(self, inst_id: int):
+        """Host copy of the per-cell sub-step schedule hashes of the last advance."""
+        _, n, _ = self.inst_info[inst_id]
+        h = np.empty(n, np.uint64)
+        _check(_lib.kin_download_schedule(self._h, inst_id, h.ctypes.data, MEM_HOST, None))
+        return h
+
+    def download_e0(self, inst_id: int):
+        """Host copy of the per-cell internal energy the instance conserves."""
+        _, n, ns = self.inst_info[inst_id]
+        e0 = np.empty(n)
+        _check(_lib.kin_download(self._h, inst_id, None, None, e0.ctypes.data, None, None, None,
+                                 MEM_HOST, None))
+        return e0
+
+    def download_device(self, inst_id: int, T, Y, e0=None, status=None, level=None, iters=None,
+                        stream=None):
         """Device-to-device copy of an instance's state into torch tensors."""
-        ptrs = [(_ptr(a)[0] if a is not None else None) for a in (T, Y, status, level, iters)]
+        ptrs = [(_ptr(a)[0] if a is not None else None) for a in (T, Y, e0, status, level, iters)]
         _check(_lib.kin_download(self._h, inst_id, *ptrs, MEM_DEVICE, _stream_handle(stream)))
 
     def sync(self, stream=None):

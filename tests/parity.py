@@ -20,11 +20,18 @@ def term_scales(om, rho, Y0, T1, Y1, dt):
 
 
 def compare(gpu, ref, rho, Y0, dt, om, rtol, sample=None):
-    """gpu, ref: (T, Y, status, level, iters).  Returns a dict of statistics."""
-    Tg, Yg, sg, lg, ig = gpu
-    Tr, Yr, sr, lr, ir = ref
+    """gpu, ref: (T, Y, status, level, iters[, schedule hash]).  Cells are compared when their
+    status, level and (if both sides give one) sub-step schedule hash agree.  Returns a dict
+    of statistics."""
+    Tg, Yg, sg, lg, ig = gpu[:5]
+    Tr, Yr, sr, lr, ir = ref[:5]
     idx = np.arange(Tg.shape[0]) if sample is None else np.asarray(sample)
     same_sched = (sg[idx] == sr[idx]) & (lg[idx] == lr[idx])
+    sched_mismatch = 0
+    if len(gpu) > 5 and len(ref) > 5:
+        same_hash = gpu[5][idx] == ref[5][idx]
+        sched_mismatch = int((~same_hash).sum())
+        same_sched &= same_hash
     ok_cells = idx[(sr[idx] < 2) & same_sched]
     S = term_scales(om, rho[ok_cells], Y0[:, ok_cells], Tr[ok_cells], Yr[:, ok_cells], dt)
     dY = np.abs(Yg[:, ok_cells] - Yr[:, ok_cells])
@@ -36,6 +43,7 @@ def compare(gpu, ref, rho, Y0, dt, om, rtol, sample=None):
     return dict(
         n=int(idx.shape[0]),
         status_mismatch=int((sg[idx] != sr[idx]).sum()),
+        schedule_mismatch=sched_mismatch,
         level_mismatch=int((lg[idx] != lr[idx]).sum()),
         iters_mismatch=int((ig[idx] != ir[idx]).sum()),
         compared=int(ok_cells.shape[0]),

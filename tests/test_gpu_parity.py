@@ -23,7 +23,7 @@ def run_gpu(ctx, mech, st, dt, prec=0, opts=None, e0=None, mech_id=None):
     mid = mech_id if mech_id is not None else ctx.mech_upload(mech)
     iid = ctx.state_upload(mid, st.rho, st.T, st.Y, e0=e0)
     ctx.advance([iid], [dt], prec=prec, opts=opts)
-    out = ctx.download(iid)
+    out = ctx.download(iid) + (ctx.download_schedule(iid),)
     ctx.instance_release(iid)
     if mech_id is None:
         ctx.mech_release(mid)
@@ -32,7 +32,8 @@ def run_gpu(ctx, mech, st, dt, prec=0, opts=None, e0=None, mech_id=None):
 
 def run_oracle(orc, mech, st, dt, e0=None, **kw):
     om = orc.OracleMech(mech)
-    return om, om.advance(st.rho, st.T, st.Y, dt, e0=e0, opts=orc.make_opts(**kw) if kw else None)
+    return om, om.advance(st.rho, st.T, st.Y, dt, e0=e0, opts=orc.make_opts(**kw) if kw else None,
+                          with_sched=True)
 
 
 def report(name, s):
@@ -46,7 +47,7 @@ def test_isomer_closed_form_gpu(ctx):
     m = isomer_mech(kf, K)
     st = synth.CellStates(np.array([0.3, 0.05, 1.0]), np.array([1500.0, 900.0, 2500.0]),
                           np.array([[0.9, 0.2, 0.5], [0.1, 0.8, 0.5]]))
-    T1, Y1, s, lv, it = run_gpu(ctx, m, st, dt)
+    T1, Y1, s, lv, it = run_gpu(ctx, m, st, dt)[:5]
     assert np.all(s == 0)
     kb = kf / K
     yeq = kb / (kf + kb)
@@ -63,7 +64,7 @@ def test_mech9_small_fp64_lane(ctx, orc):
     om, ref = run_oracle(orc, m, st, dt)
     s = compare(gpu, ref, st.rho, st.Y, dt, om, 1e-10)
     report("mech9 4096 fp64", s)
-    assert s["status_mismatch"] == 0 and s["level_mismatch"] <= 2
+    assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
     assert s["fail_Y"] == 0 and s["fail_T"] == 0
 
 
@@ -76,5 +77,152 @@ def test_mech36_sample_fp64_wave(ctx, orc):
     om, ref = run_oracle(orc, m, sub, dt)
     s = compare(gpu, ref, sub.rho, sub.Y, dt, om, 1e-10)
     report("mech36 512 fp64", s)
-    assert s["status_mismatch"] == 0 and s["level_mismatch"] <= 2
+    assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
     assert s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+def test_mech9_small_fp32lu(ctx, orc):
+    """FP32-LU form against the FP64 oracle: gate 1e-6 per result on cells whose sub-step
+    schedule (status, level) matches; schedule mismatches are counted and bounded."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m, st, dt = synth.workload_small_mech9()
+    gpu = run_gpu(ctx, m, st, dt, prec=kin.FP32_LU)
+    om, ref = run_oracle(orc, m, st, dt)
+    s = compare(gpu, ref, st.rho, st.Y, dt, om, 1e-6)
+    report("mech9 4096 fp32lu", s)
+    # FP32 Newton converges linearly, so some cells take a different sub-step schedule; those
+    # differ by the backward-Euler truncation error and are counted, not gated
+    assert s["schedule_mismatch"] <= 0.1 * s["n"]
+    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+def test_mech36_sample_fp32lu(ctx, orc):
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m, st, dt = synth.workload_mech36(1 << 18)
+    sub = st.subset(np.arange(7, 1 << 18, 1024))
+    gpu = run_gpu(ctx, m, sub, dt, prec=kin.FP32_LU)
+    om, ref = run_oracle(orc, m, sub, dt)
+    s = compare(gpu, ref, sub.rho, sub.Y, dt, om, 1e-6)
+    report("mech36 256 fp32lu", s)
+    assert s["schedule_mismatch"] <= 0.25 * s["n"]
+    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+def test_grid_multistep_sampled(ctx, orc):
+    """The 1024x1024 band grid, three steps of 1e-6 s on the GPU (all cells), compared on a
+    strided sample of cells the oracle advances through the same three steps."""
+    from tests.parity import compare
+    m, grid, dt = synth.workload_grid_mech9()
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload(mid, grid.rho, grid.T, grid.Y)
+    for _ in range(3):
+        ctx.advance([iid], [dt])
+    gpu = ctx.download(iid)
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    sample = np.arange(0, grid.n, 997)
+    sub = grid.subset(sample)
+    om = orc.OracleMech(m)
+    e0 = om.energy_batch(sub.T, sub.Y)
+    T, Y = sub.T.copy(), sub.Y.copy()
+    for _ in range(3):
+        T, Y, s_, l_, i_ = om.advance(sub.rho, T, Y, dt, e0=e0)
+    g = (gpu[0][sample], gpu[1][:, sample], gpu[2][sample], gpu[3][sample], gpu[4][sample])
+    # status/level/iters of the last step only are comparable
+    s = compare(g, (T, Y, s_, l_, i_), sub.rho, sub.Y, 3 * dt, om, 1e-10)
+    report("grid 3 steps sampled", s)
+    assert s["fail_Y"] == 0 and s["fail_T"] == 0 and s["status_mismatch"] == 0
+
+
+def test_mech36_full_size_sampled(ctx, orc):
+    """All 2^18 cells of the 36-species input on the GPU in the launch configuration the
+    benchmark times; 64 strided cells checked against the oracle."""
+    from tests.parity import compare
+    m, st, dt = synth.workload_mech36(1 << 18)
+    gpu = run_gpu(ctx, m, st, dt)
+    assert np.all(gpu[2] < 2)
+    sample = np.arange(3, 1 << 18, 4096)
+    sub = st.subset(sample)
+    om, ref = run_oracle(orc, m, sub, dt)
+    g = tuple(a[..., sample] for a in gpu)
+    s = compare(g, ref, sub.rho, sub.Y, dt, om, 1e-10)
+    report("mech36 2^18 sampled", s)
+    assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1000])
+def test_ragged_sizes_both_layouts(ctx, orc, n):
+    """Cell counts that are not multiples of the wavefront, through both layouts."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m = synth.mechanism("mech9")
+    st = synth.uniform_cells(100 + n, n, m.ns, 1.0)
+    om, ref = run_oracle(orc, m, st, 1e-6)
+    for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
+        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout))
+        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
+        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, (layout, s)
+
+
+def test_bad_inputs_and_forced_failure(ctx, orc):
+    """Non-finite or out-of-range inputs give status 3 and are left untouched; k_max = 1
+    fails every cell at L_max with its state unchanged (checked on the oracle too)."""
+    from paper_1110_4903_amd import kin
+    m = synth.mechanism("mech9")
+    st = synth.uniform_cells(61, 70, m.ns, 1.0)
+    T = st.T.copy()
+    T[0] = np.nan
+    T[1] = 100.0
+    rho = st.rho.copy()
+    rho[2] = -1.0
+    bad = synth.CellStates(rho, T, st.Y)
+    for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
+        Tg, Yg, sg, lg, ig = run_gpu(ctx, m, bad, 1e-6, opts=kin.solver_opts(layout=layout))[:5]
+        assert list(sg[:3]) == [3, 3, 3] and np.all(sg[3:] < 2)
+        assert np.isnan(Tg[0]) and Tg[1] == 100.0 and np.array_equal(Yg[:, :3], st.Y[:, :3])
+        Tg, Yg, sg, lg, ig, hg = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout, k_max=1, L_max=4))
+        _, (To, Yo, so, lo, io, ho) = run_oracle(orc, m, st, 1e-6, k_max=1, L_max=4)
+        assert np.array_equal(hg, ho)
+        assert np.array_equal(sg, so) and np.array_equal(lg, lo) and np.array_equal(ig, io)
+        assert np.all(sg == 2) and np.array_equal(Tg, st.T) and np.array_equal(Yg, st.Y)
+
+
+def test_replay_level_matches_oracle(ctx, orc):
+    """Forced level L (2^L equal sub-steps) through both layouts against the oracle replay."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m = synth.mechanism("mech9")
+    st = synth.uniform_cells(71, 128, m.ns, 1.0)
+    om, ref = run_oracle(orc, m, st, 1e-7)
+    ref = om.advance(st.rho, st.T, st.Y, 1e-7, L_forced=3)
+    for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
+        gpu = run_gpu(ctx, m, st, 1e-7, opts=kin.solver_opts(layout=layout, L_forced=3))
+        s = compare(gpu, ref, st.rho, st.Y, 1e-7, om, 1e-10)
+        assert s["status_mismatch"] == 0 and s["level_mismatch"] == 0, s
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0, s
+
+
+def test_e0_given_and_resume(ctx):
+    """Checkpoint/resume: 4 steps equal 2 steps + download + re-upload (with e0) + 2 steps,
+    bitwise, in the FP64 form."""
+    m, st, dt = synth.workload_small_mech9(512)
+    mid = ctx.mech_upload(m)
+    a = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    for _ in range(4):
+        ctx.advance([a], [dt])
+    Ta, Ya = ctx.download(a)[:2]
+    b = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    for _ in range(2):
+        ctx.advance([b], [dt])
+    Tb, Yb = ctx.download(b)[:2]
+    e0 = ctx.download_e0(b)
+    c = ctx.state_upload(mid, st.rho, Tb, Yb, e0=e0)
+    for _ in range(2):
+        ctx.advance([c], [dt])
+    Tc, Yc = ctx.download(c)[:2]
+    assert np.array_equal(Ta, Tc) and np.array_equal(Ya, Yc)
+    for i in (a, b, c):
+        ctx.instance_release(i)
+    ctx.mech_release(mid)
