@@ -186,6 +186,15 @@ kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
 /* Set a mechanism's layout and block size (what the autotuner decides). */
 kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
 
+/* Autotuner: time one advance of an existing instance with every admissible kernel layout
+ * and block size of its mechanism (lane layout with 64, 128 or 256 threads per block when
+ * ns <= 15; wave layout with 1, 2 or 4 wavefronts per block), keep the fastest for the
+ * mechanism and record it in the context's tune cache file (JSON, keyed by a hash of the
+ * mechanism, the precision and the device), from which kin_mech_upload applies it later.
+ * The instance's state is restored afterwards.  Outputs may be NULL. */
+kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double dt,
+                        kin_precision prec, int32_t *layout, int32_t *block, double *best_ms);
+
 /* Generate the lane-layout source for a mechanism and compile it for gfx950 with hipRTC,
  * without a device.  log (may be NULL) receives up to log_len bytes of compiler output. */
 kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len);

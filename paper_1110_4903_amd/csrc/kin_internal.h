@@ -98,23 +98,61 @@ struct WaveTables {
     const int *ent_list;    //   entries rl | slot << 6 | k << 9 | (nu + 8) << 15
 };
 
-// Arguments of one advance launch (both layouts); mirrors the device-side argument struct.
-struct AdvanceArgs {
-    long long n;
-    long long ld;
+// Device layout of one instance's arena (n cells, ns species), from its base address:
+//   rho[n] e0[n] T[n] Y[ns][n] sched[n] (8-byte entries, each array 256-byte aligned)
+//   status[n] level[n] iters[n] (4-byte entries) and one 64-bit work counter.
+struct Arena {
+    double *rho, *e0, *T, *Y;
+    unsigned long long *sched;
+    int *status, *level, *iters;
+    unsigned long long *counter;
+};
+
+__host__ __device__ inline size_t arena_align(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline Arena arena_at(char *base, long long n, int ns)
+{
+    const size_t d = arena_align(sizeof(double) * (size_t)n);
+    const size_t i = arena_align(sizeof(int) * (size_t)n);
+    Arena a;
+    a.rho = reinterpret_cast<double *>(base);
+    a.e0 = reinterpret_cast<double *>(base + d);
+    a.T = reinterpret_cast<double *>(base + 2 * d);
+    a.Y = reinterpret_cast<double *>(base + 3 * d);
+    a.sched = reinterpret_cast<unsigned long long *>(base + (3 + (size_t)ns) * d);
+    char *ib = base + (4 + (size_t)ns) * d;
+    a.status = reinterpret_cast<int *>(ib);
+    a.level = reinterpret_cast<int *>(ib + i);
+    a.iters = reinterpret_cast<int *>(ib + 2 * i);
+    a.counter = reinterpret_cast<unsigned long long *>(ib + 3 * i);
+    return a;
+}
+
+__host__ __device__ inline size_t arena_bytes(long long n, int ns)
+{
+    return arena_align(sizeof(double) * (size_t)n) * (4 + (size_t)ns) +
+           3 * arena_align(sizeof(int) * (size_t)n) + 256;
+}
+
+// One instance's share of an advance launch: cells [start, start + n) of the launch's global
+// cell index space live in the arena at base, advanced by dt.
+struct CellSpan {
+    long long start, n;
     double dt;
-    const double *rho;
-    const double *e0;
-    double *T;
-    double *Y;
-    int *status;
-    int *level;
-    int *iters;
+    char *base;
+};
+constexpr int kMaxSpans = 64;
+
+// Arguments of one advance launch (both layouts), passed by value; mirrors the device-side
+// argument struct of the generated lane-layout module.
+struct AdvanceArgs {
+    CellSpan span[kMaxSpans];
+    int nspan, ns;
+    long long total;                 // cells over all spans
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
-    const double *K;   // lane layout: the mechanism's constant table
-    unsigned long long *counter;  // next unclaimed cell (zero at launch)
-    unsigned long long *sched;    // per-cell sub-step schedule hash
+    const double *K;                 // lane layout: the mechanism's constant table
+    unsigned long long *counter;     // next unclaimed cell (zero at launch)
 };
 
 // Host launchers of the precompiled kernels (kin_wave.hip).
@@ -123,6 +161,8 @@ hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const d
                          const double *Y, double *e0, hipStream_t stream);
 hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, int waves_per_block,
                        int grid, hipStream_t stream);
+// Zero n 64-bit words with a kernel (graph-capturable, unlike a memset node).
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t stream);
 size_t wave_lds_bytes(const WaveTables &t, bool fp32_lu);
 
 }  // namespace kin

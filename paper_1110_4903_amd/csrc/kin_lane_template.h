@@ -11,23 +11,40 @@
 // system (I - h J) dx = -G with G = x - x_prev - h f(x), iterated as Newton's method on
 // backward Euler; the dense solve is Gaussian elimination with partial pivoting (Sec. 4.2).
 
-struct KinLaneArgs {
-    long long n;          // cells in this launch
-    long long ld;         // leading dimension of Y (cells per species row)
+// One instance's share of the launch: global cells [start, start + n) live in the arena at
+// base (layout below), advanced by dt.
+struct KinSpan {
+    long long start, n;
     double dt;
-    const double *rho;
-    const double *e0;
-    double *T;
-    double *Y;
-    int *status;
-    int *level;
-    int *iters;
+    char *base;
+};
+#define KIN_MAX_SPANS 64
+
+struct KinLaneArgs {
+    KinSpan span[KIN_MAX_SPANS];
+    int nspan, ns;
+    long long total;      // cells over all spans
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
-    unsigned long long *counter;  // next unclaimed cell; zero at launch
-    unsigned long long *sched;    // per-cell sub-step schedule hash (FNV-1a of attempts)
+    unsigned long long *counter;  // next unclaimed global cell; zero at launch
 };
+
+// Arena of an instance of n cells: rho[n] e0[n] T[n] Y[ns][n] sched[n] as 8-byte arrays, then
+// status[n] level[n] iters[n] as 4-byte arrays, each array starting on a 256-byte boundary.
+__device__ __forceinline__ size_t kin_al(size_t x) { return (x + 255) & ~(size_t)255; }
+__device__ __forceinline__ double *kin_rho(char *b, long long n) { return (double *)b; }
+__device__ __forceinline__ double *kin_e0(char *b, long long n) { return (double *)(b + kin_al(8 * (size_t)n)); }
+__device__ __forceinline__ double *kin_T(char *b, long long n) { return (double *)(b + 2 * kin_al(8 * (size_t)n)); }
+__device__ __forceinline__ double *kin_Y(char *b, long long n) { return (double *)(b + 3 * kin_al(8 * (size_t)n)); }
+__device__ __forceinline__ unsigned long long *kin_sched(char *b, long long n)
+{
+    return (unsigned long long *)(b + (3 + KIN_NS) * kin_al(8 * (size_t)n));
+}
+__device__ __forceinline__ int *kin_stat(char *b, long long n, int which)  // 0 status, 1 level, 2 iters
+{
+    return (int *)(b + (4 + KIN_NS) * kin_al(8 * (size_t)n) + which * kin_al(4 * (size_t)n));
+}
 
 #define KIN_SCHED_SEED 0xcbf29ce484222325ull
 #define KIN_SCHED_PRIME 0x100000001b3ull
@@ -223,7 +240,10 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     const int Lc = adapt ? a.L_max : a.L_forced;
     const unsigned long long end = 1ull << Lc;
 
-    long long i = -1;
+    long long i = -1;    // cell index within the lane's span
+    char *base = nullptr;
+    long long nspan_cells = 0;
+    double dt = 0.0;
     bool need = true;    // the lane has no cell in progress
     bool done = false;   // the counter ran past the last cell
     double rho = 0.0, e0 = 0.0;
@@ -240,33 +260,39 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
         if (want) {
             const int leader = __ffsll((long long)want) - 1;
             const int cnt = __popcll(want);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)cnt);
-            base = __shfl(base, leader);
+            unsigned long long gbase = 0;
+            if (lane == leader) gbase = atomicAdd(a.counter, (unsigned long long)cnt);
+            gbase = __shfl(gbase, leader);
             if (need && !done) {
                 const unsigned int lo = (unsigned int)want, hi = (unsigned int)(want >> 32);
                 const int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-                const unsigned long long ci = base + (unsigned long long)rank;
-                if (ci >= (unsigned long long)a.n) {
+                const unsigned long long gi = gbase + (unsigned long long)rank;
+                if (gi >= (unsigned long long)a.total) {
                     done = true;
                     i = -1;
                 } else {
-                    i = (long long)ci;
+                    int j = 0;
+                    while (j + 1 < a.nspan && (unsigned long long)a.span[j + 1].start <= gi) ++j;
+                    base = a.span[j].base;
+                    nspan_cells = a.span[j].n;
+                    dt = a.span[j].dt;
+                    i = (long long)gi - a.span[j].start;
                     need = false;
-                    rho = a.rho[i];
-                    e0 = a.e0[i];
+                    const double *Yin = kin_Y(base, nspan_cells);
+                    rho = kin_rho(base, nspan_cells)[i];
+                    e0 = kin_e0(base, nspan_cells)[i];
 #pragma unroll
-                    for (int s = 0; s < KIN_NS; ++s) x[s] = a.Y[s * a.ld + i];
-                    x[KIN_NS] = a.T[i];
-                    double chk = rho - rho + e0 - e0 + a.dt - a.dt;
+                    for (int s = 0; s < KIN_NS; ++s) x[s] = Yin[s * nspan_cells + i];
+                    x[KIN_NS] = kin_T(base, nspan_cells)[i];
+                    double chk = rho - rho + e0 - e0 + dt - dt;
 #pragma unroll
                     for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
-                    if (!(chk == 0.0) || !(rho > 0.0) || !(a.dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
+                    if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
                         x[KIN_NS] > KIN_T_MAX) {
-                        a.status[i] = 3;
-                        a.level[i] = 0;
-                        a.iters[i] = 0;
-                        a.sched[i] = KIN_SCHED_SEED;
+                        kin_stat(base, nspan_cells, 0)[i] = 3;
+                        kin_stat(base, nspan_cells, 1)[i] = 0;
+                        kin_stat(base, nspan_cells, 2)[i] = 0;
+                        kin_sched(base, nspan_cells)[i] = KIN_SCHED_SEED;
                         need = true;
                     } else {
 #pragma unroll
@@ -294,7 +320,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 outcome = KIN_CONTINUE;
             } else {
                 ++iters;
-                outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(a.dt, -l));
+                outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(dt, -l));
                 if (outcome == KIN_CONTINUE && ++k >= a.k_max) outcome = KIN_ATTEMPT_FAILED;
             }
             if (outcome != KIN_CONTINUE)
@@ -321,14 +347,15 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
             }
             if (st >= 0) {
                 if (st != 2) {
+                    double *Yout = kin_Y(base, nspan_cells);
 #pragma unroll
-                    for (int s = 0; s < KIN_NS; ++s) a.Y[s * a.ld + i] = x[s];
-                    a.T[i] = x[KIN_NS];
+                    for (int s = 0; s < KIN_NS; ++s) Yout[s * nspan_cells + i] = x[s];
+                    kin_T(base, nspan_cells)[i] = x[KIN_NS];
                 }
-                a.status[i] = st;
-                a.level[i] = level;
-                a.iters[i] = iters;
-                a.sched[i] = hsh;
+                kin_stat(base, nspan_cells, 0)[i] = st;
+                kin_stat(base, nspan_cells, 1)[i] = level;
+                kin_stat(base, nspan_cells, 2)[i] = iters;
+                kin_sched(base, nspan_cells)[i] = hsh;
                 need = true;
             }
         }

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -52,12 +54,13 @@ static std::unordered_map<std::string, std::pair<std::vector<char>, double>> g_j
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static uint64_t inst_bytes(int ns, long long n)
-{
-    const size_t d = align256(sizeof(double) * (size_t)n);
-    const size_t i = align256(sizeof(int) * (size_t)n);
-    return (uint64_t)(d * (4 + (size_t)ns) + 3 * i + 256);
-}
+static uint64_t inst_bytes(int ns, long long n) { return (uint64_t)arena_bytes(n, ns); }
+
+// A cached, instantiated graph of one batched advance.
+struct Plan {
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> insts;
+};
 
 }  // namespace kin
 
@@ -72,6 +75,15 @@ struct kin_ctx {
     std::map<int, std::unique_ptr<kin::Mech>> mechs;
     std::map<int, std::unique_ptr<kin::Inst>> insts;
     int next_mech = 1, next_inst = 1;
+    // batched advances: capture streams (default priority), per-launch work counters and
+    // instantiated graphs keyed by the launch description
+    std::vector<hipStream_t> cap;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    unsigned long long *counters = nullptr;
+    int ncounters = 0;
+    std::map<std::string, kin::Plan> plans;
+    kin_status plan_status = KIN_OK;
 };
 
 using namespace kin;
@@ -147,6 +159,11 @@ void kin_destroy(kin_ctx *ctx)
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         hipSetDevice(ctx->device);
         hipDeviceSynchronize();
+        for (auto &kv : ctx->plans) hipGraphExecDestroy(kv.second.exec);
+        for (hipStream_t st : ctx->cap) hipStreamDestroy(st);
+        for (hipEvent_t ev : ctx->join) hipEventDestroy(ev);
+        if (ctx->fork) hipEventDestroy(ctx->fork);
+        hipFree(ctx->counters);
         for (auto &kv : ctx->insts) hipFree(kv.second->buf);
         for (auto &kv : ctx->mechs) {
             if (kv.second->mod) hipModuleUnload(kv.second->mod);
@@ -296,6 +313,81 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     return KIN_OK;
 }
 
+// ---- autotuner cache ----------------------------------------------------------------------
+static uint64_t fnv(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    return h;
+}
+
+static std::string tune_key(const kin_ctx *ctx, const Mech &m, int prec)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    const MechHost &x = m.h;
+    h = fnv(h, &x.ns, sizeof x.ns);
+    h = fnv(h, &x.nr, sizeof x.nr);
+    h = fnv(h, x.M.data(), sizeof(double) * x.M.size());
+    h = fnv(h, x.nasa.data(), sizeof(double) * x.nasa.size());
+    for (const Rxn &r : x.rx) h = fnv(h, &r, sizeof r);
+    h = fnv(h, x.eff.data(), sizeof(double) * x.eff.size());
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) h = fnv(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%016llx-p%d", (unsigned long long)h, prec);
+    return buf;
+}
+
+// The cache file holds one flat JSON object: {"<key>": [layout, block, ms], ...}.
+static std::map<std::string, std::vector<double>> tune_read(const std::string &path)
+{
+    std::map<std::string, std::vector<double>> out;
+    FILE *f = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    std::string txt;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, r);
+    std::fclose(f);
+    size_t p = 0;
+    while ((p = txt.find('"', p)) != std::string::npos) {
+        const size_t q = txt.find('"', p + 1);
+        if (q == std::string::npos) break;
+        const std::string key = txt.substr(p + 1, q - p - 1);
+        const size_t lb = txt.find('[', q), rb = txt.find(']', q);
+        if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+        std::vector<double> v;
+        std::string body = txt.substr(lb + 1, rb - lb - 1);
+        size_t s0 = 0;
+        while (s0 < body.size()) {
+            size_t e = body.find(',', s0);
+            if (e == std::string::npos) e = body.size();
+            v.push_back(std::atof(body.substr(s0, e - s0).c_str()));
+            s0 = e + 1;
+        }
+        out[key] = v;
+        p = rb + 1;
+    }
+    return out;
+}
+
+static void tune_write(const std::string &path, const std::map<std::string, std::vector<double>> &m)
+{
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : m) {
+        std::fprintf(f, "  \"%s\": [%d, %d, %.6g]%s\n", kv.first.c_str(), (int)kv.second[0], (int)kv.second[1],
+                     kv.second.size() > 2 ? kv.second[2] : 0.0, ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path.c_str());
+}
+
 kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_id)
 {
     kin_status s = enter(ctx);
@@ -320,6 +412,22 @@ kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_i
     } else {
         m->layout = KIN_LAYOUT_WAVE;
         m->block = 2;
+    }
+    {   // a tuned choice (FP64 entry) from the cache file, if any
+        const auto cache = tune_read(ctx->tune_cache);
+        auto it = cache.find(tune_key(ctx, *m, KIN_FP64));
+        if (it != cache.end() && it->second.size() >= 2) {
+            const int lay = (int)it->second[0], blk = (int)it->second[1];
+            if (lay == KIN_LAYOUT_WAVE && blk >= 1 && blk <= 4) {
+                m->layout = lay;
+                m->block = blk;
+            } else if (lay == KIN_LAYOUT_LANE && m->h.ns <= kLaneNsMax && (blk == 64 || blk == 128 || blk == 256)) {
+                if ((s = build_lane(ctx, *m, blk)) == KIN_OK) {
+                    m->layout = lay;
+                    m->block = blk;
+                }
+            }
+        }
     }
     const int id = ctx->next_mech++;
     ctx->mechs[id] = std::move(m);
@@ -412,18 +520,10 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     in->bytes = bytes;
     KIN_HIP(ctx, hipMalloc(&in->buf, bytes));
     char *b = static_cast<char *>(in->buf);
-    const size_t d = align256(sizeof(double) * (size_t)n_cells);
+    const Arena ar = arena_at(b, n_cells, m.h.ns);
     const size_t i = align256(sizeof(int) * (size_t)n_cells);
-    in->rho = reinterpret_cast<double *>(b);
-    in->e0 = reinterpret_cast<double *>(b + d);
-    in->T = reinterpret_cast<double *>(b + 2 * d);
-    in->Y = reinterpret_cast<double *>(b + 3 * d);
-    in->sched = reinterpret_cast<unsigned long long *>(b + (3 + (size_t)m.h.ns) * d);
-    char *ib = b + (4 + (size_t)m.h.ns) * d;
-    in->status = reinterpret_cast<int *>(ib);
-    in->level = reinterpret_cast<int *>(ib + i);
-    in->iters = reinterpret_cast<int *>(ib + 2 * i);
-    in->counter = reinterpret_cast<unsigned long long *>(ib + 3 * i);
+    in->rho = ar.rho; in->e0 = ar.e0; in->T = ar.T; in->Y = ar.Y; in->sched = ar.sched;
+    in->status = ar.status; in->level = ar.level; in->iters = ar.iters; in->counter = ar.counter;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((s = fill_state(ctx, *in, m, rho, T, Y, e0, where, st)) != KIN_OK) {
         hipFree(in->buf);
@@ -453,29 +553,29 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
     return fill_state(ctx, in, m, rho, T, Y, e0, where, static_cast<hipStream_t>(stream));
 }
 
-static AdvanceArgs make_args(const Inst &in, double dt, const kin_solver_opts &o)
+static void fill_opts(AdvanceArgs &a, const kin_solver_opts &o)
 {
-    AdvanceArgs a{};
-    a.n = in.n; a.ld = in.ld; a.dt = dt;
-    a.rho = in.rho; a.e0 = in.e0; a.T = in.T; a.Y = in.Y;
-    a.status = in.status; a.level = in.level; a.iters = in.iters;
     a.rtol = o.rtol; a.atol_Y = o.atol_Y; a.atol_T = o.atol_T; a.y_neg = o.y_neg;
     a.k_max = o.k_max; a.L_max = o.L_max; a.L_forced = o.L_forced; a.max_iters = o.max_iters;
-    a.counter = in.counter;
-    a.sched = in.sched;
-    return a;
 }
 
-static kin_status launch_one(kin_ctx *ctx, Mech &m, const Inst &in, double dt, kin_precision prec,
-                             const kin_solver_opts &o, hipStream_t st)
+// Effective (layout, block) of a mechanism for these options.
+static void layout_of(const Mech &m, const kin_solver_opts &o, int &layout, int &block)
 {
-    int layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
-    AdvanceArgs a = make_args(in, dt, o);
+    layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
+    if (layout == KIN_LAYOUT_LANE) block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
+    else block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 2;
+}
+
+// Launch one kernel over the spans in a (all of mechanism m) on stream st.  The work counter
+// a.counter must already be zero (stream order).
+static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precision prec, int layout,
+                               int block, hipStream_t st)
+{
     const bool f32 = prec == KIN_FP32_LU;
-    KIN_HIP(ctx, hipMemsetAsync(in.counter, 0, sizeof(unsigned long long), st));
+    a.ns = m.h.ns;
     if (layout == KIN_LAYOUT_LANE) {
         if (m.h.ns > kLaneNsMax) return err(KIN_EINVAL, "lane layout needs ns <= 15");
-        const int block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
         kin_status s = build_lane(ctx, m, block);
         if (s != KIN_OK) return s;
         hipFunction_t fn = f32 ? m.lane_f32 : m.lane_f64;
@@ -483,17 +583,144 @@ static kin_status launch_one(kin_ctx *ctx, Mech &m, const Inst &in, double dt, k
         KIN_HIP(ctx, hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0));
         if (per_cu < 1) per_cu = 1;
         // persistent lanes: one resident wave set; more blocks than fit would only wait
-        const long long grid = std::min<long long>((in.n + block - 1) / block, (long long)per_cu * ctx->num_cu);
+        const long long grid = std::min<long long>((a.total + block - 1) / block, (long long)per_cu * ctx->num_cu);
         a.K = m.kconst;
         void *params[] = {&a};
         KIN_HIP(ctx, hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
     } else {
-        const int wpb = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 2;
-        const long long blocks = (in.n + wpb - 1) / wpb;
+        const long long blocks = (a.total + block - 1) / block;
         if (blocks > 0x7fffffffLL) return err(KIN_EINVAL, "too many cells for one wave-layout launch");
-        const int grid = (int)blocks;
-        KIN_HIP(ctx, launch_wave(m.tab, a, f32, wpb, grid, st));
+        KIN_HIP(ctx, launch_wave(m.tab, a, f32, block, (int)blocks, st));
     }
+    return KIN_OK;
+}
+
+static bool opts_ok(const kin_solver_opts &o)
+{
+    return o.rtol >= 0 && o.atol_Y >= 0 && o.atol_T >= 0 && o.y_neg >= 0 && o.k_max >= 1 && o.L_max >= 0 &&
+           o.L_max <= 62 && o.L_forced <= 30 && o.L_forced >= -1 && o.max_iters >= 1 &&
+           o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_WAVE;
+}
+
+// Batched advance: instances grouped by (mechanism, layout), at most kMaxSpans per launch, each
+// launch preceded by a kernel that zeroes its work counter, launches of different groups on
+// parallel branches; captured once into a graph and replayed while the description is unchanged.
+static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *dts, int n, kin_precision prec,
+                                const kin_solver_opts &o, hipStream_t user)
+{
+    struct Launch {
+        Mech *m;
+        int layout, block;
+        AdvanceArgs a;
+    };
+    std::map<std::pair<int, int>, std::vector<int>> groups;  // (mech, layout) -> positions
+    for (int k = 0; k < n; ++k) {
+        Inst &in = *ctx->insts[ids[k]];
+        Mech &m = *ctx->mechs[in.mech];
+        int layout, block;
+        layout_of(m, o, layout, block);
+        groups[{in.mech, layout}].push_back(k);
+    }
+    std::vector<Launch> launches;
+    for (auto &g : groups) {
+        Mech &m = *ctx->mechs[g.first.first];
+        int layout, block;
+        layout_of(m, o, layout, block);
+        for (size_t off = 0; off < g.second.size(); off += kMaxSpans) {
+            Launch L;
+            L.m = &m; L.layout = layout; L.block = block;
+            std::memset(&L.a, 0, sizeof L.a);
+            fill_opts(L.a, o);
+            long long total = 0;
+            const size_t cnt = std::min<size_t>(kMaxSpans, g.second.size() - off);
+            for (size_t q = 0; q < cnt; ++q) {
+                const int k = g.second[off + q];
+                Inst &in = *ctx->insts[ids[k]];
+                L.a.span[q].start = total;
+                L.a.span[q].n = in.n;
+                L.a.span[q].dt = dts[k];
+                L.a.span[q].base = static_cast<char *>(in.buf);
+                total += in.n;
+            }
+            L.a.nspan = (int)cnt;
+            L.a.total = total;
+            launches.push_back(L);
+        }
+    }
+    const int nl = (int)launches.size();
+    // key: everything the captured kernels depend on
+    std::string key(reinterpret_cast<const char *>(&prec), sizeof prec);
+    key.append(reinterpret_cast<const char *>(&o), sizeof o);
+    for (const Launch &L : launches) {
+        key.append(reinterpret_cast<const char *>(&L.layout), sizeof(int));
+        key.append(reinterpret_cast<const char *>(&L.block), sizeof(int));
+        key.append(reinterpret_cast<const char *>(&L.m), sizeof(void *));
+        key.append(reinterpret_cast<const char *>(L.a.span), sizeof(CellSpan) * L.a.nspan);
+    }
+    auto pit = ctx->plans.find(key);
+    if (pit == ctx->plans.end()) {
+        if (ctx->ncounters < nl) {
+            // existing graphs point at the old counters
+            for (auto &kv : ctx->plans) KIN_HIP(ctx, hipGraphExecDestroy(kv.second.exec));
+            ctx->plans.clear();
+            if (ctx->counters) KIN_HIP(ctx, hipFree(ctx->counters));
+            ctx->ncounters = std::max(nl, 16);
+            KIN_HIP(ctx, hipMalloc(&ctx->counters, sizeof(unsigned long long) * ctx->ncounters));
+        }
+        while ((int)ctx->cap.size() < nl) {
+            hipStream_t sx;
+            KIN_HIP(ctx, hipStreamCreateWithFlags(&sx, hipStreamNonBlocking));
+            ctx->cap.push_back(sx);
+            hipEvent_t ev;
+            KIN_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            ctx->join.push_back(ev);
+        }
+        if (!ctx->fork) KIN_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+        // compile lane modules outside the capture
+        for (Launch &L : launches)
+            if (L.layout == KIN_LAYOUT_LANE) {
+                kin_status s = build_lane(ctx, *L.m, L.block);
+                if (s != KIN_OK) return s;
+            }
+        hipStream_t c0 = ctx->cap[0];
+        KIN_HIP(ctx, hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
+        kin_status cs = KIN_OK;
+        hipError_t he = hipEventRecord(ctx->fork, c0);
+        for (int q = 0; q < nl && he == hipSuccess && cs == KIN_OK; ++q) {
+            hipStream_t sq = ctx->cap[q];
+            if (q > 0) he = hipStreamWaitEvent(sq, ctx->fork, 0);
+            if (he != hipSuccess) break;
+            launches[q].a.counter = ctx->counters + q;
+            he = launch_zero_u64(ctx->counters + q, 1, sq);
+            if (he != hipSuccess) break;
+            cs = launch_spans(ctx, *launches[q].m, launches[q].a, prec, launches[q].layout, launches[q].block, sq);
+            if (cs == KIN_OK && q > 0) {
+                he = hipEventRecord(ctx->join[q], sq);
+                if (he == hipSuccess) he = hipStreamWaitEvent(c0, ctx->join[q], 0);
+            }
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t he2 = hipStreamEndCapture(c0, &graph);
+        if (cs != KIN_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return cs;
+        }
+        if (he != hipSuccess || he2 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            ctx->poisoned = true;
+            return err(KIN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(he != hipSuccess ? he : he2));
+        }
+        Plan plan;
+        hipError_t he3 = hipGraphInstantiate(&plan.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (he3 != hipSuccess) {
+            ctx->poisoned = true;
+            return err(KIN_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(he3));
+        }
+        plan.insts.assign(ids, ids + n);
+        pit = ctx->plans.emplace(key, plan).first;
+    }
+    KIN_HIP(ctx, hipGraphLaunch(pit->second.exec, user));
     return KIN_OK;
 }
 
@@ -507,22 +734,33 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     kin_solver_opts o;
     kin_default_solver_opts(&o);
     if (sopt) o = *sopt;
-    if (!(o.rtol >= 0) || !(o.atol_Y >= 0) || !(o.atol_T >= 0) || !(o.y_neg >= 0) || o.k_max < 1 ||
-        o.L_max < 0 || o.L_max > 62 || o.L_forced > 30 || o.L_forced < -1 || o.max_iters < 1)
-        return err(KIN_EINVAL, "bad solver options");
+    if (!opts_ok(o)) return err(KIN_EINVAL, "bad solver options");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     for (int k = 0; k < n; ++k) {
         auto it = ctx->insts.find(inst_ids[k]);
         if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
         if (!std::isfinite(dts[k]) || dts[k] < 0) return err(KIN_EINVAL, "dt must be finite and >= 0");
+        for (int q = 0; q < k; ++q)
+            if (inst_ids[q] == inst_ids[k]) return err(KIN_EINVAL, "an instance appears twice in one advance");
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int k = 0; k < n; ++k) {
-        Inst &in = *ctx->insts[inst_ids[k]];
-        Mech &m = *ctx->mechs[in.mech];
-        if ((s = launch_one(ctx, m, in, dts[k], prec, o, st)) != KIN_OK) return s;
-    }
-    return KIN_OK;
+    if (n > 1) return advance_batch(ctx, inst_ids, dts, n, prec, o, st);
+    Inst &in = *ctx->insts[inst_ids[0]];
+    Mech &m = *ctx->mechs[in.mech];
+    int layout, block;
+    layout_of(m, o, layout, block);
+    AdvanceArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_opts(a, o);
+    a.span[0].start = 0;
+    a.span[0].n = in.n;
+    a.span[0].dt = dts[0];
+    a.span[0].base = static_cast<char *>(in.buf);
+    a.nspan = 1;
+    a.total = in.n;
+    a.counter = in.counter;
+    KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
+    return launch_spans(ctx, m, a, prec, layout, block, st);
 }
 
 kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,
@@ -581,6 +819,14 @@ kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id)
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->insts.find(inst_id);
     if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
+    for (auto pit = ctx->plans.begin(); pit != ctx->plans.end();) {
+        if (std::find(pit->second.insts.begin(), pit->second.insts.end(), inst_id) != pit->second.insts.end()) {
+            KIN_HIP(ctx, hipGraphExecDestroy(pit->second.exec));
+            pit = ctx->plans.erase(pit);
+        } else {
+            ++pit;
+        }
+    }
     KIN_HIP(ctx, hipFree(it->second->buf));
     ctx->in_use -= it->second->bytes;
     ctx->mechs[it->second->mech]->refs--;
@@ -632,6 +878,66 @@ kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out)
     default:
         return err(KIN_EINVAL, "unknown query");
     }
+}
+
+kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double dt, kin_precision prec,
+                        int32_t *layout_out, int32_t *block_out, double *best_ms)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!std::isfinite(dt) || dt < 0) return err(KIN_EINVAL, "dt must be finite and >= 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto mit = ctx->mechs.find(mech_id);
+    auto iit = ctx->insts.find(inst_id);
+    if (mit == ctx->mechs.end() || iit == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown id");
+    Mech &m = *mit->second;
+    Inst &in = *iit->second;
+    if (in.mech != mech_id) return err(KIN_EINVAL, "instance belongs to another mechanism");
+    std::vector<std::pair<int, int>> cand;
+    if (m.h.ns <= kLaneNsMax)
+        for (int b : {64, 128, 256}) cand.push_back({KIN_LAYOUT_LANE, b});
+    for (int b : {1, 2, 4}) cand.push_back({KIN_LAYOUT_WAVE, b});
+    void *save = nullptr;
+    KIN_HIP(ctx, hipMalloc(&save, in.bytes));
+    KIN_HIP(ctx, hipMemcpy(save, in.buf, in.bytes, hipMemcpyDeviceToDevice));
+    hipEvent_t e0, e1;
+    KIN_HIP(ctx, hipEventCreate(&e0));
+    KIN_HIP(ctx, hipEventCreate(&e1));
+    const int old_layout = m.layout, old_block = m.block;
+    double best = 1e300;
+    std::pair<int, int> win = {old_layout, old_block};
+    kin_solver_opts o;
+    kin_default_solver_opts(&o);
+    for (const auto &c : cand) {
+        if ((s = kin_set_layout(ctx, mech_id, c.first, c.second)) != KIN_OK) break;
+        KIN_HIP(ctx, hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice));
+        // one untimed launch loads the module and warms the caches
+        if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, &o, nullptr)) != KIN_OK) break;
+        KIN_HIP(ctx, hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice));
+        KIN_HIP(ctx, hipEventRecord(e0, nullptr));
+        if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, &o, nullptr)) != KIN_OK) break;
+        KIN_HIP(ctx, hipEventRecord(e1, nullptr));
+        KIN_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        KIN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; win = c; }
+    }
+    hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice);
+    hipFree(save);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != KIN_OK) {
+        kin_set_layout(ctx, mech_id, old_layout, old_block);
+        return s;
+    }
+    if ((s = kin_set_layout(ctx, mech_id, win.first, win.second)) != KIN_OK) return s;
+    auto cache = tune_read(ctx->tune_cache);
+    cache[tune_key(ctx, m, prec)] = {(double)win.first, (double)win.second, best};
+    tune_write(ctx->tune_cache, cache);
+    if (layout_out) *layout_out = win.first;
+    if (block_out) *block_out = win.second;
+    if (best_ms) *best_ms = best;
+    return KIN_OK;
 }
 
 kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len)

@@ -452,17 +452,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
     // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones
     // retire, which balances cells that need very different numbers of Newton iterations
     {
-        const long long cell = (long long)blockIdx.x * wpb + wid;
-        if (cell >= a.n) return;
-        const double rho = a.rho[cell];
-        const double e0 = a.e0[cell];
+        const long long gcell = (long long)blockIdx.x * wpb + wid;
+        if (gcell >= a.total) return;
+        int j = 0;
+        while (j + 1 < a.nspan && a.span[j + 1].start <= gcell) ++j;
+        const long long cell = gcell - a.span[j].start;
+        const double dt = a.span[j].dt;
+        const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
+        const long long ld = a.span[j].n;
+        const double rho = ar.rho[cell];
+        const double e0 = ar.e0[cell];
         double xs = 0.0;
-        if (lane < ns) xs = a.Y[(size_t)lane * a.ld + cell];
-        else if (lane == ns) xs = a.T[cell];
+        if (lane < ns) xs = ar.Y[(size_t)lane * ld + cell];
+        else if (lane == ns) xs = ar.T[cell];
         const double T0 = bcast(xs, ns);
         const bool bad_in = __any(lane < N && !__builtin_isfinite(xs)) || !__builtin_isfinite(rho) ||
-                            !(rho > 0.0) || !__builtin_isfinite(e0) || !__builtin_isfinite(a.dt) ||
-                            !(a.dt >= 0.0) || T0 < kTmin || T0 > kTmax;
+                            !(rho > 0.0) || !__builtin_isfinite(e0) || !__builtin_isfinite(dt) ||
+                            !(dt >= 0.0) || T0 < kTmin || T0 > kTmax;
         // dyadic sub-stepping in ticks of dt 2^-Lc (see the lane layout for the rule)
         const bool adapt = a.L_forced < 0;
         const int Lc = adapt ? a.L_max : a.L_forced;
@@ -474,7 +480,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
         unsigned long long hsh = 0xcbf29ce484222325ull;  // FNV-1a of the sub-step attempts
         while (tt < end) {
             if (iters >= a.max_iters) { st = 2; break; }
-            const double h = ldexp(a.dt, -l);
+            const double h = ldexp(dt, -l);
             const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters);
             hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
             if (ok) {
@@ -490,16 +496,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) w
         }
         if (st == 0 && failed) st = 1;
         if (st < 2) {
-            if (lane < ns) a.Y[(size_t)lane * a.ld + cell] = xs;
-            else if (lane == ns) a.T[cell] = xs;
+            if (lane < ns) ar.Y[(size_t)lane * ld + cell] = xs;
+            else if (lane == ns) ar.T[cell] = xs;
         }
         if (lane == 0) {
-            a.status[cell] = st;
-            a.level[cell] = level;
-            a.iters[cell] = iters;
-            a.sched[cell] = hsh;
+            ar.status[cell] = st;
+            ar.level[cell] = level;
+            ar.iters[cell] = iters;
+            ar.sched[cell] = hsh;
         }
     }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
 }
 
 __global__ void energy_kernel(WaveTables t, long long n, long long ld, const double *T,
@@ -570,6 +582,12 @@ hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool f32, int 
         return hipErrorInvalidValue;
     }
 #undef KIN_CASE
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,

@@ -26,7 +26,7 @@ Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS = rang
 EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destroy",
            "kin_mech_upload", "kin_mech_release", "kin_state_upload", "kin_state_reset",
            "kin_advance", "kin_download", "kin_sync", "kin_instance_release", "kin_footprint",
-           "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule")
+           "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune")
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -72,6 +72,7 @@ _lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_sync.argtypes = [_vp, _vp]
 _lib.kin_download_schedule.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
+_lib.kin_autotune.argtypes = [_vp, _i32, _i32, C.c_double, C.c_int, _vp, _vp, _vp]
 _lib.kin_instance_release.argtypes = [_vp, _i32]
 _lib.kin_footprint.argtypes = [_vp, _i32, _i64, C.c_int, _vp]
 _lib.kin_query.argtypes = [_vp, _i32, _i64, _vp]
@@ -187,6 +188,13 @@ class Context:
 
     def set_layout(self, mech_id: int, layout: int, block: int):
         _check(_lib.kin_set_layout(self._h, mech_id, layout, block))
+
+    def autotune(self, mech_id: int, inst_id: int, dt: float, prec: int = FP64):
+        """Time every admissible (layout, block) on an instance and keep the fastest."""
+        lay, blk, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.kin_autotune(self._h, mech_id, inst_id, float(dt), prec, C.byref(lay), C.byref(blk),
+                                 C.byref(ms)))
+        return lay.value, blk.value, ms.value
 
     # -- instances --------------------------------------------------------------------------
     def state_upload(self, mech_id: int, rho, T, Y, e0=None, stream=None) -> int:

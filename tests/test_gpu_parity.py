@@ -226,3 +226,86 @@ def test_e0_given_and_resume(ctx):
     for i in (a, b, c):
         ctx.instance_release(i)
     ctx.mech_release(mid)
+
+
+def _batch_setup(ctx, insts):
+    mids = {}
+    ids, states = [], []
+    for ins in insts:
+        if ins.mech not in mids:
+            mids[ins.mech] = ctx.mech_upload(synth.mechanism(ins.mech))
+        st = ins.states()
+        states.append(st)
+        ids.append(ctx.state_upload(mids[ins.mech], st.rho, st.T, st.Y))
+    return mids, ids, states
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_graph_equals_single_launches(ctx, prec):
+    """An uneven batch (mech9 and mech36 instances of 1..3000 cells, one dt each) advanced in
+    one call (one graph launch, one kernel per mechanism and layout, spans of up to 64
+    instances) gives, bitwise, what advancing every instance alone gives.  70 instances, so
+    the 9-species group needs two launches of its span table."""
+    insts = synth.batch_instances(seed=11, n_inst=70, min_cells=1, max_cells=3000)
+    mids, ids, states = _batch_setup(ctx, insts)
+    dts = [ins.dt for ins in insts]
+    ctx.advance(ids, dts, prec=prec)
+    batched = [ctx.download(i) + (ctx.download_schedule(i),) for i in ids]
+    # a second batched call replays the cached graph
+    for i, st in zip(ids, states):
+        ctx.state_reset(i, st.rho, st.T, st.Y)
+    ctx.advance(ids, dts, prec=prec)
+    again = [ctx.download(i) + (ctx.download_schedule(i),) for i in ids]
+    for i, st in zip(ids, states):
+        ctx.state_reset(i, st.rho, st.T, st.Y)
+    for i, dt in zip(ids, dts):
+        ctx.advance([i], [dt], prec=prec)
+    single = [ctx.download(i) + (ctx.download_schedule(i),) for i in ids]
+    for k, (a, b, c) in enumerate(zip(batched, again, single)):
+        for x, y, z in zip(a, b, c):
+            assert np.array_equal(x, z, equal_nan=True), (k, insts[k])
+            assert np.array_equal(y, z, equal_nan=True), (k, insts[k])
+    for i in ids:
+        ctx.instance_release(i)
+    for m in mids.values():
+        ctx.mech_release(m)
+
+
+def test_batched_against_oracle(ctx, orc):
+    """Every instance of a 24-instance uneven batch, advanced in one call, against the
+    oracle per instance (FP64 gate)."""
+    from tests.parity import compare
+    insts = synth.batch_instances(seed=12, n_inst=24, min_cells=1, max_cells=400)
+    mids, ids, states = _batch_setup(ctx, insts)
+    ctx.advance(ids, [ins.dt for ins in insts])
+    for ins, i, st in zip(insts, ids, states):
+        gpu = ctx.download(i) + (ctx.download_schedule(i),)
+        om, ref = run_oracle(orc, synth.mechanism(ins.mech), st, ins.dt)
+        s = compare(gpu, ref, st.rho, st.Y, ins.dt, om, 1e-10)
+        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, (ins, s)
+        assert s["schedule_mismatch"] <= max(1, ins.n_cells // 200), (ins, s)
+        ctx.instance_release(i)
+    for m in mids.values():
+        ctx.mech_release(m)
+
+
+def test_autotune_restores_state_and_persists(ctx, tmp_path):
+    """The autotuner leaves the instance's state as it was, picks an admissible layout, and a
+    new context reading its cache file applies the same choice at upload."""
+    from paper_1110_4903_amd import kin
+    cache = str(tmp_path / "tune.json")
+    m, st, dt = synth.workload_small_mech9(8192)
+    with kin.Context(0, tune_cache=cache) as c1:
+        mid = c1.mech_upload(m)
+        iid = c1.state_upload(mid, st.rho, st.T, st.Y)
+        before = c1.download(iid)[:2]
+        lay, blk, ms = c1.autotune(mid, iid, dt)
+        after = c1.download(iid)[:2]
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        assert (lay, blk) in {(kin.LAYOUT_LANE, 64), (kin.LAYOUT_LANE, 128), (kin.LAYOUT_LANE, 256),
+                              (kin.LAYOUT_WAVE, 1), (kin.LAYOUT_WAVE, 2), (kin.LAYOUT_WAVE, 4)}
+        assert ms > 0
+        print(f"\n[autotune mech9 8192] layout={lay} block={blk} {ms:.3f} ms", flush=True)
+    with kin.Context(0, tune_cache=cache) as c2:
+        mid = c2.mech_upload(m)
+        assert c2.query_int(kin.Q_LAYOUT, mid) == lay and c2.query_int(kin.Q_BLOCK, mid) == blk
