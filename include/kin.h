@@ -44,7 +44,11 @@ typedef enum {
 } kin_status;
 
 typedef enum { KIN_FP64 = 0, KIN_FP32_LU = 1 } kin_precision;
-typedef enum { KIN_MEM_HOST = 0, KIN_MEM_DEVICE = 1 } kin_mem;
+/* Where caller buffers live.  KIN_MEM_HOST: pageable host memory, copied synchronously.
+ * KIN_MEM_DEVICE: device memory, copied in stream order.  KIN_MEM_PINNED: page-locked host
+ * memory (hipHostMalloc), copied in stream order without waiting; the caller keeps the buffer
+ * alive and unchanged until the stream has passed the copy. */
+typedef enum { KIN_MEM_HOST = 0, KIN_MEM_DEVICE = 1, KIN_MEM_PINNED = 2 } kin_mem;
 
 /* Kernel layouts: one cell per lane with the Newton matrix in registers, or one cell per
  * 64-wide wavefront with one matrix row per lane and the Jacobian staged in LDS. */
@@ -62,7 +66,11 @@ typedef struct kin_ctx kin_ctx;
 
 typedef struct {
     int32_t device;          /* HIP device ordinal */
-    uint64_t hbm_budget;     /* bytes of instance state the context may hold; 0 = no limit */
+    uint64_t hbm_budget;     /* bytes of instance state the context may hold; 0 = no limit.
+                              * A budget is reserved at creation as one device pool that
+                              * instances are carved from first-fit (no hipMalloc or hipFree
+                              * per instance); an upload that finds no free block of its
+                              * footprint fails with KIN_ENOMEM. */
     const char *tune_cache;  /* autotuner cache file (JSON); NULL = $KIN_TUNE_CACHE or none */
 } kin_ctx_opts;
 
@@ -166,6 +174,8 @@ kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched,
 /* Wait for `stream` (NULL = the null stream). */
 kin_status kin_sync(kin_ctx *ctx, void *stream);
 
+/* Free an instance.  Work already enqueued on it must have completed (with a budget pool the
+ * memory goes straight back to the pool, without a device synchronisation). */
 kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id);
 
 /* Device bytes an instance of n_cells cells of a mechanism occupies. */
@@ -178,7 +188,8 @@ typedef enum {
     KIN_Q_BLOCK = 2,          /* arg: mech id; out: int32 threads per block of that layout */
     KIN_Q_NUM_CU = 3,         /* out: int32 */
     KIN_Q_DEVICE_PTRS = 4,    /* arg: instance id; out: 7 x uint64 rho, e0, T, Y, status, level, iters */
-    KIN_Q_JIT_SECONDS = 5     /* arg: mech id; out: double compile time of its lane kernels */
+    KIN_Q_JIT_SECONDS = 5,    /* arg: mech id; out: double compile time of its lane kernels */
+    KIN_Q_LARGEST_FREE = 6    /* out: uint64 largest free block of the budget pool (0 without one) */
 } kin_query_what;
 
 kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);

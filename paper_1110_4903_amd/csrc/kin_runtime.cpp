@@ -84,9 +84,50 @@ struct kin_ctx {
     int ncounters = 0;
     std::map<std::string, kin::Plan> plans;
     kin_status plan_status = KIN_OK;
+    // with a budget: one device pool of that size, carved first-fit into instance arenas
+    char *pool = nullptr;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
 };
 
 using namespace kin;
+
+// ---- instance memory: a first-fit pool when the context has a budget, else hipMalloc ----
+static void *pool_alloc(kin_ctx *ctx, size_t bytes)
+{
+    for (auto it = ctx->free_blocks.begin(); it != ctx->free_blocks.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, left = it->second - bytes;
+        ctx->free_blocks.erase(it);
+        if (left) ctx->free_blocks[off + bytes] = left;
+        return ctx->pool + off;
+    }
+    return nullptr;
+}
+
+static void pool_free(kin_ctx *ctx, void *p, size_t bytes)
+{
+    size_t off = static_cast<char *>(p) - ctx->pool;
+    auto next = ctx->free_blocks.lower_bound(off);
+    if (next != ctx->free_blocks.end() && off + bytes == next->first) {
+        bytes += next->second;
+        next = ctx->free_blocks.erase(next);
+    }
+    if (next != ctx->free_blocks.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+            prev->second += bytes;
+            return;
+        }
+    }
+    ctx->free_blocks[off] = bytes;
+}
+
+static size_t pool_largest(const kin_ctx *ctx)
+{
+    size_t m = 0;
+    for (const auto &kv : ctx->free_blocks) m = std::max(m, kv.second);
+    return m;
+}
 
 #define KIN_HIP(ctx, call)                                                                   \
     do {                                                                                     \
@@ -148,6 +189,13 @@ kin_status kin_create(kin_ctx **out, const kin_ctx_opts *o)
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) return err(KIN_EDEVICE, hipGetErrorString(e));
     c->num_cu = prop.multiProcessorCount;
+    if (c->budget) {
+        c->budget &= ~(uint64_t)255;
+        if (c->budget == 0) return err(KIN_EINVAL, "budget below 256 bytes");
+        if ((e = hipMalloc(reinterpret_cast<void **>(&c->pool), c->budget)) != hipSuccess)
+            return err(KIN_ENOMEM, std::string("cannot reserve the budget: ") + hipGetErrorString(e));
+        c->free_blocks[0] = c->budget;
+    }
     *out = c.release();
     return KIN_OK;
 }
@@ -164,7 +212,9 @@ void kin_destroy(kin_ctx *ctx)
         for (hipEvent_t ev : ctx->join) hipEventDestroy(ev);
         if (ctx->fork) hipEventDestroy(ctx->fork);
         hipFree(ctx->counters);
-        for (auto &kv : ctx->insts) hipFree(kv.second->buf);
+        if (ctx->pool) hipFree(ctx->pool);
+        else
+            for (auto &kv : ctx->insts) hipFree(kv.second->buf);
         for (auto &kv : ctx->mechs) {
             if (kv.second->mod) hipModuleUnload(kv.second->mod);
             hipFree(kv.second->dbuf);
@@ -476,8 +526,16 @@ static kin_status copy_in(kin_ctx *ctx, void *dst, const void *src, size_t bytes
                           hipStream_t st)
 {
     if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    else if (where == KIN_MEM_PINNED) KIN_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
     else KIN_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
     return KIN_OK;
+}
+
+static bool mem_ok(kin_mem w) { return w == KIN_MEM_HOST || w == KIN_MEM_DEVICE || w == KIN_MEM_PINNED; }
+
+static hipMemcpyKind out_kind(kin_mem w)
+{
+    return w == KIN_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
 }
 
 static kin_status fill_state(kin_ctx *ctx, Inst &in, const Mech &m, const double *rho,
@@ -505,7 +563,7 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     kin_status s = enter(ctx);
     if (s != KIN_OK) return s;
     if (!inst_id || n_cells < 1 || !rho || !T || !Y) return err(KIN_EINVAL, "bad state arguments");
-    if (where != KIN_MEM_HOST && where != KIN_MEM_DEVICE) return err(KIN_EINVAL, "bad memory kind");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->mechs.find(mech_id);
     if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
@@ -518,7 +576,12 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     in->n = n_cells;
     in->ld = n_cells;
     in->bytes = bytes;
-    KIN_HIP(ctx, hipMalloc(&in->buf, bytes));
+    if (ctx->pool) {
+        if (!(in->buf = pool_alloc(ctx, bytes)))
+            return err(KIN_ENOMEM, "no free block of " + std::to_string(bytes) + " bytes in the budget");
+    } else {
+        KIN_HIP(ctx, hipMalloc(&in->buf, bytes));
+    }
     char *b = static_cast<char *>(in->buf);
     const Arena ar = arena_at(b, n_cells, m.h.ns);
     const size_t i = align256(sizeof(int) * (size_t)n_cells);
@@ -526,7 +589,8 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     in->status = ar.status; in->level = ar.level; in->iters = ar.iters; in->counter = ar.counter;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((s = fill_state(ctx, *in, m, rho, T, Y, e0, where, st)) != KIN_OK) {
-        hipFree(in->buf);
+        if (ctx->pool) pool_free(ctx, in->buf, bytes);
+        else hipFree(in->buf);
         return s;
     }
     KIN_HIP(ctx, hipMemsetAsync(in->status, 0, 3 * i, st));
@@ -545,6 +609,7 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
     kin_status s = enter(ctx);
     if (s != KIN_OK) return s;
     if (!rho || !T || !Y) return err(KIN_EINVAL, "NULL state array");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->insts.find(inst_id);
     if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
@@ -774,8 +839,9 @@ kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, dou
     if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
     const Inst &in = *it->second;
     const int ns = ctx->mechs[in.mech]->h.ns;
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const hipMemcpyKind kind = where == KIN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind kind = out_kind(where);
     const size_t nd = sizeof(double) * (size_t)in.n, ni = sizeof(int) * (size_t)in.n;
     if (T) KIN_HIP(ctx, hipMemcpyAsync(T, in.T, nd, kind, st));
     if (Y) KIN_HIP(ctx, hipMemcpyAsync(Y, in.Y, nd * ns, kind, st));
@@ -797,9 +863,9 @@ kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched,
     auto it = ctx->insts.find(inst_id);
     if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
     const Inst &in = *it->second;
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    KIN_HIP(ctx, hipMemcpyAsync(sched, in.sched, sizeof(uint64_t) * (size_t)in.n,
-                                where == KIN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    KIN_HIP(ctx, hipMemcpyAsync(sched, in.sched, sizeof(uint64_t) * (size_t)in.n, out_kind(where), st));
     if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
     return KIN_OK;
 }
@@ -827,7 +893,8 @@ kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id)
             ++pit;
         }
     }
-    KIN_HIP(ctx, hipFree(it->second->buf));
+    if (ctx->pool) pool_free(ctx, it->second->buf, it->second->bytes);
+    else KIN_HIP(ctx, hipFree(it->second->buf));
     ctx->in_use -= it->second->bytes;
     ctx->mechs[it->second->mech]->refs--;
     ctx->insts.erase(it);
@@ -853,6 +920,9 @@ kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out)
         return KIN_OK;
     case KIN_Q_NUM_CU:
         *static_cast<int32_t *>(out) = ctx->num_cu;
+        return KIN_OK;
+    case KIN_Q_LARGEST_FREE:
+        *static_cast<uint64_t *>(out) = ctx->pool ? pool_largest(ctx) : 0;
         return KIN_OK;
     case KIN_Q_LAYOUT:
     case KIN_Q_BLOCK:

@@ -2,7 +2,8 @@
 kinetics update runs in the library's HIP kernels.
 
 Device arrays may be passed as torch tensors (their data_ptr() is handed over with
-KIN_MEM_DEVICE and the current torch stream); host arrays as numpy arrays.  Importing this
+KIN_MEM_DEVICE, pinned CPU tensors with KIN_MEM_PINNED), host arrays as numpy arrays; stream
+arguments take a torch.cuda.Stream or a raw handle.  Importing this
 module loads the shared library and raises ImportError if it has not been built.
 """
 from __future__ import annotations
@@ -18,10 +19,10 @@ SO = os.path.join(HERE, "libkin.so")
 
 OK, EINVAL, ENOMEM, EBUSY, ENOTFOUND, EDEVICE, ECOMPILE = range(7)
 FP64, FP32_LU = 0, 1
-MEM_HOST, MEM_DEVICE = 0, 1
+MEM_HOST, MEM_DEVICE, MEM_PINNED = 0, 1, 2
 LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_WAVE = 0, 1, 2
 CELL_OK, CELL_OK_HALVED, CELL_FAILED, CELL_BAD_INPUT = 0, 1, 2, 3
-Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS = range(6)
+Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS, Q_LARGEST_FREE = range(7)
 
 EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destroy",
            "kin_mech_upload", "kin_mech_release", "kin_state_upload", "kin_state_reset",
@@ -126,7 +127,7 @@ def jit_check(mech) -> str:
 
 
 def _ptr(x):
-    """(address, memory kind) of a numpy array (host) or torch tensor (device)."""
+    """(address, memory kind) of a numpy array (host) or torch tensor (device, or pinned host)."""
     if x is None:
         return None, None
     if isinstance(x, np.ndarray):
@@ -136,7 +137,9 @@ def _ptr(x):
     if hasattr(x, "data_ptr"):
         if not x.is_contiguous():
             raise ValueError("device tensors must be contiguous")
-        return x.data_ptr(), (MEM_DEVICE if x.is_cuda else MEM_HOST)
+        if x.is_cuda:
+            return x.data_ptr(), MEM_DEVICE
+        return x.data_ptr(), (MEM_PINNED if x.is_pinned() else MEM_HOST)
     raise TypeError(f"unsupported array type {type(x)}")
 
 
@@ -253,9 +256,14 @@ class Context:
 
     def download_device(self, inst_id: int, T, Y, e0=None, status=None, level=None, iters=None,
                         stream=None):
-        """Device-to-device copy of an instance's state into torch tensors."""
+        """Stream-ordered copy of an instance's state into torch tensors, all on the device or
+        all in pinned host memory; nothing waits for it."""
+        arrs = [a for a in (T, Y, e0, status, level, iters) if a is not None]
+        kinds = {_ptr(a)[1] for a in arrs}
+        if len(kinds) != 1 or kinds == {MEM_HOST}:
+            raise ValueError("destinations must all be device tensors or all pinned host tensors")
         ptrs = [(_ptr(a)[0] if a is not None else None) for a in (T, Y, e0, status, level, iters)]
-        _check(_lib.kin_download(self._h, inst_id, *ptrs, MEM_DEVICE, _stream_handle(stream)))
+        _check(_lib.kin_download(self._h, inst_id, *ptrs, kinds.pop(), _stream_handle(stream)))
 
     def sync(self, stream=None):
         _check(_lib.kin_sync(self._h, _stream_handle(stream)))
@@ -273,6 +281,11 @@ class Context:
     def query_int(self, what: int, arg: int = 0) -> int:
         v = C.c_int32()
         _check(_lib.kin_query(self._h, what, arg, C.byref(v)))
+        return v.value
+
+    def largest_free(self) -> int:
+        v = C.c_uint64()
+        _check(_lib.kin_query(self._h, Q_LARGEST_FREE, 0, C.byref(v)))
         return v.value
 
     def bytes_in_use(self) -> int:

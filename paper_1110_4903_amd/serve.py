@@ -1,0 +1,211 @@
+"""Serving loop: continuous batching of chemistry solves of uneven size on one GPU.
+
+Requests (a mechanism, a cell count, a dt and the cells' state in host memory) arrive over
+time.  The loop keeps every mechanism resident on the device, queues arrivals in order and
+admits the queue's head as soon as a slot is free and its HBM footprint fits the budget
+(strict first-come-first-served, so no request waits behind a later one).  An admitted request
+is uploaded, advanced and downloaded in stream order on its slot's stream, so the work of
+requests admitted while others run overlaps on the device.  Its latency runs from arrival to
+the moment the loop sees its results in host memory.
+
+The loop itself knows nothing of HIP: a backend starts, polls and finishes requests, and a
+clock gives the time.  KinBackend drives libkin; the tests also drive the loop with a
+simulated backend and clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Job:
+    rid: int
+    arrival: float      # s since the start of the run
+    mech: str
+    n_cells: int
+    dt: float
+    state: object = None  # backend-specific inputs
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    mech: str
+    n_cells: int
+    arrival: float
+    admitted: float
+    done: float
+    result: object = None
+    rejected: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class Report:
+    records: List[Record]
+    max_bytes_in_use: int
+    max_in_flight: int
+    start_order: List[int]
+    wall_s: float
+
+    def summary(self) -> dict:
+        ok = [r for r in self.records if not r.rejected]
+        lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+        cells = sum(r.n_cells for r in ok)
+        first = min((r.arrival for r in ok), default=0.0)
+        last = max((r.done for r in ok), default=0.0)
+        span = max(last - first, 1e-12)
+        return dict(requests=len(ok), rejected=len(self.records) - len(ok), cells=cells,
+                    cells_per_s=cells / span, p50_ms=1e3 * percentile(lat, 50),
+                    p99_ms=1e3 * percentile(lat, 99), mean_ms=1e3 * float(lat.mean()),
+                    max_in_flight=self.max_in_flight, max_bytes_in_use=self.max_bytes_in_use,
+                    span_s=span)
+
+
+def percentile(x, q) -> float:
+    """Nearest-rank percentile (the smallest sample with at least q% of samples at or below)."""
+    s = np.sort(np.asarray(x, dtype=float))
+    if s.size == 0:
+        return float("nan")
+    k = max(int(np.ceil(q / 100.0 * s.size)) - 1, 0)
+    return float(s[k])
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def idle(self, next_arrival: Optional[float], backend) -> None:
+        # nothing to do this round: yield briefly, but never sleep past the next arrival
+        d = 50e-6 if next_arrival is None else min(50e-6, max(next_arrival - self.now(), 0.0))
+        if d > 0:
+            time.sleep(d)
+
+
+def run(jobs: List[Job], backend, budget: int, n_slots: int, clock=None) -> Report:
+    """Serve `jobs` (sorted by arrival).  backend: footprint(job) -> bytes,
+    start(job, slot) -> bool (False: no room on the device now, retry later), done(slot) ->
+    bool, finish(slot) -> result.  A job whose footprint exceeds the whole budget is rejected."""
+    clock = clock or WallClock()
+    pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
+    queue: collections.deque = collections.deque()
+    free = list(range(n_slots - 1, -1, -1))
+    inflight: Dict[int, tuple] = {}
+    used = 0
+    records: List[Record] = []
+    order: List[int] = []
+    max_used = max_fl = 0
+    t_start = clock.now()
+    while pending or queue or inflight:
+        now = clock.now()
+        while pending and pending[0].arrival <= now:
+            queue.append(pending.popleft())
+        progressed = False
+        for slot in list(inflight):
+            if backend.done(slot):
+                job, fp, t_adm = inflight.pop(slot)
+                res = backend.finish(slot)
+                records.append(Record(job.rid, job.mech, job.n_cells, job.arrival, t_adm, clock.now(), res))
+                used -= fp
+                free.append(slot)
+                progressed = True
+        while queue and free:
+            job = queue[0]
+            fp = backend.footprint(job)
+            if fp > budget:
+                queue.popleft()
+                t = clock.now()
+                records.append(Record(job.rid, job.mech, job.n_cells, job.arrival, t, t, None, rejected=True))
+                progressed = True
+                continue
+            if used + fp > budget:
+                break
+            slot = free.pop()
+            if not backend.start(job, slot):
+                free.append(slot)
+                if not inflight:
+                    raise RuntimeError(f"request {job.rid} fits the budget but the device has no room "
+                                       "for it with nothing in flight")
+                break
+            queue.popleft()
+            used += fp
+            inflight[slot] = (job, fp, clock.now())
+            order.append(job.rid)
+            max_used = max(max_used, used)
+            max_fl = max(max_fl, len(inflight))
+            progressed = True
+        if not progressed:
+            clock.idle(pending[0].arrival if pending else None, backend)
+    return Report(records, max_used, max_fl, order, clock.now() - t_start)
+
+
+class KinBackend:
+    """Requests through libkin: one stream per slot; upload from pinned host memory, advance
+    and download in stream order; completion seen through an event on the slot's stream."""
+
+    def __init__(self, ctx, mech_ids: Dict[str, int], prec: int, n_slots: int, opts=None):
+        import torch
+        self.torch = torch
+        self.ctx, self.mids, self.prec, self.opts = ctx, mech_ids, prec, opts
+        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self.events = [torch.cuda.Event() for _ in range(n_slots)]
+        self.slot: Dict[int, tuple] = {}
+        self._ns = {name: ctx.mech_ns[mid] for name, mid in mech_ids.items()}
+        self._fp: Dict[tuple, int] = {}
+
+    def prepare(self, job: Job, st) -> None:
+        """Pinned host copies of a request's inputs and room for its outputs."""
+        torch = self.torch
+        pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+        ns = self._ns[job.mech]
+        job.state = dict(rho=pin(st.rho), T=pin(st.T), Y=pin(st.Y),
+                         T_out=torch.empty(job.n_cells, dtype=torch.float64, pin_memory=True),
+                         Y_out=torch.empty((ns, job.n_cells), dtype=torch.float64, pin_memory=True),
+                         status=torch.empty(job.n_cells, dtype=torch.int32, pin_memory=True))
+
+    def footprint(self, job: Job) -> int:
+        key = (job.mech, job.n_cells)
+        if key not in self._fp:
+            self._fp[key] = self.ctx.footprint(self.mids[job.mech], job.n_cells, self.prec)
+        return self._fp[key]
+
+    def start(self, job: Job, slot: int) -> bool:
+        from . import kin
+        s = self.streams[slot]
+        d = job.state
+        try:
+            iid = self.ctx.state_upload(self.mids[job.mech], d["rho"], d["T"], d["Y"], stream=s)
+        except kin.KinError as e:
+            if e.status == kin.ENOMEM:
+                return False
+            raise
+        self.ctx.advance([iid], [job.dt], prec=self.prec, opts=self.opts, stream=s)
+        self.ctx.download_device(iid, d["T_out"], d["Y_out"], status=d["status"], stream=s)
+        self.events[slot].record(s)
+        self.slot[slot] = (job, iid)
+        return True
+
+    def done(self, slot: int) -> bool:
+        return self.events[slot].query()
+
+    def finish(self, slot: int):
+        job, iid = self.slot.pop(slot)
+        self.ctx.instance_release(iid)
+        d = job.state
+        return d["T_out"].numpy(), d["Y_out"].numpy(), d["status"].numpy()
+
+
+def make_jobs(requests, time_scale: float = 1.0) -> List[Job]:
+    """Jobs from synth.Request records (arrival times multiplied by time_scale)."""
+    return [Job(k, r.arrival * time_scale, r.inst.mech, r.inst.n_cells, r.inst.dt) for k, r in enumerate(requests)]
