@@ -80,22 +80,35 @@ struct RxnRec {
 };
 static_assert(sizeof(RxnRec) == 32, "reaction record must stay 32 bytes");
 
+// Per-reaction coefficients of the Jacobian scatter, one slot per participant j: the row factor
+// nu_rj M_j (zero when the net coefficient is zero) and the column factor 1 / M_j.
+struct RxnCoef {
+    double rowc[6];
+    double colc[6];
+};
+
+// Third-body reaction (one slot per such reaction): the rows it writes (participants with a nonzero
+// net coefficient) and their factors nu_rs M_s.
+struct TbRec {
+    int8_t nrow;
+    int8_t row[7];
+    double coef[6];
+    double pad;
+};
+static_assert(sizeof(TbRec) == 64, "third-body record must stay 64 bytes");
+
 struct WaveTables {
-    int ns, nr, ntb, nchunk;
+    int ns, nr, ntb, nchunk;  // ntb: third-body reactions (each has a slot; RxnRec::tb is the slot)
     double lnPaR;           // ln(P_atm / R) in CGS units
     const double *nasa;     // [ns][14]
     const double *Tmid;     // [ns]
     const double *M;        // [ns] g/mol
     const double *rxd;      // [nr][4]: ln A, b, Ta, sum nu
     const RxnRec *rxc;      // [nr]
-    const double *effT;     // [ns][ntb] third-body efficiencies, transposed
-    const double *effM;     // [ntb][ns] efficiency / molar mass (eff_rk / M_k)
-    const int *tb_ptr;      // [nchunk + 1] third-body reactions of each chunk ...
-    const int *tb_list;     //   ... as reaction indices
-    const int *sp_ptr;      // [ns][nchunk + 1] per species and chunk: reactions with a nonzero
-    const int *sp_list;     //   net coefficient, rl * 16 + (nu + 8), rl local to the chunk
-    const int *ent_ptr;     // [ns][nchunk + 1] per species row and chunk: sparse Jacobian
-    const int *ent_list;    //   entries rl | slot << 6 | k << 9 | (nu + 8) << 15
+    const RxnCoef *rxk;     // [nr]
+    const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
+    const double *effM;     // [ntb][ns] efficiency / molar mass (eff_rk / M_k) per slot
+    const TbRec *tbr;       // [ntb] per slot
 };
 
 // Device layout of one instance's arena (n cells, ns species), from its base address:

@@ -265,8 +265,16 @@ static kin_status build_lane(kin_ctx *ctx, Mech &m, int block)
 static kin_status upload_tables(kin_ctx *ctx, Mech &m)
 {
     const MechHost &h = m.h;
-    const int ns = h.ns, nr = h.nr, ntb = h.ntb;
+    const int ns = h.ns, nr = h.nr;
     const int nchunk = (nr + kChunk - 1) / kChunk;
+    // third-body reactions get slots of their own (two reactions may share an efficiency row)
+    std::vector<int> slot(nr, -1), slot_row;
+    for (int r = 0; r < nr; ++r)
+        if (h.rx[r].tb >= 0) {
+            slot[r] = (int)slot_row.size();
+            slot_row.push_back(h.rx[r].tb);
+        }
+    const int ntb = (int)slot_row.size();
     std::vector<double> rxd((size_t)nr * 4);
     std::vector<RxnRec> rxc(nr);
     for (int r = 0; r < nr; ++r) {
@@ -278,7 +286,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         RxnRec &p = rxc[r];
         std::memset(&p, 0, sizeof p);
         p.rev = (int8_t)x.rev; p.nreac = (int8_t)x.nreac; p.nprod = (int8_t)x.nprod;
-        p.npart = (int8_t)x.npart; p.tb = (int16_t)x.tb;
+        p.npart = (int8_t)x.npart; p.tb = (int16_t)slot[r];
         for (int j = 0; j < 3; ++j) {
             p.reac_sp[j] = (int8_t)(j < x.nreac ? x.reac_sp[j] : 0);
             p.reac_nu[j] = (int8_t)(j < x.nreac ? x.reac_nu[j] : 0);
@@ -290,52 +298,41 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             p.part_nu[j] = (int8_t)(j < x.npart ? x.part[j].nu : 0);
         }
     }
-    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effM((size_t)std::max(1, ntb * ns), 0.0);
-    for (int r = 0; r < ntb; ++r)
-        for (int k = 0; k < ns; ++k) {
-            effT[(size_t)k * ntb + r] = h.eff[(size_t)r * ns + k];
-            effM[(size_t)r * ns + k] = h.eff[(size_t)r * ns + k] / h.M[k];
+    std::vector<RxnCoef> rxk(nr);
+    std::vector<TbRec> tbr((size_t)std::max(1, ntb));
+    std::memset(tbr.data(), 0, sizeof(TbRec) * tbr.size());
+    for (int r = 0; r < nr; ++r) {
+        const Rxn &x = h.rx[r];
+        RxnCoef &k = rxk[r];
+        for (int j = 0; j < 6; ++j) {
+            k.rowc[j] = j < x.npart ? (double)x.part[j].nu * h.M[x.part[j].sp] : 0.0;
+            k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
         }
-    std::vector<int> tb_ptr(nchunk + 1), tb_list;
-    for (int cb = 0; cb < nchunk; ++cb) {
-        tb_ptr[cb] = (int)tb_list.size();
-        for (int r = cb * kChunk; r < std::min(nr, (cb + 1) * kChunk); ++r)
-            if (h.rx[r].tb >= 0) tb_list.push_back(r);
-    }
-    tb_ptr[nchunk] = (int)tb_list.size();
-    // per species row and chunk: reactions with nonzero net coefficient, and sparse entries
-    std::vector<int> sp_ptr((size_t)ns * (nchunk + 1)), sp_list, ent_ptr((size_t)ns * (nchunk + 1)), ent_list;
-    for (int s = 0; s < ns; ++s) {
-        for (int cb = 0; cb < nchunk; ++cb) {
-            sp_ptr[(size_t)s * (nchunk + 1) + cb] = (int)sp_list.size();
-            ent_ptr[(size_t)s * (nchunk + 1) + cb] = (int)ent_list.size();
-            for (int r = cb * kChunk; r < std::min(nr, (cb + 1) * kChunk); ++r) {
-                const Rxn &x = h.rx[r];
-                const int rl = r - cb * kChunk;
-                int nu = 0;
-                for (int j = 0; j < x.npart; ++j) if (x.part[j].sp == s) nu = x.part[j].nu;
-                if (!nu) continue;
-                sp_list.push_back(rl * 16 + (nu + 8));
-                for (int j = 0; j < x.npart; ++j)
-                    ent_list.push_back(rl | (j << 6) | (x.part[j].sp << 9) | ((nu + 8) << 15));
+        if (slot[r] >= 0) {
+            TbRec &t = tbr[slot[r]];
+            for (int j = 0; j < x.npart; ++j) {
+                if (!x.part[j].nu) continue;
+                t.row[t.nrow] = (int8_t)x.part[j].sp;
+                t.coef[t.nrow] = (double)x.part[j].nu * h.M[x.part[j].sp];
+                ++t.nrow;
             }
         }
-        sp_ptr[(size_t)s * (nchunk + 1) + nchunk] = (int)sp_list.size();
-        ent_ptr[(size_t)s * (nchunk + 1) + nchunk] = (int)ent_list.size();
     }
-    if (sp_list.empty()) sp_list.push_back(0);
-    if (ent_list.empty()) ent_list.push_back(0);
-    if (tb_list.empty()) tb_list.push_back(0);
+    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effM((size_t)std::max(1, ntb * ns), 0.0);
+    for (int q = 0; q < ntb; ++q)
+        for (int k = 0; k < ns; ++k) {
+            const double e = h.eff[(size_t)slot_row[q] * ns + k];
+            effT[(size_t)k * ntb + q] = e;
+            effM[(size_t)q * ns + k] = e / h.M[k];
+        }
     // one allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pc = {
         {h.nasa.data(), sizeof(double) * h.nasa.size(), 0}, {h.Tmid.data(), sizeof(double) * ns, 0},
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
-        {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {effT.data(), sizeof(double) * effT.size(), 0},
-        {effM.data(), sizeof(double) * effM.size(), 0}, {tb_ptr.data(), sizeof(int) * tb_ptr.size(), 0},
-        {tb_list.data(), sizeof(int) * tb_list.size(), 0}, {sp_ptr.data(), sizeof(int) * sp_ptr.size(), 0},
-        {sp_list.data(), sizeof(int) * sp_list.size(), 0}, {ent_ptr.data(), sizeof(int) * ent_ptr.size(), 0},
-        {ent_list.data(), sizeof(int) * ent_list.size(), 0}};
+        {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
+        {effT.data(), sizeof(double) * effT.size(), 0}, {effM.data(), sizeof(double) * effM.size(), 0},
+        {tbr.data(), sizeof(TbRec) * tbr.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -352,14 +349,10 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.M = reinterpret_cast<const double *>(b + pc[2].off);
     t.rxd = reinterpret_cast<const double *>(b + pc[3].off);
     t.rxc = reinterpret_cast<const RxnRec *>(b + pc[4].off);
-    t.effT = reinterpret_cast<const double *>(b + pc[5].off);
-    t.effM = reinterpret_cast<const double *>(b + pc[6].off);
-    t.tb_ptr = reinterpret_cast<const int *>(b + pc[7].off);
-    t.tb_list = reinterpret_cast<const int *>(b + pc[8].off);
-    t.sp_ptr = reinterpret_cast<const int *>(b + pc[9].off);
-    t.sp_list = reinterpret_cast<const int *>(b + pc[10].off);
-    t.ent_ptr = reinterpret_cast<const int *>(b + pc[11].off);
-    t.ent_list = reinterpret_cast<const int *>(b + pc[12].off);
+    t.rxk = reinterpret_cast<const RxnCoef *>(b + pc[5].off);
+    t.effT = reinterpret_cast<const double *>(b + pc[6].off);
+    t.effM = reinterpret_cast<const double *>(b + pc[7].off);
+    t.tbr = reinterpret_cast<const TbRec *>(b + pc[8].off);
     return KIN_OK;
 }
 
@@ -461,7 +454,7 @@ kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_i
         }
     } else {
         m->layout = KIN_LAYOUT_WAVE;
-        m->block = 2;
+        m->block = 1;
     }
     {   // a tuned choice (FP64 entry) from the cache file, if any
         const auto cache = tune_read(ctx->tune_cache);
@@ -514,6 +507,8 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
         if ((s = build_lane(ctx, m, block)) != KIN_OK) return s;
     } else if (layout == KIN_LAYOUT_WAVE) {
         if (block < 1 || block > 4) return err(KIN_EINVAL, "wave layout takes 1..4 wavefronts per block");
+        if (wave_lds_bytes(m.tab, false) * (size_t)block > 65536)
+            return err(KIN_EINVAL, "that many wavefronts per block exceed 64 KiB of LDS for this mechanism");
     } else {
         return err(KIN_EINVAL, "layout must be LANE or WAVE");
     }
@@ -629,7 +624,7 @@ static void layout_of(const Mech &m, const kin_solver_opts &o, int &layout, int 
 {
     layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
     if (layout == KIN_LAYOUT_LANE) block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
-    else block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 2;
+    else block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 1;
 }
 
 // Launch one kernel over the spans in a (all of mechanism m) on stream st.  The work counter
@@ -966,7 +961,8 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     std::vector<std::pair<int, int>> cand;
     if (m.h.ns <= kLaneNsMax)
         for (int b : {64, 128, 256}) cand.push_back({KIN_LAYOUT_LANE, b});
-    for (int b : {1, 2, 4}) cand.push_back({KIN_LAYOUT_WAVE, b});
+    for (int b : {1, 2, 4})
+        if (wave_lds_bytes(m.tab, false) * (size_t)b <= 65536) cand.push_back({KIN_LAYOUT_WAVE, b});
     void *save = nullptr;
     KIN_HIP(ctx, hipMalloc(&save, in.bytes));
     KIN_HIP(ctx, hipMemcpy(save, in.buf, in.bytes, hipMemcpyDeviceToDevice));

@@ -6,11 +6,18 @@
 // (I - h dOmega/dQ) dQ = -G (Sec. 3.2, Eq. "kinetics") iterated as Newton's method on
 // backward Euler; Gaussian elimination with partial pivoting per cell (Sec. 4.2).  The paper
 // stored a cell's Jacobian either in global memory or in one thread block's shared memory;
-// here a cell owns one wavefront: lanes evaluate reactions 64 at a time, species rows are
-// accumulated in LDS, and each lane then holds one matrix row in registers for the
-// elimination, with the pivot row broadcast through LDS and the pivot search done by a
-// butterfly of cross-lane shuffles.  Wavefronts of a block never synchronise with each
-// other, so cells with different iteration counts do not wait for one another.
+// here a cell owns one wavefront:
+//   * lanes evaluate reactions 64 at a time and add each reaction's terms straight into the
+//     cell's Jacobian in LDS with LDS atomic adds (no per-row gather lists); the dense
+//     third-body terms go in afterwards one Jacobian column per lane;
+//   * each lane then holds one row of the Newton matrix in registers; the elimination runs as
+//     a loop over blocks of four pivot steps (the row is rotated by four registers after each
+//     block, so every step addresses its pivot column at a compile-time register), the pivot
+//     search is a DPP butterfly inside 16-lane rows plus a read of the four row winners, and
+//     each pivot row is stored once, packed, in LDS, where it serves both the elimination and
+//     the back substitution.
+// Wavefronts never synchronise with each other, so cells with different iteration counts do
+// not wait for one another.
 #include <hip/hip_runtime.h>
 
 #include "kin_internal.h"
@@ -29,16 +36,86 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// ---- cross-lane helpers (all lanes of the wavefront must be active) ------------------------
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kW);
-    return v;
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ double bcast(double v, int lane)
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
 {
-    return __shfl(v, lane, kW);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp<CTRL>((int)b), hi = dpp<CTRL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_bit_cast(float, dpp<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ double rdlane(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float rdlane(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror: after the four
+// steps every lane of a 16-lane row has combined all sixteen of the row's values.
+constexpr int kDppX1 = 0xB1, kDppX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+// Wave-wide sum; every lane returns the same value.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp<kDppX1>(v);
+    v += dpp<kDppX2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppMirror>(v);
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+
+// Pivot choice: the largest v, ties to the lowest position p.  The order is total, so any
+// combining tree gives the same winner.
+template <typename R>
+__device__ __forceinline__ void piv_take(R &v, int &p, R ov, int op)
+{
+    const bool take = (ov > v) || (ov == v && op < p);
+    v = take ? ov : v;
+    p = take ? op : p;
+}
+
+template <int CTRL, typename R>
+__device__ __forceinline__ void piv_step(R &v, int &p)
+{
+    piv_take(v, p, dpp<CTRL>(v), dpp<CTRL>(p));
+}
+
+// On return every lane holds the wave-wide winner (v, p).
+template <typename R>
+__device__ __forceinline__ void wave_argmax(R &v, int &p)
+{
+    piv_step<kDppX1>(v, p);
+    piv_step<kDppX2>(v, p);
+    piv_step<kDppHalfMirror>(v, p);
+    piv_step<kDppMirror>(v, p);
+    R bv = rdlane(v, 0);
+    int bp = rdlane(p, 0);
+    piv_take(bv, bp, rdlane(v, 16), rdlane(p, 16));
+    piv_take(bv, bp, rdlane(v, 32), rdlane(p, 32));
+    piv_take(bv, bp, rdlane(v, 48), rdlane(p, 48));
+    v = bv;
+    p = bp;
 }
 
 // NASA-7 functions of species s at T from the table.
@@ -57,46 +134,61 @@ __device__ __forceinline__ Thermo thermo(const WaveTables &t, int s, double T, d
     return o;
 }
 
-// Per-wave LDS layout (in doubles).  JS = NPAD + 1 (row stride of the Jacobian).
-struct Lds {
-    double *J;     // [N][JS]
-    double *c;     // [NPAD] concentrations
-    double *g;     // [NPAD] g/RT
-    double *h;     // [NPAD] h/RT
-    double *ek;    // [NPAD] e_s (J/kg)
-    double *cvk;   // [NPAD] cv_s (J/kg/K)
-    double *f;     // [NPAD] right-hand side
-    double *sol;   // [NPAD] solution exchange
-    double *invM;  // [NPAD]
-    double *cq;    // [9][kChunk] chunk buffer: q, dqT, D, dq[6]
-    double *Mc;    // [ntb] third-body concentrations
-    double *prow;  // [NPAD + 2] pivot row (FP64 or FP32 view)
-};
+// ---- per-wavefront LDS layout (in doubles) --------------------------------------------------
+// [0, R)            J[N][NPAD] during the evaluation (columns N.. stay zero); packed U rows
+//                   during the solve
+// W[NPAD]           net production sums, then f; the eliminated right-hand side in the solve
+// WT[NPAD]          d(net production)/dT sums
+// c[NPAD]           concentrations
+// g[NPAD], hh[NPAD] g/RT and h/RT for the rates, then e_s and cv_s for the energy row
+// Mc[ntbp], DTB[ntbp]  third-body concentrations and the third-body reactions' q_f - q_b
+__host__ __device__ inline int round_even(int x) { return (x + 1) & ~1; }
 
-template <int NPAD>
-__host__ __device__ __forceinline__ size_t lds_doubles(int N, int ntb)
+// Packed U rows hold 16-byte units; row k starts at the sum of the rounded lengths of the rows
+// before it, and its store may run NPAD elements past its start (the tail is overwritten by
+// later rows or falls into the slack).
+__host__ __device__ inline int u_row_len(int N, int k, int elems16) { return ((N - k) + elems16 - 1) / elems16 * elems16; }
+
+__host__ __device__ inline int u_extent_doubles(int N, int npad)
 {
-    return (size_t)N * (NPAD + 1) + 8 * NPAD + 9 * kChunk + (size_t)((ntb + 1) & ~1) + NPAD + 2;
+    int off = 0;
+    for (int k = 0; k + 1 < N; ++k) off += u_row_len(N, k, 2);
+    return off + npad + 2;
 }
 
-template <int NPAD>
-__device__ __forceinline__ Lds lds_map(double *base, int N, int ntb)
+__host__ __device__ inline int j_region(int N, int npad)
+{
+    const int a = N * npad, b = u_extent_doubles(N, npad);
+    return round_even(a > b ? a : b);
+}
+
+__host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
+{
+    return (size_t)j_region(N, npad) + 5 * (size_t)npad + 2 * (size_t)round_even(ntb);
+}
+
+struct Lds {
+    double *J, *W, *WT, *c, *g, *hh, *Mc, *DTB;
+};
+
+__device__ __forceinline__ Lds lds_map(double *base, int N, int ntb, int npad)
 {
     Lds L;
     double *p = base;
-    L.J = p; p += (size_t)N * (NPAD + 1);
-    L.c = p; p += NPAD;
-    L.g = p; p += NPAD;
-    L.h = p; p += NPAD;
-    L.ek = p; p += NPAD;
-    L.cvk = p; p += NPAD;
-    L.f = p; p += NPAD;
-    L.sol = p; p += NPAD;
-    L.invM = p; p += NPAD;
-    L.cq = p; p += 9 * kChunk;
-    L.Mc = p; p += (ntb + 1) & ~1;
-    L.prow = p;
+    L.J = p; p += j_region(N, npad);
+    L.W = p; p += npad;
+    L.WT = p; p += npad;
+    L.c = p; p += npad;
+    L.g = p; p += npad;
+    L.hh = p; p += npad;
+    L.Mc = p; p += round_even(ntb);
+    L.DTB = p;
     return L;
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // Mixture e and c_v at T (wave-wide sums).  Every lane returns the same values.
@@ -142,160 +234,169 @@ __device__ __forceinline__ bool invert_T(const WaveTables &t, int lane, double x
     return true;
 }
 
+// c^nu for nu in 0..3
 __device__ __forceinline__ double cpow_nu(double c, int nu)
 {
-    return (nu == 1) ? c : (nu == 2 ? c * c : c * c * c);
+    const double c2 = c * c;
+    return nu == 0 ? 1.0 : (nu == 1 ? c : (nu == 2 ? c2 : c2 * c));
 }
 
-// f = dx/dt and J = df/dx of the cell at x (lane i holds x_i).  Leaves J in L.J (rows
-// 0..N-1) and f in L.f.
-//
-// Per pass of 64 reactions (one per lane) the rates, net progress, its T-derivative and its
-// derivatives with respect to the participating concentrations go to the chunk buffer; then
-// lane s, owner of Jacobian row s, gathers the chunk's contributions to its row from a
-// precomputed list of (reaction, participant, column, coefficient) entries, and lane k adds
-// column k of the dense third-body terms nu_rs (M_s / M_k) eff_rk (q_f - q_b).
-template <int NPAD>
-__device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane, double rho, double xs)
+// d(c^nu)/dc = nu c^(nu-1)
+__device__ __forceinline__ double dcpow_nu(double c, int nu)
 {
-    const int ns = t.ns, N = ns + 1, JS = NPAD + 1;
-    const double T = bcast(xs, ns);
+    return nu == 0 ? 0.0 : (nu == 1 ? 1.0 : (nu == 2 ? 2.0 * c : 3.0 * c * c));
+}
+
+// Rates and Jacobian terms of reaction r (lane-owned), added into W, WT and J.
+//   Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''),  dQ_r/dc_k over the participants,
+//   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  WT[s] += nu_rs dQ_r/dT.
+template <int NPAD>
+__device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, double iT,
+                                               double lT, double lPaRT)
+{
+    const RxnRec x = t.rxc[r];
+    const double *rd = t.rxd + (size_t)r * 4;
+    const double lnA = rd[0], b = rd[1], Ta = rd[2], dnu = rd[3];
+    const RxnCoef *kc = t.rxk + r;
+    const double lkf = fma(-Ta, iT, fma(b, lT, lnA));
+    const double kf = exp(lkf);
+    const double dlkf = fma(Ta, iT, b) * iT;
+    double cr[3], pr[3], dr[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int nu = m < x.nreac ? x.reac_nu[m] : 0;
+        cr[m] = L.c[x.reac_sp[m]];
+        pr[m] = cpow_nu(cr[m], nu);
+        dr[m] = dcpow_nu(cr[m], nu);
+    }
+    const double pf = kf * (pr[0] * pr[1] * pr[2]);
+    double dpf[3];
+    dpf[0] = kf * (dr[0] * pr[1] * pr[2]);
+    dpf[1] = kf * (pr[0] * dr[1] * pr[2]);
+    dpf[2] = kf * (pr[0] * pr[1] * dr[2]);
+    double pb = 0.0, dlKc = 0.0, dpb[3] = {0.0, 0.0, 0.0};
+    if (x.rev) {
+        double sg = 0.0, sh = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (j < x.npart) {
+                const double nu = (double)x.part_nu[j];
+                sg = fma(nu, L.g[x.part_sp[j]], sg);
+                sh = fma(nu, L.hh[x.part_sp[j]], sh);
+            }
+        }
+        const double lKc = dnu * lPaRT - sg;
+        const double kb = exp(lkf - lKc);
+        dlKc = (sh - dnu) * iT;
+        double cp[3], pp[3], dp[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int nu = m < x.nprod ? x.prod_nu[m] : 0;
+            cp[m] = L.c[x.prod_sp[m]];
+            pp[m] = cpow_nu(cp[m], nu);
+            dp[m] = dcpow_nu(cp[m], nu);
+        }
+        pb = kb * (pp[0] * pp[1] * pp[2]);
+        dpb[0] = kb * (dp[0] * pp[1] * pp[2]);
+        dpb[1] = kb * (pp[0] * dp[1] * pp[2]);
+        dpb[2] = kb * (pp[0] * pp[1] * dp[2]);
+    }
+    const double Mc = (x.tb >= 0) ? L.Mc[x.tb] : 1.0;
+    const double D = pf - pb;
+    const double q = Mc * D;
+    const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
+    if (x.tb >= 0) L.DTB[x.tb] = D;
+    // dQ/dc_k / M_k for each participant k
+    double dq[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const int sp = x.part_sp[j];
+        double gf = 0.0, gb = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            gf += (m < x.nreac && x.reac_sp[m] == sp) ? dpf[m] : 0.0;
+            gb += (m < x.nprod && x.prod_sp[m] == sp) ? dpb[m] : 0.0;
+        }
+        dq[j] = Mc * (gf - gb) * kc->colc[j];
+    }
+    const int JS = NPAD;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        if (i < x.npart && x.part_nu[i] != 0) {
+            const int si = x.part_sp[i];
+            const double nu = (double)x.part_nu[i];
+            const double a = kc->rowc[i];
+            lds_add(L.W + si, nu * q);
+            lds_add(L.WT + si, nu * qT);
+            double *Jr = L.J + (size_t)si * JS;
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                if (j < x.npart) lds_add(Jr + x.part_sp[j], a * dq[j]);
+        }
+    }
+}
+
+// f = dx/dt and J = df/dx of the cell at x (lane i holds x_i).  Leaves J in L.J (row-major,
+// stride NPAD, zero beyond column N - 1) and f in L.W.
+template <int NPAD>
+__device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane, double rho, double xs,
+                                     double Ms, double invMs)
+{
+    const int ns = t.ns, N = ns + 1, JS = NPAD;
+    const double T = rdlane(xs, ns);
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
     const double lPaRT = t.lnPaR - lT;  // ln(P_atm / (R T)), CGS
-    for (int k = lane; k < N * JS; k += kW) L.J[k] = 0.0;
+    {   // clear J, W and WT (J's region ends where W begins)
+        double2 *z = reinterpret_cast<double2 *>(L.J);
+        const int nj = N * JS / 2, n2 = nj + NPAD;
+        const int skip = j_region(N, NPAD) / 2 - nj;
+        for (int k = lane; k < n2; k += kW) z[k < nj ? k : k + skip] = make_double2(0.0, 0.0);
+    }
     double cvk = 0.0, dcvk = 0.0, ek = 0.0;
     if (lane < ns) {
         const Thermo th = thermo(t, lane, T, iT, lT);
-        const double invM = 1.0 / t.M[lane];
-        const double rm = 8.31446261815324e3 * invM;
-        L.c[lane] = xs * (rc * invM);
+        const double rm = 8.31446261815324e3 * invMs;
+        L.c[lane] = xs * (rc * invMs);
         L.g[lane] = th.h - th.s;
-        L.h[lane] = th.h;
+        L.hh[lane] = th.h;
         ek = rm * T * (th.h - 1.0);
         cvk = rm * (th.cp - 1.0);
         dcvk = rm * th.dcp;
-        L.ek[lane] = ek;
-        L.cvk[lane] = cvk;
-        L.invM[lane] = invM;
     }
     wave_sync();
     // third-body concentrations [M]_r = sum_s eff_rs c_s, one reaction per lane
     for (int r = lane; r < t.ntb; r += kW) {
         double acc = 0.0;
-        for (int s = 0; s < ns; ++s) acc = fma(t.effT[(size_t)s * t.ntb + r], L.c[s], acc);
+        const double *e = t.effT + r;
+#pragma unroll 4
+        for (int s = 0; s < ns; ++s, e += t.ntb) acc = fma(*e, L.c[s], acc);
         L.Mc[r] = acc;
     }
     wave_sync();
-    double w = 0.0, jt = 0.0;
-    double *const Q = L.cq, *const QT = L.cq + kChunk, *const DD = L.cq + 2 * kChunk;
-    double *const DQ = L.cq + 3 * kChunk;
-    const double Ms = (lane < ns) ? t.M[lane] : 0.0;
-    for (int cb = 0; cb < t.nchunk; ++cb) {
-        const int r = cb * kChunk + lane;
-        if (r < t.nr) {
-            const RxnRec x = t.rxc[r];
-            const double *rd = t.rxd + (size_t)r * 4;
-            const double b = rd[1], Ta = rd[2], dnu = rd[3];
-            const double lkf = fma(-Ta, iT, fma(b, lT, rd[0]));
-            const double kf = exp(lkf);
-            const double dlkf = fma(Ta, iT, b) * iT;
-            double cr[3], cpd[3];
-            double pf = kf;
-            for (int j = 0; j < x.nreac; ++j) {
-                cr[j] = L.c[x.reac_sp[j]];
-                pf *= cpow_nu(cr[j], x.reac_nu[j]);
-            }
-            double kb = 0.0, pb = 0.0, dlKc = 0.0;
-            if (x.rev) {
-                double sg = 0.0, sh = 0.0;
-                for (int j = 0; j < x.npart; ++j) {
-                    const double nu = (double)x.part_nu[j];
-                    sg = fma(nu, L.g[x.part_sp[j]], sg);
-                    sh = fma(nu, L.h[x.part_sp[j]], sh);
-                }
-                const double lKc = dnu * lPaRT - sg;
-                kb = exp(lkf - lKc);
-                dlKc = (sh - dnu) * iT;
-                pb = kb;
-                for (int j = 0; j < x.nprod; ++j) {
-                    cpd[j] = L.c[x.prod_sp[j]];
-                    pb *= cpow_nu(cpd[j], x.prod_nu[j]);
-                }
-            }
-            const double Mc = (x.tb >= 0) ? L.Mc[x.tb] : 1.0;
-            const double D = pf - pb;
-            Q[lane] = Mc * D;
-            QT[lane] = Mc * (pf * dlkf - pb * (dlkf - dlKc));
-            DD[lane] = D;
-            for (int j = 0; j < x.npart; ++j) {
-                const int sp = x.part_sp[j];
-                // d/dc_sp of kf prod c^nu' minus d/dc_sp of kb prod c^nu''
-                double gf = 0.0, gb = 0.0;
-                for (int m = 0; m < x.nreac; ++m) {
-                    if (x.reac_sp[m] != sp) continue;
-                    const int nu = x.reac_nu[m];
-                    double d = kf * (double)nu * (nu == 1 ? 1.0 : (nu == 2 ? cr[m] : cr[m] * cr[m]));
-                    for (int o = 0; o < x.nreac; ++o)
-                        if (o != m) d *= cpow_nu(cr[o], x.reac_nu[o]);
-                    gf = d;
-                }
-                if (x.rev) {
-                    for (int m = 0; m < x.nprod; ++m) {
-                        if (x.prod_sp[m] != sp) continue;
-                        const int nu = x.prod_nu[m];
-                        double d = kb * (double)nu * (nu == 1 ? 1.0 : (nu == 2 ? cpd[m] : cpd[m] * cpd[m]));
-                        for (int o = 0; o < x.nprod; ++o)
-                            if (o != m) d *= cpow_nu(cpd[o], x.prod_nu[o]);
-                        gb = d;
-                    }
-                }
-                DQ[j * kChunk + lane] = Mc * (gf - gb);
-            }
+    for (int r = lane; r < t.nr; r += kW) reaction_terms<NPAD>(t, L, r, iT, lT, lPaRT);
+    wave_sync();
+    // dense third-body terms: lane k adds nu_rs M_s (q_f - q_b) eff_rk / M_k to J[s][k]
+    if (lane < ns) {
+        const double *em = t.effM + lane;
+        for (int tb = 0; tb < t.ntb; ++tb) {
+            const TbRec rec = t.tbr[tb];
+            const double v = L.DTB[tb] * em[(size_t)tb * ns];
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                if (i < rec.nrow) lds_add(L.J + (size_t)rec.row[i] * JS + lane, rec.coef[i] * v);
         }
-        wave_sync();
-        if (lane < ns) {
-            const int *sp = t.sp_ptr + (size_t)lane * (t.nchunk + 1);
-            for (int e = sp[cb]; e < sp[cb + 1]; ++e) {
-                const int ent = t.sp_list[e];
-                const int rl = ent >> 4;
-                const double nu = (double)((ent & 15) - 8);
-                w = fma(nu, Q[rl], w);
-                jt = fma(nu, QT[rl], jt);
-            }
-            const int *ep = t.ent_ptr + (size_t)lane * (t.nchunk + 1);
-            double *Jrow = L.J + (size_t)lane * JS;
-            for (int e = ep[cb]; e < ep[cb + 1]; ++e) {
-                const int ent = t.ent_list[e];
-                const int rl = ent & 63, slot = (ent >> 6) & 7, k = (ent >> 9) & 63;
-                const double nu = (double)(((ent >> 15) & 15) - 8);
-                Jrow[k] = fma(nu * Ms * L.invM[k], DQ[slot * kChunk + rl], Jrow[k]);
-            }
-        }
-        wave_sync();
-        // dense third-body part, one Jacobian column per lane
-        if (lane < ns) {
-            for (int e = t.tb_ptr[cb]; e < t.tb_ptr[cb + 1]; ++e) {
-                const int r2 = t.tb_list[e];
-                const RxnRec x = t.rxc[r2];
-                const double tk = DD[r2 - cb * kChunk] * t.effM[(size_t)x.tb * ns + lane];
-                for (int j = 0; j < x.npart; ++j) {
-                    if (!x.part_nu[j]) continue;
-                    const int s2 = x.part_sp[j];
-                    double *Jp = L.J + (size_t)s2 * JS + lane;
-                    *Jp = fma((double)x.part_nu[j] * t.M[s2], tk, *Jp);
-                }
-            }
-        }
-        wave_sync();
     }
-    // species rows of f and the temperature column
+    wave_sync();
+    // species rows of f and the temperature column; e_s and cv_s replace g and h
     double fs = 0.0;
     if (lane < ns) {
         const double ms = Ms * irc;
-        fs = w * ms;
-        L.J[(size_t)lane * JS + ns] = jt * ms;
-        L.f[lane] = fs;
+        fs = L.W[lane] * ms;
+        L.J[(size_t)lane * JS + ns] = L.WT[lane] * ms;
+        L.W[lane] = fs;
+        L.g[lane] = ek;
+        L.hh[lane] = cvk;
     }
     const double cv = wave_sum(lane < ns ? xs * cvk : 0.0);
     const double dcv = wave_sum(lane < ns ? xs * dcvk : 0.0);
@@ -304,73 +405,90 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     const double icv = 1.0 / cv;
     wave_sync();
     // energy row: lane k < ns forms J[ns][k]; lane ns forms J[ns][ns]
+    const double *E = L.g, *CV = L.hh;
     if (lane <= ns) {
         double acc = 0.0;
         if (lane < ns) {
-            for (int s = 0; s < ns; ++s) acc = fma(L.ek[s], L.J[(size_t)s * JS + lane], acc);
-            L.J[(size_t)ns * JS + lane] = -fma(fT, L.cvk[lane], acc) * icv;
+            for (int s = 0; s < ns; ++s) acc = fma(E[s], L.J[(size_t)s * JS + lane], acc);
+            L.J[(size_t)ns * JS + lane] = -fma(fT, cvk, acc) * icv;
         } else {
-            for (int s = 0; s < ns; ++s)
-                acc = fma(L.cvk[s], L.f[s], fma(L.ek[s], L.J[(size_t)s * JS + ns], acc));
+            for (int s = 0; s < ns; ++s) acc = fma(CV[s], L.W[s], fma(E[s], L.J[(size_t)s * JS + ns], acc));
             L.J[(size_t)ns * JS + ns] = -fma(fT, dcv, acc) * icv;
-            L.f[ns] = fT;
+            L.W[ns] = fT;
         }
     }
     wave_sync();
 }
 
-// Gaussian elimination with partial pivoting, one row per lane.  Lane i < N enters with row i
-// of A in a[] and b_i in bb; on return sol[0..N) in LDS holds the solution.  Pivot rule: the
-// first (lowest current position) row of largest |a_ik| among rows not yet used.  Returns
-// false on an exactly zero pivot.
+// Gaussian elimination with partial pivoting, one row per lane, and back substitution.  Lane
+// i < N enters with row i of A in a[] and b_i in bb; on return x holds solution component
+// `lane` (lanes >= N: 0).  Pivot rule: the row of largest |a_ik| among rows not yet used,
+// ties to the lowest current position.  The pivot row of step k is stored packed at U + off_k
+// (16-byte aligned; element m is column k + m) and y_k at Y[k].  Returns false on an exactly
+// zero pivot.
 template <int NPAD, typename R>
-__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, const Lds &L)
+__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, double *Ubase, double *Ybase, R &x)
 {
-    R *prow = reinterpret_cast<R *>(L.prow);
-    int pos = lane;
+    constexpr int E16 = 16 / sizeof(R);
+    R *const U = reinterpret_cast<R *>(Ubase);
+    R *const Y = reinterpret_cast<R *>(Ybase);
+    int pos = lane, myoff = 0, off = 0;
     bool ok = true;
+    for (int blk = 0; blk < NPAD / 4; ++blk) {
+        if (4 * blk >= N) break;
 #pragma unroll
-    for (int k = 0; k < NPAD; ++k) {
-        if (k < N) {
-            R v = (pos >= k) ? (R)fabs(a[k]) : R(-1);
-            int p = pos;
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * blk + kk;
+            if (k < N) {
+                R v = (pos >= k && lane < N) ? (R)fabs(a[kk]) : R(-1);
+                int p = pos;
+                wave_argmax(v, p);
+                ok = ok && (v > R(0));
+                const int w = __builtin_ctzll(__ballot(pos == p));
+                pos = (lane == w) ? k : (pos == k ? p : pos);
+                myoff = (lane == k) ? off : myoff;
+                R *row = static_cast<R *>(__builtin_assume_aligned(U + off, 16));
+                if (lane == w) {
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const R ov = __shfl_xor(v, off, kW);
-                const int op = __shfl_xor(p, off, kW);
-                const bool take = (ov > v) || (ov == v && op < p);
-                v = take ? ov : v;
-                p = take ? op : p;
+                    for (int j = kk; j < NPAD; ++j) row[j - kk] = a[j];
+                    Y[k] = bb;
+                }
+                wave_sync();
+                if (pos > k) {
+                    const R l = a[kk] / row[0];
+                    bb = fma(-l, Y[k], bb);
+                    // the pivot row is read eight columns at a time so that its copy never
+                    // occupies more than a few registers beside the lane's own row
+#pragma unroll
+                    for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
+#pragma unroll
+                        for (int j = j0; j < j0 + 8 && j < NPAD; ++j) a[j] = fma(-l, row[j - kk], a[j]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                off += u_row_len(N, k, E16);
             }
-            ok = ok && (v > R(0));
-            const bool is_piv = (pos == p);
-            pos = is_piv ? k : (pos == k ? p : pos);
-            if (is_piv) {
-#pragma unroll
-                for (int j = k; j < NPAD; ++j) prow[j] = a[j];
-                prow[NPAD] = bb;
-            }
-            wave_sync();
-            if (pos > k) {
-                const R l = a[k] / prow[k];
-#pragma unroll
-                for (int j = k + 1; j < NPAD; ++j) a[j] = fma(-l, prow[j], a[j]);
-                bb = fma(-l, prow[NPAD], bb);
-            }
-            wave_sync();
         }
-    }
-    // back substitution, one unknown per step
+        // rotate the row left by four so the next block's pivot columns sit in a[0..3]
+        const R t0 = a[0], t1 = a[1], t2 = a[2], t3 = a[3];
 #pragma unroll
-    for (int k = NPAD - 1; k >= 0; --k) {
-        if (k < N) {
-            if (pos == k) L.sol[k] = (double)(bb / a[k]);
-            wave_sync();
-            const R xk = (R)L.sol[k];
-            if (pos < k) bb = fma(-a[k], xk, bb);
-            wave_sync();
-        }
+        for (int j = 0; j + 4 < NPAD; ++j) a[j] = a[j + 4];
+        a[NPAD - 4] = t0;
+        a[NPAD - 3] = t1;
+        a[NPAD - 2] = t2;
+        a[NPAD - 1] = t3;
     }
+    wave_sync();
+    // back substitution: lane i keeps y_i; step k forms x_k and removes it from rows i < k
+    R y = (lane < N) ? Y[lane] : R(0);
+    R xl = R(0);
+    for (int k = N - 1; k >= 0; --k) {
+        const int ok_ = rdlane(myoff, k);
+        const R xk = rdlane(y, k) / U[ok_];
+        xl = (lane == k) ? xk : xl;
+        if (lane < k) y = fma(-U[myoff + (k - lane)], xk, y);
+    }
+    x = xl;
     return ok;
 }
 
@@ -382,32 +500,38 @@ struct StepCtl {
 // One backward-Euler sub-step of size h.  xs (lane i: x_i) is updated on success.
 template <int NPAD, bool F32>
 __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int lane, double rho, double e0,
-                        double &xs, double h, const StepCtl &c, int &iters)
+                                        double &xs, double h, const StepCtl &c, int &iters, double Ms,
+                                        double invMs)
 {
-    const int ns = t.ns, N = ns + 1, JS = NPAD + 1;
+    const int ns = t.ns, N = ns + 1, JS = NPAD;
     double xk = xs;
     for (int k = 0; k < c.k_max; ++k) {
         ++iters;
-        eval<NPAD>(t, L, lane, rho, xk);
+        eval<NPAD>(t, L, lane, rho, xk, Ms, invMs);
         double bi = 0.0;
         double arow[NPAD];
         bool bad = false;
         if (lane < N) {
-            bi = -((xk - xs) - h * L.f[lane]);
+            bi = -((xk - xs) - h * L.W[lane]);
             bad = !__builtin_isfinite(bi);
-            const double *Jr = L.J + (size_t)lane * JS;
-#pragma unroll
-            for (int j = 0; j < NPAD; ++j) {
-                const double v = (j < N) ? ((j == lane ? 1.0 : 0.0) - h * Jr[j]) : 0.0;
-                arow[j] = v;
+            // the Newton matrix row I - hJ, formed in place (columns N.. stay zero)
+            double *Jr = L.J + (size_t)lane * JS;
+#pragma unroll 4
+            for (int j = 0; j < N; ++j) {
+                const double v = (j == lane ? 1.0 : 0.0) - h * Jr[j];
+                Jr[j] = v;
                 bad = bad || !__builtin_isfinite(v);
             }
+#pragma unroll
+            for (int j = 0; j < NPAD; ++j) arow[j] = Jr[j];
         } else {
 #pragma unroll
             for (int j = 0; j < NPAD; ++j) arow[j] = 0.0;
         }
         if (__any(bad)) return false;
+        wave_sync();  // J and f are read; the solve reuses their space
         bool ok;
+        double d;
         if (F32) {
             float af[NPAD];
             double m = 0.0;
@@ -416,17 +540,18 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
             const double s = (lane < N) ? 1.0 / m : 0.0;
 #pragma unroll
             for (int j = 0; j < NPAD; ++j) af[j] = (float)(arow[j] * s);
-            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, L);
+            float xf;
+            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, L.J, L.W, xf);
+            d = (double)xf;
         } else {
-            ok = lu_solve<NPAD, double>(arow, bi, N, lane, L);
+            ok = lu_solve<NPAD, double>(arow, bi, N, lane, L.J, L.W, d);
         }
         if (!ok) return false;
-        const double d = (lane < N) ? L.sol[lane] : 0.0;
         wave_sync();
         xk += d;
         const double atol = (lane < ns) ? c.atol_Y : c.atol_T;
         if (__any(lane < N && !__builtin_isfinite(xk))) return false;
-        const double T = bcast(xk, ns);
+        const double T = rdlane(xk, ns);
         if (T < kTmin || T > kTmax) return false;
         const bool conv = __all(lane >= N || fabs(d) <= atol + c.rtol * fabs(xk));
         if (conv) {
@@ -441,70 +566,70 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
 }
 
 template <int NPAD, bool F32>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) wave_kernel(WaveTables t, AdvanceArgs a, int wpb)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) wave_kernel(WaveTables t, AdvanceArgs a, int wpb)
 {
     extern __shared__ double smem[];
     const int lane = threadIdx.x & (kW - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
     const int ns = t.ns, N = ns + 1;
-    const Lds L = lds_map<NPAD>(smem + (size_t)wid * lds_doubles<NPAD>(N, t.ntb), N, t.ntb);
+    const Lds L = lds_map(smem + (size_t)wid * lds_doubles(N, t.ntb, NPAD), N, t.ntb, NPAD);
     const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max};
+    const double Ms = lane < ns ? t.M[lane] : 1.0;
+    const double invMs = 1.0 / Ms;
     // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones
     // retire, which balances cells that need very different numbers of Newton iterations
-    {
-        const long long gcell = (long long)blockIdx.x * wpb + wid;
-        if (gcell >= a.total) return;
-        int j = 0;
-        while (j + 1 < a.nspan && a.span[j + 1].start <= gcell) ++j;
-        const long long cell = gcell - a.span[j].start;
-        const double dt = a.span[j].dt;
-        const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
-        const long long ld = a.span[j].n;
-        const double rho = ar.rho[cell];
-        const double e0 = ar.e0[cell];
-        double xs = 0.0;
-        if (lane < ns) xs = ar.Y[(size_t)lane * ld + cell];
-        else if (lane == ns) xs = ar.T[cell];
-        const double T0 = bcast(xs, ns);
-        const bool bad_in = __any(lane < N && !__builtin_isfinite(xs)) || !__builtin_isfinite(rho) ||
-                            !(rho > 0.0) || !__builtin_isfinite(e0) || !__builtin_isfinite(dt) ||
-                            !(dt >= 0.0) || T0 < kTmin || T0 > kTmax;
-        // dyadic sub-stepping in ticks of dt 2^-Lc (see the lane layout for the rule)
-        const bool adapt = a.L_forced < 0;
-        const int Lc = adapt ? a.L_max : a.L_forced;
-        const unsigned long long end = 1ull << Lc;
-        unsigned long long tt = bad_in ? end : 0ull;
-        int l = adapt ? 0 : a.L_forced;
-        int iters = 0, level = bad_in ? 0 : l, st = bad_in ? 3 : 0;
-        bool failed = false;
-        unsigned long long hsh = 0xcbf29ce484222325ull;  // FNV-1a of the sub-step attempts
-        while (tt < end) {
-            if (iters >= a.max_iters) { st = 2; break; }
-            const double h = ldexp(dt, -l);
-            const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters);
-            hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
-            if (ok) {
-                tt += 1ull << (Lc - l);
-                if (adapt && l > 0 && (tt & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
-            } else {
-                if (!adapt) { st = 2; break; }
-                failed = true;
-                ++l;
-                if (l > level) level = l;
-                if (l > a.L_max) { level = a.L_max; st = 2; break; }
-            }
+    const long long gcell = (long long)blockIdx.x * wpb + wid;
+    if (gcell >= a.total) return;
+    int j = 0;
+    while (j + 1 < a.nspan && a.span[j + 1].start <= gcell) ++j;
+    const long long cell = gcell - a.span[j].start;
+    const double dt = a.span[j].dt;
+    const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
+    const long long ld = a.span[j].n;
+    const double rho = ar.rho[cell];
+    const double e0 = ar.e0[cell];
+    double xs = 0.0;
+    if (lane < ns) xs = ar.Y[(size_t)lane * ld + cell];
+    else if (lane == ns) xs = ar.T[cell];
+    const double T0 = rdlane(xs, ns);
+    const bool bad_in = __any(lane < N && !__builtin_isfinite(xs)) || !__builtin_isfinite(rho) ||
+                        !(rho > 0.0) || !__builtin_isfinite(e0) || !__builtin_isfinite(dt) ||
+                        !(dt >= 0.0) || T0 < kTmin || T0 > kTmax;
+    // dyadic sub-stepping in ticks of dt 2^-Lc (see the lane layout for the rule)
+    const bool adapt = a.L_forced < 0;
+    const int Lc = adapt ? a.L_max : a.L_forced;
+    const unsigned long long end = 1ull << Lc;
+    unsigned long long tt = bad_in ? end : 0ull;
+    int l = adapt ? 0 : a.L_forced;
+    int iters = 0, level = bad_in ? 0 : l, st = bad_in ? 3 : 0;
+    bool failed = false;
+    unsigned long long hsh = 0xcbf29ce484222325ull;  // FNV-1a of the sub-step attempts
+    while (tt < end) {
+        if (iters >= a.max_iters) { st = 2; break; }
+        const double h = ldexp(dt, -l);
+        const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters, Ms, invMs);
+        hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
+        if (ok) {
+            tt += 1ull << (Lc - l);
+            if (adapt && l > 0 && (tt & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
+        } else {
+            if (!adapt) { st = 2; break; }
+            failed = true;
+            ++l;
+            if (l > level) level = l;
+            if (l > a.L_max) { level = a.L_max; st = 2; break; }
         }
-        if (st == 0 && failed) st = 1;
-        if (st < 2) {
-            if (lane < ns) ar.Y[(size_t)lane * ld + cell] = xs;
-            else if (lane == ns) ar.T[cell] = xs;
-        }
-        if (lane == 0) {
-            ar.status[cell] = st;
-            ar.level[cell] = level;
-            ar.iters[cell] = iters;
-            ar.sched[cell] = hsh;
-        }
+    }
+    if (st == 0 && failed) st = 1;
+    if (st < 2) {
+        if (lane < ns) ar.Y[(size_t)lane * ld + cell] = xs;
+        else if (lane == ns) ar.T[cell] = xs;
+    }
+    if (lane == 0) {
+        ar.status[cell] = st;
+        ar.level[cell] = level;
+        ar.iters[cell] = iters;
+        ar.sched[cell] = hsh;
     }
 }
 
@@ -528,16 +653,11 @@ __global__ void energy_kernel(WaveTables t, long long n, long long ld, const dou
     e0[i] = e;
 }
 
-template <int NPAD>
-size_t lds_bytes_host(int N, int ntb)
-{
-    return sizeof(double) * lds_doubles<NPAD>(N, ntb);
-}
-
 template <int NPAD, bool F32>
 hipError_t launch_t(const WaveTables &t, const AdvanceArgs &a, int wpb, int grid, hipStream_t s)
 {
-    const size_t lds = lds_bytes_host<NPAD>(t.ns + 1, t.ntb) * wpb;
+    const size_t lds = sizeof(double) * lds_doubles(t.ns + 1, t.ntb, NPAD) * wpb;
+    if (lds > 65536) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((wave_kernel<NPAD, F32>), dim3(grid), dim3(kW * wpb), lds, s, t, a, wpb);
     return hipGetLastError();
 }
@@ -553,15 +673,8 @@ int wave_npad(int n)
 
 size_t wave_lds_bytes(const WaveTables &t, bool)
 {
-    const int N = t.ns + 1;
-    switch (wave_npad(N)) {
-    case 16: return lds_bytes_host<16>(N, t.ntb);
-    case 24: return lds_bytes_host<24>(N, t.ntb);
-    case 32: return lds_bytes_host<32>(N, t.ntb);
-    case 40: return lds_bytes_host<40>(N, t.ntb);
-    case 48: return lds_bytes_host<48>(N, t.ntb);
-    default: return lds_bytes_host<64>(N, t.ntb);
-    }
+    const int N = t.ns + 1, p = wave_npad(N);
+    return p < 0 ? 0 : sizeof(double) * lds_doubles(N, t.ntb, p);
 }
 
 hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool f32, int wpb, int grid,

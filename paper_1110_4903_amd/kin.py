@@ -31,6 +31,12 @@ EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destr
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
+# torch's wheel carries its own HIP runtime under the same soname as the system one.  A process
+# must hold only one, so torch is loaded first and the library binds to the runtime it brought.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - the library also works without torch
+    pass
 _lib = C.CDLL(SO)
 
 
