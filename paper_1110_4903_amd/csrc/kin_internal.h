@@ -87,15 +87,13 @@ struct RxnCoef {
     double colc[6];
 };
 
-// Third-body reaction (one slot per such reaction): the rows it writes (participants with a nonzero
-// net coefficient) and their factors nu_rs M_s.
+// Third-body reaction (one slot per such reaction): the Jacobian rows it writes (participants
+// with a nonzero net coefficient).
 struct TbRec {
     int8_t nrow;
     int8_t row[7];
-    double coef[6];
-    double pad;
 };
-static_assert(sizeof(TbRec) == 64, "third-body record must stay 64 bytes");
+static_assert(sizeof(TbRec) == 8, "third-body record must stay 8 bytes");
 
 struct WaveTables {
     int ns, nr, ntb, nchunk;  // ntb: third-body reactions (each has a slot; RxnRec::tb is the slot)
@@ -107,7 +105,7 @@ struct WaveTables {
     const RxnRec *rxc;      // [nr]
     const RxnCoef *rxk;     // [nr]
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
-    const double *effM;     // [ntb][ns] efficiency / molar mass (eff_rk / M_k) per slot
+    const double *effR;     // [ntb][6][ns] per slot and row i: nu_ri M_i eff_rk / M_k
     const TbRec *tbr;       // [ntb] per slot
 };
 

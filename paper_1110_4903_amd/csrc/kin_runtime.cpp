@@ -308,30 +308,30 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             k.rowc[j] = j < x.npart ? (double)x.part[j].nu * h.M[x.part[j].sp] : 0.0;
             k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
         }
-        if (slot[r] >= 0) {
-            TbRec &t = tbr[slot[r]];
-            for (int j = 0; j < x.npart; ++j) {
-                if (!x.part[j].nu) continue;
-                t.row[t.nrow] = (int8_t)x.part[j].sp;
-                t.coef[t.nrow] = (double)x.part[j].nu * h.M[x.part[j].sp];
-                ++t.nrow;
-            }
-        }
     }
-    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effM((size_t)std::max(1, ntb * ns), 0.0);
-    for (int q = 0; q < ntb; ++q)
-        for (int k = 0; k < ns; ++k) {
-            const double e = h.eff[(size_t)slot_row[q] * ns + k];
-            effT[(size_t)k * ntb + q] = e;
-            effM[(size_t)q * ns + k] = e / h.M[k];
+    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR((size_t)std::max(1, ntb * 6 * ns), 0.0);
+    for (int r = 0; r < nr; ++r) {
+        const int q = slot[r];
+        if (q < 0) continue;
+        const Rxn &x = h.rx[r];
+        TbRec &t = tbr[q];
+        for (int j = 0; j < x.npart; ++j) {
+            if (!x.part[j].nu) continue;
+            const double cs = (double)x.part[j].nu * h.M[x.part[j].sp];
+            for (int k = 0; k < ns; ++k)
+                effR[((size_t)q * 6 + t.nrow) * ns + k] = cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k];
+            t.row[t.nrow] = (int8_t)x.part[j].sp;
+            ++t.nrow;
         }
+        for (int k = 0; k < ns; ++k) effT[(size_t)k * ntb + q] = h.eff[(size_t)slot_row[q] * ns + k];
+    }
     // one allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pc = {
         {h.nasa.data(), sizeof(double) * h.nasa.size(), 0}, {h.Tmid.data(), sizeof(double) * ns, 0},
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
-        {effT.data(), sizeof(double) * effT.size(), 0}, {effM.data(), sizeof(double) * effM.size(), 0},
+        {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
         {tbr.data(), sizeof(TbRec) * tbr.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
@@ -351,7 +351,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.rxc = reinterpret_cast<const RxnRec *>(b + pc[4].off);
     t.rxk = reinterpret_cast<const RxnCoef *>(b + pc[5].off);
     t.effT = reinterpret_cast<const double *>(b + pc[6].off);
-    t.effM = reinterpret_cast<const double *>(b + pc[7].off);
+    t.effR = reinterpret_cast<const double *>(b + pc[7].off);
     t.tbr = reinterpret_cast<const TbRec *>(b + pc[8].off);
     return KIN_OK;
 }

@@ -251,12 +251,10 @@ __device__ __forceinline__ double dcpow_nu(double c, int nu)
 //   Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''),  dQ_r/dc_k over the participants,
 //   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  WT[s] += nu_rs dQ_r/dT.
 template <int NPAD>
-__device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, double iT,
-                                               double lT, double lPaRT)
+__device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
+                                               const double4 &rd, double iT, double lT, double lPaRT)
 {
-    const RxnRec x = t.rxc[r];
-    const double *rd = t.rxd + (size_t)r * 4;
-    const double lnA = rd[0], b = rd[1], Ta = rd[2], dnu = rd[3];
+    const double lnA = rd.x, b = rd.y, Ta = rd.z, dnu = rd.w;
     const RxnCoef *kc = t.rxk + r;
     const double lkf = fma(-Ta, iT, fma(b, lT, lnA));
     const double kf = exp(lkf);
@@ -374,17 +372,34 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         L.Mc[r] = acc;
     }
     wave_sync();
-    for (int r = lane; r < t.nr; r += kW) reaction_terms<NPAD>(t, L, r, iT, lT, lPaRT);
+    {   // reactions, 64 at a time; each pass loads the next pass's records
+        const double4 *rxd4 = reinterpret_cast<const double4 *>(t.rxd);
+        RxnRec xn{};
+        double4 rn{};
+        if (lane < t.nr) { xn = t.rxc[lane]; rn = rxd4[lane]; }
+        for (int r0 = 0; r0 < t.nr; r0 += kW) {
+            const int r = r0 + lane;
+            const RxnRec x = xn;
+            const double4 rd = rn;
+            if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; }
+            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, iT, lT, lPaRT);
+        }
+    }
     wave_sync();
     // dense third-body terms: lane k adds nu_rs M_s (q_f - q_b) eff_rk / M_k to J[s][k]
     if (lane < ns) {
-        const double *em = t.effM + lane;
+        const double *er = t.effR + lane;
+#pragma unroll 2
         for (int tb = 0; tb < t.ntb; ++tb) {
             const TbRec rec = t.tbr[tb];
-            const double v = L.DTB[tb] * em[(size_t)tb * ns];
+            const double D = L.DTB[tb];
+            const double *e = er + (size_t)tb * 6 * ns;
+            double v[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) v[i] = (i < rec.nrow) ? e[(size_t)i * ns] : 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
-                if (i < rec.nrow) lds_add(L.J + (size_t)rec.row[i] * JS + lane, rec.coef[i] * v);
+                if (i < rec.nrow) lds_add(L.J + (size_t)rec.row[i] * JS + lane, D * v[i]);
         }
     }
     wave_sync();
@@ -409,9 +424,11 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     if (lane <= ns) {
         double acc = 0.0;
         if (lane < ns) {
+#pragma unroll 4
             for (int s = 0; s < ns; ++s) acc = fma(E[s], L.J[(size_t)s * JS + lane], acc);
             L.J[(size_t)ns * JS + lane] = -fma(fT, cvk, acc) * icv;
         } else {
+#pragma unroll 4
             for (int s = 0; s < ns; ++s) acc = fma(CV[s], L.W[s], fma(E[s], L.J[(size_t)s * JS + ns], acc));
             L.J[(size_t)ns * JS + ns] = -fma(fT, dcv, acc) * icv;
             L.W[ns] = fT;
@@ -423,16 +440,17 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
 // Gaussian elimination with partial pivoting, one row per lane, and back substitution.  Lane
 // i < N enters with row i of A in a[] and b_i in bb; on return x holds solution component
 // `lane` (lanes >= N: 0).  Pivot rule: the row of largest |a_ik| among rows not yet used,
-// ties to the lowest current position.  The pivot row of step k is stored packed at U + off_k
-// (16-byte aligned; element m is column k + m) and y_k at Y[k].  Returns false on an exactly
-// zero pivot.
+// ties to the lowest current position.  The pivot row is broadcast from its lane's registers
+// (readlane), and stored packed at U + off_k (element m is column k + m) for the back
+// substitution; lane k keeps the pivot u_kk and the eliminated right-hand side y_k.  Returns
+// false on an exactly zero pivot.
 template <int NPAD, typename R>
-__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, double *Ubase, double *Ybase, R &x)
+__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, double *Ubase, R &x)
 {
     constexpr int E16 = 16 / sizeof(R);
     R *const U = reinterpret_cast<R *>(Ubase);
-    R *const Y = reinterpret_cast<R *>(Ybase);
     int pos = lane, myoff = 0, off = 0;
+    R dg = R(1), yv = R(0);
     bool ok = true;
     for (int blk = 0; blk < NPAD / 4; ++blk) {
         if (4 * blk >= N) break;
@@ -447,24 +465,30 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
                 const int w = __builtin_ctzll(__ballot(pos == p));
                 pos = (lane == w) ? k : (pos == k ? p : pos);
                 myoff = (lane == k) ? off : myoff;
-                R *row = static_cast<R *>(__builtin_assume_aligned(U + off, 16));
+                const R piv = rdlane(a[kk], w);
+                const R yk = rdlane(bb, w);
+                dg = (lane == k) ? piv : dg;
+                yv = (lane == k) ? yk : yv;
                 if (lane == w) {
+                    R *row = static_cast<R *>(__builtin_assume_aligned(U + off, 16));
 #pragma unroll
                     for (int j = kk; j < NPAD; ++j) row[j - kk] = a[j];
-                    Y[k] = bb;
                 }
-                wave_sync();
-                if (pos > k) {
-                    const R l = a[kk] / row[0];
-                    bb = fma(-l, Y[k], bb);
-                    // the pivot row is read eight columns at a time so that its copy never
-                    // occupies more than a few registers beside the lane's own row
+                const bool elim = pos > k;
+                const R l = elim ? a[kk] / piv : R(0);
+                bb = fma(-l, yk, bb);
+                // pivot row from the pivot lane's registers, eight columns at a time; register
+                // positions from NPAD - 4 blk on hold columns already eliminated (rotated in
+                // from the front) and are skipped eight at a time
 #pragma unroll
-                    for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
+                for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
+                    if (j0 >= NPAD - 4 * blk) break;
+                    R pr[8];
 #pragma unroll
-                        for (int j = j0; j < j0 + 8 && j < NPAD; ++j) a[j] = fma(-l, row[j - kk], a[j]);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
+                    for (int j = j0; j < j0 + 8 && j < NPAD; ++j) pr[j - j0] = rdlane(a[j], w);
+#pragma unroll
+                    for (int j = j0; j < j0 + 8 && j < NPAD; ++j) a[j] = fma(-l, pr[j - j0], a[j]);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 off += u_row_len(N, k, E16);
             }
@@ -479,14 +503,16 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
         a[NPAD - 1] = t3;
     }
     wave_sync();
-    // back substitution: lane i keeps y_i; step k forms x_k and removes it from rows i < k
-    R y = (lane < N) ? Y[lane] : R(0);
+    // back substitution: lane i keeps y_i; step k forms x_k and removes it from rows i < k.
+    // The U element of the next step is loaded one step ahead.
     R xl = R(0);
+    R un = (lane < N - 1) ? U[myoff + (N - 1) - lane] : R(0);
     for (int k = N - 1; k >= 0; --k) {
-        const int ok_ = rdlane(myoff, k);
-        const R xk = rdlane(y, k) / U[ok_];
+        const R u = un;
+        if (lane + 1 < k) un = U[myoff + (k - 1) - lane];
+        const R xk = rdlane(yv, k) / rdlane(dg, k);
         xl = (lane == k) ? xk : xl;
-        if (lane < k) y = fma(-U[myoff + (k - lane)], xk, y);
+        if (lane < k) yv = fma(-u, xk, yv);
     }
     x = xl;
     return ok;
@@ -541,10 +567,10 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
 #pragma unroll
             for (int j = 0; j < NPAD; ++j) af[j] = (float)(arow[j] * s);
             float xf;
-            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, L.J, L.W, xf);
+            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, L.J, xf);
             d = (double)xf;
         } else {
-            ok = lu_solve<NPAD, double>(arow, bi, N, lane, L.J, L.W, d);
+            ok = lu_solve<NPAD, double>(arow, bi, N, lane, L.J, d);
         }
         if (!ok) return false;
         wave_sync();
