@@ -87,16 +87,9 @@ struct RxnCoef {
     double colc[6];
 };
 
-// Third-body reaction (one slot per such reaction): the Jacobian rows it writes (participants
-// with a nonzero net coefficient).
-struct TbRec {
-    int8_t nrow;
-    int8_t row[7];
-};
-static_assert(sizeof(TbRec) == 8, "third-body record must stay 8 bytes");
-
 struct WaveTables {
     int ns, nr, ntb, nchunk;  // ntb: third-body reactions (each has a slot; RxnRec::tb is the slot)
+    int ntbe;                 // third-body Jacobian entries (slot, row) over all slots
     double lnPaR;           // ln(P_atm / R) in CGS units
     const double *nasa;     // [ns][14]
     const double *Tmid;     // [ns]
@@ -105,8 +98,8 @@ struct WaveTables {
     const RxnRec *rxc;      // [nr]
     const RxnCoef *rxk;     // [nr]
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
-    const double *effR;     // [ntb][6][ns] per slot and row i: nu_ri M_i eff_rk / M_k
-    const TbRec *tbr;       // [ntb] per slot
+    const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
+    const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
 };
 
 // Device layout of one instance's arena (n cells, ns species), from its base address:

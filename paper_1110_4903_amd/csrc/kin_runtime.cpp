@@ -299,8 +299,6 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         }
     }
     std::vector<RxnCoef> rxk(nr);
-    std::vector<TbRec> tbr((size_t)std::max(1, ntb));
-    std::memset(tbr.data(), 0, sizeof(TbRec) * tbr.size());
     for (int r = 0; r < nr; ++r) {
         const Rxn &x = h.rx[r];
         RxnCoef &k = rxk[r];
@@ -309,22 +307,24 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
         }
     }
-    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR((size_t)std::max(1, ntb * 6 * ns), 0.0);
+    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR;
+    std::vector<int> tbe;
     for (int r = 0; r < nr; ++r) {
         const int q = slot[r];
         if (q < 0) continue;
         const Rxn &x = h.rx[r];
-        TbRec &t = tbr[q];
         for (int j = 0; j < x.npart; ++j) {
             if (!x.part[j].nu) continue;
-            const double cs = (double)x.part[j].nu * h.M[x.part[j].sp];
-            for (int k = 0; k < ns; ++k)
-                effR[((size_t)q * 6 + t.nrow) * ns + k] = cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k];
-            t.row[t.nrow] = (int8_t)x.part[j].sp;
-            ++t.nrow;
+            const int s = x.part[j].sp;
+            const double cs = (double)x.part[j].nu * h.M[s];
+            tbe.push_back(q | (s << 16));
+            for (int k = 0; k < ns; ++k) effR.push_back(cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k]);
         }
         for (int k = 0; k < ns; ++k) effT[(size_t)k * ntb + q] = h.eff[(size_t)slot_row[q] * ns + k];
     }
+    const int ntbe = (int)tbe.size();
+    if (tbe.empty()) tbe.push_back(0);
+    if (effR.empty()) effR.push_back(0.0);
     // one allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pc = {
@@ -332,7 +332,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
-        {tbr.data(), sizeof(TbRec) * tbr.size(), 0}};
+        {tbe.data(), sizeof(int) * tbe.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -342,7 +342,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     KIN_HIP(ctx, hipMemcpy(m.dbuf, host.data(), total, hipMemcpyHostToDevice));
     char *b = static_cast<char *>(m.dbuf);
     WaveTables &t = m.tab;
-    t.ns = ns; t.nr = nr; t.ntb = ntb; t.nchunk = nchunk;
+    t.ns = ns; t.nr = nr; t.ntb = ntb; t.nchunk = nchunk; t.ntbe = ntbe;
     t.lnPaR = std::log(kPatmCgs / kRuCgs);
     t.nasa = reinterpret_cast<const double *>(b + pc[0].off);
     t.Tmid = reinterpret_cast<const double *>(b + pc[1].off);
@@ -352,7 +352,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.rxk = reinterpret_cast<const RxnCoef *>(b + pc[5].off);
     t.effT = reinterpret_cast<const double *>(b + pc[6].off);
     t.effR = reinterpret_cast<const double *>(b + pc[7].off);
-    t.tbr = reinterpret_cast<const TbRec *>(b + pc[8].off);
+    t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
     return KIN_OK;
 }
 

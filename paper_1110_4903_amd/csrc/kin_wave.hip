@@ -90,7 +90,8 @@ __device__ __forceinline__ double wave_sum(double v)
 template <typename R>
 __device__ __forceinline__ void piv_take(R &v, int &p, R ov, int op)
 {
-    const bool take = (ov > v) || (ov == v && op < p);
+    // bitwise, not short-circuit: no branches inside the butterfly
+    const bool take = (ov > v) | ((ov == v) & (op < p));
     v = take ? ov : v;
     p = take ? op : p;
 }
@@ -386,20 +387,25 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         }
     }
     wave_sync();
-    // dense third-body terms: lane k adds nu_rs M_s (q_f - q_b) eff_rk / M_k to J[s][k]
-    if (lane < ns) {
-        const double *er = t.effR + lane;
-#pragma unroll 2
-        for (int tb = 0; tb < t.ntb; ++tb) {
-            const TbRec rec = t.tbr[tb];
-            const double D = L.DTB[tb];
-            const double *e = er + (size_t)tb * 6 * ns;
-            double v[6];
+    // dense third-body terms: lane k adds nu_rs M_s (q_f - q_b) eff_rk / M_k to J[s][k], one
+    // (reaction, row) entry per step, eight entries per batch so that their loads overlap
+    {
+        const bool col = lane < ns;
+        const double *er = t.effR + (col ? lane : 0);
+        for (int e0 = 0; e0 < t.ntbe; e0 += 8) {
+            int ent[8];
+            double v[8], D[8];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) v[i] = (i < rec.nrow) ? e[(size_t)i * ns] : 0.0;
+            for (int q = 0; q < 8; ++q) {
+                const int e = e0 + q < t.ntbe ? e0 + q : t.ntbe - 1;
+                ent[q] = t.tbe[e];
+                v[q] = er[(size_t)e * ns];
+            }
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
-                if (i < rec.nrow) lds_add(L.J + (size_t)rec.row[i] * JS + lane, D * v[i]);
+            for (int q = 0; q < 8; ++q) D[q] = L.DTB[ent[q] & 0xffff];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (col && e0 + q < t.ntbe) lds_add(L.J + (size_t)(ent[q] >> 16) * JS + lane, D[q] * v[q]);
         }
     }
     wave_sync();
