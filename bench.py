@@ -1,21 +1,34 @@
 """Benchmark of the implicit chemical-kinetics update on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--quick]
+                    [--no-batch] [--no-serve] [--serve-requests R]
 
-Workload (the headline): the 9-species/38-reaction synthetic mechanism on a 1024 x 1024 grid
-(2^20 cells, shock-heated band temperature field), advanced K steps of dt = 1e-6 s (default
-K = 10), state resident in HBM.  A "step" advances every cell by one dt through the whole
-hot path (rates, equilibrium constants, Jacobian, LU, Newton, sub-step halving, temperature
-inversion).  It is timed for the plain FP64 form (the reported value) and for the FP32-LU
-form; the 36-species/308-reaction mechanism on 2^18 cells (one step) is timed beside it.
+Headline (the reported value): the 9-species / 38-reaction synthetic mechanism on a 1024 x 1024
+grid (2^20 cells, shock-heated band temperature field), advanced K steps of dt = 1e-6 s
+(default K = 10) with the state resident in HBM, plain FP64 form.  A "step" advances every
+cell by one dt through the whole hot path: rates, equilibrium constants, third-body sums,
+analytic Jacobian, partially pivoted LU of I - hJ, Newton iteration, sub-step halving and the
+temperature inversion.  Also measured and reported under "forms":
+  * the same grid in the FP32-LU form, with its deviation from the FP64 form;
+  * the 36-species / 308-reaction mechanism on 2^18 cells, one step, both forms;
+  * an uneven batch of 64 instances of both mechanisms (log-uniform 1024..262144 cells, dt
+    uniform in [1e-7, 1e-5] s) advanced in one graph launch in the FP32-LU form after the
+    autotuner has chosen each mechanism's layout, against 64 separate launches;
+  * the serving loop: Poisson arrivals at 0.5, 0.8 and 0.95 of the measured saturated rate,
+    log-normal request sizes (median 16384 cells), 70/30 mix of the two mechanisms, admission
+    by HBM footprint under a 256 MiB budget, p50/p99 latency from arrival to results in host
+    memory.
+The FP64 CPU oracle is timed on a strided sample of the headline grid on the host cores.
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -25,57 +38,73 @@ sys.path.insert(0, HERE)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "traffic_kin_lane_f64_mech9_grid1024.txt")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def device_state(torch, st):
-    d = dict(rho=torch.from_numpy(st.rho).cuda(), T=torch.from_numpy(st.T).cuda(),
-             Y=torch.from_numpy(st.Y).cuda())
-    return d
+    return dict(rho=torch.from_numpy(st.rho).cuda(), T=torch.from_numpy(st.T).cuda(),
+                Y=torch.from_numpy(st.Y).cuda())
 
 
-def time_steps(torch, ctx, kin, iid, state, dt, prec, steps, warmup, stream):
-    """Warm up, reset to the input state, then time `steps` advance calls with HIP events on
+def time_steps(torch, ctx, iid, state, dt, prec, steps, warmup, stream):
+    """Warm up, reset to the input state, then time `steps` advance calls with events recorded on
     the launch stream.  Returns (total_s, per-launch seconds)."""
     for _ in range(warmup):
         ctx.advance([iid], [dt], prec=prec, stream=stream)
     ctx.state_reset(iid, state["rho"], state["T"], state["Y"], stream=stream)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    with torch.cuda.stream(stream):
-        ev[0].record(stream)
-        for k in range(steps):
-            ctx.advance([iid], [dt], prec=prec, stream=stream)
-            ev[k + 1].record(stream)
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.advance([iid], [dt], prec=prec, stream=stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
     per = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(steps)]
     return sum(per), per
 
 
 def replay_stats(torch, ctx, iid, state, dt, prec, steps, stream):
-    """Untimed replay of the same steps collecting per-step diagnostics."""
+    """Untimed replay of the same steps collecting per-step diagnostics (the kernels are
+    deterministic, so the replay takes the same iterations as the timed run)."""
     ctx.state_reset(iid, state["rho"], state["T"], state["Y"], stream=stream)
     its, st_hist, lv_max = [], np.zeros(4, np.int64), 0
     out = None
     for _ in range(steps):
         ctx.advance([iid], [dt], prec=prec, stream=stream)
         torch.cuda.synchronize()
-        out = ctx.download(iid)
+        out = ctx.download(iid) + (ctx.download_schedule(iid),)
         its.append(int(out[4].astype(np.int64).sum()))
         st_hist += np.bincount(out[2], minlength=4)[:4]
         lv_max = max(lv_max, int(out[3].max()))
     return its, st_hist, lv_max, out
 
 
-def run_gpu(args):
-    import torch
-    from paper_1110_4903_amd import flops, kin, synth
+def form_stats(n, steps, tot, per, its, hist, lvmax, flops_per_iter):
+    return dict(cells=n, steps=steps, seconds=tot, cells_per_s=n * steps / tot,
+                kernel_ms_avg=1e3 * float(np.mean(per)),
+                newton_iters_per_cell=float(np.sum(its)) / (n * steps),
+                status_hist=hist.tolist(), max_level=lvmax,
+                tflops_model=float(np.mean([flops_per_iter * it / p / 1e12 for it, p in zip(its, per)])))
 
-    torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    ctx = kin.Context(0)
-    res = {}
 
-    # ---- headline: mech9 on the 1024x1024 band grid, K steps ------------------------------
+def deviation(a, b):
+    """Relative deviation of form b from form a over cells whose status, level and sub-step
+    schedule agree (the others took different step sizes and are counted)."""
+    same = (a[2] == b[2]) & (a[3] == b[3]) & (a[5] == b[5]) & (a[2] < 2)
+    Ya, Yb = a[1][:, same], b[1][:, same]
+    big = np.abs(Ya) >= 1e-14
+    rel = np.where(big, np.abs(Yb - Ya) / np.maximum(np.abs(Ya), 1e-300), 0.0)
+    relT = np.abs(b[0][same] - a[0][same]) / a[0][same]
+    return dict(compared=int(same.sum()), schedule_differs=int((~same).sum()),
+                max_rel_Y=float(rel.max()) if rel.size else 0.0,
+                max_rel_T=float(relT.max()) if relT.size else 0.0)
+
+
+def run_headline(torch, ctx, kin, flops, synth, args, stream):
     nx = 256 if args.quick else 1024
     m9, grid, dt9 = synth.workload_grid_mech9(nx, nx)
     t0 = time.time()
@@ -85,33 +114,176 @@ def run_gpu(args):
     iid9 = ctx.state_upload(mid9, st9["rho"], st9["T"], st9["Y"], stream=stream)
     torch.cuda.synchronize()
     f9 = flops.newton_iteration_flops(m9)["total"]
-    for name, prec in (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU)):
-        tot, per = time_steps(torch, ctx, kin, iid9, st9, dt9, prec, args.steps, args.warmup, stream)
+    res, outs = {}, {}
+    forms = (("fp64", kin.FP64),) if args.only == "headline" else (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU))
+    for name, prec in forms:
+        log(f"mech9 grid {nx}x{nx}, {args.steps} steps, {name}")
+        tot, per = time_steps(torch, ctx, iid9, st9, dt9, prec, args.steps, args.warmup, stream)
         its, hist, lvmax, _ = replay_stats(torch, ctx, iid9, st9, dt9, prec, args.steps, stream)
-        achieved = [f9 * it / p / 1e12 for it, p in zip(its, per)]
-        res[f"mech9_{name}"] = dict(
-            cells=grid.n, steps=args.steps, seconds=tot, cells_per_s=grid.n * args.steps / tot,
-            kernel_ms_avg=1e3 * float(np.mean(per)), newton_iters_per_cell=float(np.sum(its)) / (grid.n * args.steps),
-            status_hist=hist.tolist(), max_level=lvmax, tflops_model=float(np.mean(achieved)))
+        res[f"mech9_{name}"] = form_stats(grid.n, args.steps, tot, per, its, hist, lvmax, f9)
+        # one step from the input state, for the deviation between the forms
+        outs[name] = replay_stats(torch, ctx, iid9, st9, dt9, prec, 1, stream)[3]
+    if "fp32lu" in outs:
+        res["mech9_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
     res["mech9_jit_s"] = jit9
+    res["mech9_layout"] = [ctx.query_int(kin.Q_LAYOUT, mid9), ctx.query_int(kin.Q_BLOCK, mid9)]
     ctx.instance_release(iid9)
+    ctx.mech_release(mid9)
+    return res, grid, m9, dt9
 
-    # ---- mech36, 2^18 cells, one step ------------------------------------------------------
+
+def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     n36 = (1 << 14) if args.quick else (1 << 18)
     m36, s36, dt36 = synth.workload_mech36(n36)
     mid36 = ctx.mech_upload(m36)
     st36 = device_state(torch, s36)
     iid36 = ctx.state_upload(mid36, st36["rho"], st36["T"], st36["Y"], stream=stream)
     f36 = flops.newton_iteration_flops(m36)["total"]
-    steps36 = 1
+    res, outs = {}, {}
     for name, prec in (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU)):
-        tot, per = time_steps(torch, ctx, kin, iid36, st36, dt36, prec, steps36, 1, stream)
-        its, hist, lvmax, _ = replay_stats(torch, ctx, iid36, st36, dt36, prec, steps36, stream)
-        res[f"mech36_{name}"] = dict(
-            cells=n36, steps=steps36, seconds=tot, cells_per_s=n36 * steps36 / tot,
-            kernel_ms_avg=1e3 * float(np.mean(per)), newton_iters_per_cell=float(np.sum(its)) / (n36 * steps36),
-            status_hist=hist.tolist(), max_level=lvmax, tflops_model=f36 * its[0] / per[0] / 1e12)
-    ctx.close()
+        log(f"mech36 {n36} cells, 1 step, {name}")
+        tot, per = time_steps(torch, ctx, iid36, st36, dt36, prec, 1, 1, stream)
+        its, hist, lvmax, out = replay_stats(torch, ctx, iid36, st36, dt36, prec, 1, stream)
+        res[f"mech36_{name}"] = form_stats(n36, 1, tot, per, its, hist, lvmax, f36)
+        outs[name] = out
+    res["mech36_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
+    res["mech36_layout"] = [ctx.query_int(kin.Q_LAYOUT, mid36), ctx.query_int(kin.Q_BLOCK, mid36)]
+    ctx.instance_release(iid36)
+    ctx.mech_release(mid36)
+    return res
+
+
+def run_batch(torch, kin, synth, args, stream):
+    """64 uneven instances, FP32-LU, one graph launch vs 64 separate launches."""
+    n_inst = 16 if args.quick else 64
+    hi = 16384 if args.quick else 262144
+    insts = synth.batch_instances(seed=3, n_inst=n_inst, min_cells=1024, max_cells=hi)
+    cache = os.path.join(tempfile.mkdtemp(prefix="kin_tune_"), "tune.json")
+    res = {}
+    with kin.Context(0, tune_cache=cache) as ctx:
+        mids = {}
+        for name in ("mech9", "mech36"):
+            m = synth.mechanism(name)
+            mids[name] = ctx.mech_upload(m)
+            probe = synth.uniform_cells(7, 16384 if not args.quick else 4096, m.ns, 1.0 if name == "mech9" else 0.5)
+            pid = ctx.state_upload(mids[name], probe.rho, probe.T, probe.Y)
+            log(f"autotune {name}")
+            lay, blk, ms = ctx.autotune(mids[name], pid, 1e-6, kin.FP32_LU)
+            res[f"autotune_{name}"] = dict(layout="lane" if lay == kin.LAYOUT_LANE else "wave", block=blk, ms=ms)
+            ctx.instance_release(pid)
+        states, ids = [], []
+        for ins in insts:
+            st = device_state(torch, ins.states())
+            states.append(st)
+            ids.append(ctx.state_upload(mids[ins.mech], st["rho"], st["T"], st["Y"], stream=stream))
+        dts = [ins.dt for ins in insts]
+        cells = sum(ins.n_cells for ins in insts)
+
+        def reset():
+            for i, st in zip(ids, states):
+                ctx.state_reset(i, st["rho"], st["T"], st["Y"], stream=stream)
+            torch.cuda.synchronize()
+
+        def snapshot():
+            out = []
+            for i, ins in zip(ids, insts):
+                ns = synth.mechanism(ins.mech).ns
+                T = torch.empty(ins.n_cells, dtype=torch.float64, device="cuda")
+                Y = torch.empty((ns, ins.n_cells), dtype=torch.float64, device="cuda")
+                ctx.download_device(i, T, Y, stream=stream)
+                out.append((T, Y))
+            torch.cuda.synchronize()
+            return out
+
+        log(f"batch of {len(insts)} instances, {cells} cells: graph build")
+        ctx.advance(ids, dts, prec=kin.FP32_LU, stream=stream)   # builds and caches the graph
+        reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        log("batch: one graph launch")
+        e0.record(stream)
+        ctx.advance(ids, dts, prec=kin.FP32_LU, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_graph = e0.elapsed_time(e1) * 1e-3
+        g = snapshot()
+        reset()
+        log("batch: 64 separate launches")
+        e0.record(stream)
+        for i, dt in zip(ids, dts):
+            ctx.advance([i], [dt], prec=kin.FP32_LU, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_sep = e0.elapsed_time(e1) * 1e-3
+        s = snapshot()
+        same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(g, s))
+        res.update(instances=len(insts), cells=cells, graph_s=t_graph, separate_s=t_sep,
+                   cells_per_s_graph=cells / t_graph, cells_per_s_separate=cells / t_sep,
+                   graph_equals_separate_bitwise=bool(same))
+        for i in ids:
+            ctx.instance_release(i)
+    return res
+
+
+def run_serving(torch, kin, serve, synth, args):
+    """Calibrate the saturated rate with every request present at t = 0, then serve Poisson
+    arrivals at fractions of it."""
+    n_req = 20 if args.quick else args.serve_requests
+    budget = 256 << 20
+    out = {}
+    with kin.Context(0, hbm_budget=budget) as ctx:
+        mids = {name: ctx.mech_upload(synth.mechanism(name)) for name in ("mech9", "mech36")}
+        for name, prec, loads in (("fp32lu", kin.FP32_LU, (0.5, 0.8, 0.95)), ("fp64", kin.FP64, (0.8,))):
+            be = serve.KinBackend(ctx, mids, prec, n_slots=16)
+            reqs = synth.serving_requests(4, n_req, rate_per_s=1.0)
+            jobs = serve.make_jobs(reqs, time_scale=0.0)
+            for j, r in zip(jobs, reqs):
+                be.prepare(j, r.inst.states())
+            log(f"serving {name}: saturation run, {n_req} requests")
+            sat = serve.run(jobs, be, budget, 16).summary()
+            rate = sat["cells_per_s"] / synth.mean_request_cells()
+            runs = {"saturated": sat}
+            for load in loads:
+                reqs = synth.serving_requests(4, n_req, rate_per_s=load * rate)
+                jobs = serve.make_jobs(reqs)
+                for j, r in zip(jobs, reqs):
+                    be.prepare(j, r.inst.states())
+                log(f"serving {name}: load {load}")
+                runs[f"load_{load}"] = serve.run(jobs, be, budget, 16).summary()
+            out[name] = runs
+    return out
+
+
+def run_copy(torch):
+    """A plain device-to-device copy of 512 MiB (torch's copy kernel): the reference for scaling
+    the HBM byte counters."""
+    a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}
+
+
+def run_gpu(args):
+    import torch
+    from paper_1110_4903_amd import flops, kin, serve, synth
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    res = {}
+    grid = m9 = dt9 = None
+    if args.only == "copy":
+        return run_copy(torch), None, None, None
+    with kin.Context(0) as ctx:
+        if args.only in ("all", "headline"):
+            head, grid, m9, dt9 = run_headline(torch, ctx, kin, flops, synth, args, stream)
+            res.update(head)
+        if args.only in ("all", "mech36"):
+            res.update(run_mech36(torch, ctx, kin, flops, synth, args, stream))
+    if args.only in ("all", "batch") and not args.no_batch:
+        res["batch64"] = run_batch(torch, kin, synth, args, stream)
+    if args.only in ("all", "serve") and not args.no_serve:
+        res["serving"] = run_serving(torch, kin, serve, synth, args)
     return res, grid, m9, dt9
 
 
@@ -128,8 +300,31 @@ def cpu_baseline(grid, m9, dt9, steps, sample_stride):
         T, Y, _, _, _ = om.advance(sub.rho, T, Y, dt9, e0=e0)
     el = time.time() - t0
     return dict(value=idx.shape[0] * steps / el, unit="cells/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{idx.shape[0]} cells (every {sample_stride}th of the 1024x1024 grid) x {steps} steps "
-                       f"of dt=1e-6 s, FP64, {el:.1f} s")
+                sample=f"{idx.shape[0]} cells (every {sample_stride}th of the {int(np.sqrt(grid.n))}^2 grid) x "
+                       f"{steps} steps of dt=1e-6 s, FP64, {el:.1f} s")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that define the headline kernel (lane layout): template and
+    generator.  A traffic figure measured for another hash is stale."""
+    h = hashlib.sha256()
+    for f in ("kin_lane_template.h", "kin_codegen.cpp"):
+        with open(os.path.join(HERE, "paper_1110_4903_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch_cells):
+    """HBM bytes per launch of the headline kernel from the committed counter summary, scaled
+    to this launch's cell count; None when the summary is missing or the kernel has changed."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.split("=", 1) for line in f.read().splitlines() if "=" in line and not line.startswith("#"))
+        if kv.get("kernel_source_hash", "").strip() != kernel_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_cell_step"]) * launch_cells
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -138,17 +333,28 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="small grid, for smoke runs")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=80)
+    ap.add_argument("--quick", action="store_true", help="small sizes, for smoke runs")
+    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "batch", "serve", "copy"),
+                    help="run one part (for profiler runs); the JSON line needs the headline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the per-cell kinetics update has "
-                                   "no cross-GPU exchange (cells shard trivially), so --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU: the per-cell kinetics update has no "
+                                   "cross-GPU exchange (cells shard trivially), so --gpus must be 1"}))
         sys.exit(2)
     res, grid, m9, dt9 = run_gpu(args)
+    if grid is None:
+        print(json.dumps({"only": args.only, "forms": res}))
+        return
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(grid, m9, dt9, args.steps, 16 if not args.quick else 4)
+    if not args.no_cpu and args.only == "all":
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(grid, m9, dt9, args.steps, 1 if not args.quick else 4)
     h = res["mech9_fp64"]
+    traffic = measured_traffic(grid.n)
+    side = int(np.sqrt(grid.n))
     line = {
         "metric": "cells/s advanced one dt (9-sp & 36-sp), FP32-LU vs FP64 at stated err; p99 latency",
         "value": h["cells_per_s"],
@@ -162,11 +368,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"mech9 (9 species, 38 reactions) on a {int(np.sqrt(grid.n))}x{int(np.sqrt(grid.n))} "
-                               f"band grid, {args.steps} steps of dt=1e-6 s, FP64 form, state resident in HBM",
+        "config": {"workload": f"mech9 (9 species, 38 reactions) on a {side}x{side} band grid, {args.steps} steps "
+                               f"of dt=1e-6 s, FP64 form, state resident in HBM",
                    "cells": grid.n, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": h["tflops_model"], "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": h["tflops_model"] / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": h["tflops_model"] / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "kin_lane_f64"},
         "cpu_baseline": cpu,
         "forms": res,
