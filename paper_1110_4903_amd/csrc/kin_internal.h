@@ -94,12 +94,15 @@ struct WaveTables {
     const double *nasa;     // [ns][14]
     const double *Tmid;     // [ns]
     const double *M;        // [ns] g/mol
+    // reaction tables are stored in order of participant count (not the mechanism's order)
     const double *rxd;      // [nr][4]: ln A, b, Ta, sum nu
     const RxnRec *rxc;      // [nr]
     const RxnCoef *rxk;     // [nr]
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
     const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
     const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
+    const unsigned *pslot;  // [nr] per participant j, bits 4j..4j+3: reactant slot | product slot << 2 (3 = none)
+    const int *chunk_np;    // [nchunk] largest participant count of each pass of 64 reactions
 };
 
 // Device layout of one instance's arena (n cells, ns species), from its base address:

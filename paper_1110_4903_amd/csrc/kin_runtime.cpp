@@ -275,15 +275,35 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             slot_row.push_back(h.rx[r].tb);
         }
     const int ntb = (int)slot_row.size();
+    // reactions in order of participant count, so that each pass of 64 lanes is homogeneous
+    // and its loops over participants stop at the pass's largest count
+    std::vector<int> perm(nr);
+    for (int r = 0; r < nr; ++r) perm[r] = r;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return h.rx[a].npart < h.rx[b].npart; });
+    std::vector<int> chunk_np(nchunk, 0);
+    for (int i = 0; i < nr; ++i) chunk_np[i / kChunk] = std::max(chunk_np[i / kChunk], h.rx[perm[i]].npart);
     std::vector<double> rxd((size_t)nr * 4);
     std::vector<RxnRec> rxc(nr);
-    for (int r = 0; r < nr; ++r) {
+    std::vector<unsigned> pslot(nr, 0u);
+    for (int i = 0; i < nr; ++i) {
+        const int r = perm[i];
         const Rxn &x = h.rx[r];
-        rxd[4 * r + 0] = x.lnA;
-        rxd[4 * r + 1] = x.b;
-        rxd[4 * r + 2] = x.Ta;
-        rxd[4 * r + 3] = (double)x.dnu;
-        RxnRec &p = rxc[r];
+        // per participant j, 4 bits: reactant slot (bits 0-1, 3 = none), product slot (bits 2-3)
+        unsigned ps = 0;
+        for (int j = 0; j < 6; ++j) {
+            unsigned rs = 3, qs = 3;
+            if (j < x.npart) {
+                for (int m = 0; m < x.nreac; ++m) if (x.reac_sp[m] == x.part[j].sp) rs = (unsigned)m;
+                for (int m = 0; m < x.nprod; ++m) if (x.prod_sp[m] == x.part[j].sp) qs = (unsigned)m;
+            }
+            ps |= (rs | (qs << 2)) << (4 * j);
+        }
+        pslot[i] = ps;
+        rxd[4 * i + 0] = x.lnA;
+        rxd[4 * i + 1] = x.b;
+        rxd[4 * i + 2] = x.Ta;
+        rxd[4 * i + 3] = (double)x.dnu;
+        RxnRec &p = rxc[i];
         std::memset(&p, 0, sizeof p);
         p.rev = (int8_t)x.rev; p.nreac = (int8_t)x.nreac; p.nprod = (int8_t)x.nprod;
         p.npart = (int8_t)x.npart; p.tb = (int16_t)slot[r];
@@ -299,9 +319,9 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         }
     }
     std::vector<RxnCoef> rxk(nr);
-    for (int r = 0; r < nr; ++r) {
-        const Rxn &x = h.rx[r];
-        RxnCoef &k = rxk[r];
+    for (int i = 0; i < nr; ++i) {
+        const Rxn &x = h.rx[perm[i]];
+        RxnCoef &k = rxk[i];
         for (int j = 0; j < 6; ++j) {
             k.rowc[j] = j < x.npart ? (double)x.part[j].nu * h.M[x.part[j].sp] : 0.0;
             k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
@@ -332,7 +352,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
-        {tbe.data(), sizeof(int) * tbe.size(), 0}};
+        {tbe.data(), sizeof(int) * tbe.size(), 0}, {pslot.data(), sizeof(unsigned) * pslot.size(), 0},
+        {chunk_np.data(), sizeof(int) * chunk_np.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -353,6 +374,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.effT = reinterpret_cast<const double *>(b + pc[6].off);
     t.effR = reinterpret_cast<const double *>(b + pc[7].off);
     t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
+    t.pslot = reinterpret_cast<const unsigned *>(b + pc[9].off);
+    t.chunk_np = reinterpret_cast<const int *>(b + pc[10].off);
     return KIN_OK;
 }
 

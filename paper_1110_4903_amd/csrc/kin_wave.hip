@@ -253,7 +253,8 @@ __device__ __forceinline__ double dcpow_nu(double c, int nu)
 //   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  WT[s] += nu_rs dQ_r/dT.
 template <int NPAD>
 __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
-                                               const double4 &rd, double iT, double lT, double lPaRT)
+                                               const double4 &rd, unsigned ps, int npmax, double iT,
+                                               double lT, double lPaRT)
 {
     const double lnA = rd.x, b = rd.y, Ta = rd.z, dnu = rd.w;
     const RxnCoef *kc = t.rxk + r;
@@ -278,7 +279,7 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
         double sg = 0.0, sh = 0.0;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            if (j < x.npart) {
+            if (j < npmax && j < x.npart) {
                 const double nu = (double)x.part_nu[j];
                 sg = fma(nu, L.g[x.part_sp[j]], sg);
                 sh = fma(nu, L.hh[x.part_sp[j]], sh);
@@ -306,22 +307,24 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
     const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
     if (x.tb >= 0) L.DTB[x.tb] = D;
     // dQ/dc_k / M_k for each participant k
+    // participant j takes d/dc of its reactant slot's term minus its product slot's term
+    // (species are merged within each side, so each side has at most one slot)
     double dq[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const int sp = x.part_sp[j];
-        double gf = 0.0, gb = 0.0;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            gf += (m < x.nreac && x.reac_sp[m] == sp) ? dpf[m] : 0.0;
-            gb += (m < x.nprod && x.prod_sp[m] == sp) ? dpb[m] : 0.0;
+        if (j < npmax) {
+            const unsigned rs = (ps >> (4 * j)) & 3u, qs = (ps >> (4 * j + 2)) & 3u;
+            const double gf = rs == 0 ? dpf[0] : (rs == 1 ? dpf[1] : (rs == 2 ? dpf[2] : 0.0));
+            const double gb = qs == 0 ? dpb[0] : (qs == 1 ? dpb[1] : (qs == 2 ? dpb[2] : 0.0));
+            dq[j] = Mc * (gf - gb) * kc->colc[j];
+        } else {
+            dq[j] = 0.0;
         }
-        dq[j] = Mc * (gf - gb) * kc->colc[j];
     }
     const int JS = NPAD;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        if (i < x.npart && x.part_nu[i] != 0) {
+        if (i < npmax && i < x.npart && x.part_nu[i] != 0) {
             const int si = x.part_sp[i];
             const double nu = (double)x.part_nu[i];
             const double a = kc->rowc[i];
@@ -330,7 +333,7 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
             double *Jr = L.J + (size_t)si * JS;
 #pragma unroll
             for (int j = 0; j < 6; ++j)
-                if (j < x.npart) lds_add(Jr + x.part_sp[j], a * dq[j]);
+                if (j < npmax && j < x.npart) lds_add(Jr + x.part_sp[j], a * dq[j]);
         }
     }
 }
@@ -377,13 +380,16 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         const double4 *rxd4 = reinterpret_cast<const double4 *>(t.rxd);
         RxnRec xn{};
         double4 rn{};
-        if (lane < t.nr) { xn = t.rxc[lane]; rn = rxd4[lane]; }
+        unsigned pn = 0u;
+        if (lane < t.nr) { xn = t.rxc[lane]; rn = rxd4[lane]; pn = t.pslot[lane]; }
         for (int r0 = 0; r0 < t.nr; r0 += kW) {
             const int r = r0 + lane;
             const RxnRec x = xn;
             const double4 rd = rn;
-            if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; }
-            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, iT, lT, lPaRT);
+            const unsigned ps = pn;
+            const int npmax = t.chunk_np[r0 / kW];
+            if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; pn = t.pslot[r + kW]; }
+            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, ps, npmax, iT, lT, lPaRT);
         }
     }
     wave_sync();
