@@ -85,38 +85,73 @@ __device__ __forceinline__ double wave_sum(double v)
     return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
 }
 
-// Pivot choice: the largest v, ties to the lowest position p.  The order is total, so any
-// combining tree gives the same winner.
-template <typename R>
-__device__ __forceinline__ void piv_take(R &v, int &p, R ov, int op)
+// Pivot search.  A non-negative floating-point value orders like its bit pattern read as an
+// unsigned integer, so the largest |a_ik| is an integer maximum of those patterns (rows out of
+// the search take key 0).  The lanes holding the maximum come from a ballot; when there are
+// several (an exact tie), the one of lowest current row position wins.
+template <typename R> struct PivKey;
+template <> struct PivKey<double> { using T = unsigned long long; };
+template <> struct PivKey<float> { using T = unsigned; };
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp(unsigned long long v)
 {
-    // bitwise, not short-circuit: no branches inside the butterfly
-    const bool take = (ov > v) | ((ov == v) & (op < p));
-    v = take ? ov : v;
-    p = take ? op : p;
+    const unsigned lo = (unsigned)dpp<CTRL>((int)(unsigned)v), hi = (unsigned)dpp<CTRL>((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
-template <int CTRL, typename R>
-__device__ __forceinline__ void piv_step(R &v, int &p)
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp(unsigned v)
 {
-    piv_take(v, p, dpp<CTRL>(v), dpp<CTRL>(p));
+    return (unsigned)dpp<CTRL>((int)v);
 }
 
-// On return every lane holds the wave-wide winner (v, p).
-template <typename R>
-__device__ __forceinline__ void wave_argmax(R &v, int &p)
+__device__ __forceinline__ unsigned long long rdlane(unsigned long long v, int l)
 {
-    piv_step<kDppX1>(v, p);
-    piv_step<kDppX2>(v, p);
-    piv_step<kDppHalfMirror>(v, p);
-    piv_step<kDppMirror>(v, p);
-    R bv = rdlane(v, 0);
-    int bp = rdlane(p, 0);
-    piv_take(bv, bp, rdlane(v, 16), rdlane(p, 16));
-    piv_take(bv, bp, rdlane(v, 32), rdlane(p, 32));
-    piv_take(bv, bp, rdlane(v, 48), rdlane(p, 48));
-    v = bv;
-    p = bp;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned rdlane(unsigned v, int l) { return (unsigned)__builtin_amdgcn_readlane((int)v, l); }
+
+template <typename K>
+__device__ __forceinline__ K kmax(K a, K b) { return a > b ? a : b; }
+
+// Wave-wide maximum; every lane returns the same value.
+template <typename K>
+__device__ __forceinline__ K wave_max(K v)
+{
+    v = kmax(v, dpp<kDppX1>(v));
+    v = kmax(v, dpp<kDppX2>(v));
+    v = kmax(v, dpp<kDppHalfMirror>(v));
+    v = kmax(v, dpp<kDppMirror>(v));
+    return kmax(kmax(rdlane(v, 0), rdlane(v, 16)), kmax(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// Wave-wide minimum of non-negative ints; every lane returns the same value.
+__device__ __forceinline__ int wave_min(int v)
+{
+    v = min(v, dpp<kDppX1>(v));
+    v = min(v, dpp<kDppX2>(v));
+    v = min(v, dpp<kDppHalfMirror>(v));
+    v = min(v, dpp<kDppMirror>(v));
+    return min(min(rdlane(v, 0), rdlane(v, 16)), min(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// Lane holding the pivot row among lanes with `cand` set; `nonzero` is false when the largest
+// candidate magnitude is zero.
+template <typename R>
+__device__ __forceinline__ int pivot_lane(R mag, bool cand, int pos, bool &nonzero)
+{
+    using K = typename PivKey<R>::T;
+    const K key = cand ? __builtin_bit_cast(K, mag) : K(0);
+    const K km = wave_max(key);
+    nonzero = km != K(0);
+    const unsigned long long m = __ballot(cand && key == km);
+    if (__builtin_popcountll(m) == 1) return __builtin_ctzll(m);
+    const int pmin = wave_min(((m >> __lane_id()) & 1ull) ? pos : 0x7fffffff);
+    return __builtin_ctzll(__ballot(pos == pmin));
 }
 
 // NASA-7 functions of species s at T from the table.
@@ -470,11 +505,10 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
         for (int kk = 0; kk < 4; ++kk) {
             const int k = 4 * blk + kk;
             if (k < N) {
-                R v = (pos >= k && lane < N) ? (R)fabs(a[kk]) : R(-1);
-                int p = pos;
-                wave_argmax(v, p);
-                ok = ok && (v > R(0));
-                const int w = __builtin_ctzll(__ballot(pos == p));
+                bool nz;
+                const int w = pivot_lane<R>((R)fabs(a[kk]), pos >= k && lane < N, pos, nz);
+                const int p = rdlane(pos, w);
+                ok = ok && nz;
                 pos = (lane == w) ? k : (pos == k ? p : pos);
                 myoff = (lane == k) ? off : myoff;
                 const R piv = rdlane(a[kk], w);
