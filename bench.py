@@ -50,31 +50,31 @@ def device_state(torch, st):
                 Y=torch.from_numpy(st.Y).cuda())
 
 
-def time_steps(torch, ctx, iid, state, dt, prec, steps, warmup, stream):
+def time_steps(torch, ctx, iid, state, dt, prec, steps, warmup, stream, opts=None):
     """Warm up, reset to the input state, then time `steps` advance calls with events recorded on
     the launch stream.  Returns (total_s, per-launch seconds)."""
     for _ in range(warmup):
-        ctx.advance([iid], [dt], prec=prec, stream=stream)
+        ctx.advance([iid], [dt], prec=prec, stream=stream, opts=opts)
     ctx.state_reset(iid, state["rho"], state["T"], state["Y"], stream=stream)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
     for k in range(steps):
-        ctx.advance([iid], [dt], prec=prec, stream=stream)
+        ctx.advance([iid], [dt], prec=prec, stream=stream, opts=opts)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     per = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(steps)]
     return sum(per), per
 
 
-def replay_stats(torch, ctx, iid, state, dt, prec, steps, stream):
+def replay_stats(torch, ctx, iid, state, dt, prec, steps, stream, opts=None):
     """Untimed replay of the same steps collecting per-step diagnostics (the kernels are
     deterministic, so the replay takes the same iterations as the timed run)."""
     ctx.state_reset(iid, state["rho"], state["T"], state["Y"], stream=stream)
     its, st_hist, lv_max = [], np.zeros(4, np.int64), 0
     out = None
     for _ in range(steps):
-        ctx.advance([iid], [dt], prec=prec, stream=stream)
+        ctx.advance([iid], [dt], prec=prec, stream=stream, opts=opts)
         torch.cuda.synchronize()
         out = ctx.download(iid) + (ctx.download_schedule(iid),)
         its.append(int(out[4].astype(np.int64).sum()))
@@ -89,6 +89,30 @@ def form_stats(n, steps, tot, per, its, hist, lvmax, flops_per_iter):
                 newton_iters_per_cell=float(np.sum(its)) / (n * steps),
                 status_hist=hist.tolist(), max_level=lvmax,
                 tflops_model=float(np.mean([flops_per_iter * it / p / 1e12 for it, p in zip(its, per)])))
+
+
+def method_difference(a, b):
+    """Relative difference between two methods' one-step results on cells both accepted."""
+    ok = (a[2] < 2) & (b[2] < 2)
+    Ya, Yb = a[1][:, ok], b[1][:, ok]
+    big = np.abs(Ya) >= 1e-6
+    rel = np.where(big, np.abs(Yb - Ya) / np.maximum(np.abs(Ya), 1e-300), 0.0)
+    relT = np.abs(b[0][ok] - a[0][ok]) / a[0][ok]
+    return {"both_accepted": int(ok.sum()), "failed_in_b": int((b[2] == 2).sum()),
+            "max_rel_Y_where_Y_ge_1e-6": float(rel.max()) if rel.size else 0.0,
+            "median_rel_Y_where_Y_ge_1e-6": float(np.median(rel[big])) if big.any() else 0.0,
+            "max_rel_T": float(relT.max()) if relT.size else 0.0}
+
+
+def point_implicit_form(torch, ctx, kin, iid, st, dt, steps, n, flops_per_iter, newton_one_step, stream):
+    """The paper's point-implicit step (one linearised backward-Euler step per dt), FP64."""
+    o = kin.solver_opts(point_implicit=1)
+    tot, per = time_steps(torch, ctx, iid, st, dt, kin.FP64, steps, 1, stream, opts=o)
+    its, hist, lvmax, _ = replay_stats(torch, ctx, iid, st, dt, kin.FP64, steps, stream, opts=o)
+    r = form_stats(n, steps, tot, per, its, hist, lvmax, flops_per_iter)
+    one = replay_stats(torch, ctx, iid, st, dt, kin.FP64, 1, stream, opts=o)[3]
+    r["difference_from_newton_be_one_step"] = method_difference(newton_one_step, one)
+    return r
 
 
 def deviation(a, b):
@@ -125,6 +149,9 @@ def run_headline(torch, ctx, kin, flops, synth, args, stream):
         outs[name] = replay_stats(torch, ctx, iid9, st9, dt9, prec, 1, stream)[3]
     if "fp32lu" in outs:
         res["mech9_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
+        log(f"mech9 grid {nx}x{nx}, {args.steps} steps, point-implicit")
+        res["mech9_point_implicit_fp64"] = point_implicit_form(torch, ctx, kin, iid9, st9, dt9, args.steps, grid.n,
+                                                               f9, outs["fp64"], stream)
     res["mech9_jit_s"] = jit9
     res["mech9_layout"] = [ctx.query_int(kin.Q_LAYOUT, mid9), ctx.query_int(kin.Q_BLOCK, mid9)]
     ctx.instance_release(iid9)
@@ -147,6 +174,9 @@ def run_mech36(torch, ctx, kin, flops, synth, args, stream):
         res[f"mech36_{name}"] = form_stats(n36, 1, tot, per, its, hist, lvmax, f36)
         outs[name] = out
     res["mech36_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
+    log(f"mech36 {n36} cells, 1 step, point-implicit")
+    res["mech36_point_implicit_fp64"] = point_implicit_form(torch, ctx, kin, iid36, st36, dt36, 1, n36, f36,
+                                                            outs["fp64"], stream)
     res["mech36_layout"] = [ctx.query_int(kin.Q_LAYOUT, mid36), ctx.query_int(kin.Q_BLOCK, mid36)]
     ctx.instance_release(iid36)
     ctx.mech_release(mid36)

@@ -101,7 +101,7 @@ typedef struct {
 
 /* Newton / sub-stepping controls.  Defaults (kin_default_solver_opts): rtol 1e-12,
  * atol_Y 1e-20, atol_T 1e-9 K, y_neg 1e-10, k_max 10, L_max 40, layout AUTO, L_forced -1,
- * max_iters 100000. */
+ * max_iters 100000, point_implicit 0. */
 typedef struct {
     double rtol;       /* Newton converged when |dx_i| <= atol_i + rtol |x_i| for all i */
     double atol_Y;
@@ -112,6 +112,15 @@ typedef struct {
     int32_t layout;    /* kin_layout */
     int32_t L_forced;  /* -1: adaptive; >= 0: exactly 2^L_forced equal sub-steps */
     int32_t max_iters; /* Newton iterations per cell before it is declared FAILED */
+    int32_t point_implicit; /* 1: the paper's point-implicit step (Sec. 3.2, Eq. "kinetics"):
+                             * one linearised backward-Euler step over the whole dt,
+                             * (I - dt J(x_n)) dx = dt f(x_n), taken without a convergence test
+                             * or a negative-Y check, followed by the temperature inversion.
+                             * k_max, L_max and L_forced are then ignored; a failure
+                             * (non-finite, zero pivot, T out of range) gives status 2.
+                             * FP64 only: without Newton's refinement an FP32 factorisation
+                             * of I - dt J carries its full rounding error into the result,
+                             * so kin_advance rejects it with KIN_EINVAL for KIN_FP32_LU. */
 } kin_solver_opts;
 
 void kin_default_solver_opts(kin_solver_opts *s);

@@ -72,6 +72,7 @@ void orc_default_opts(orc_opts *o)
     o->k_max = 10;
     o->L_max = 40;
     o->max_iters = 100000;
+    o->point_implicit = 0;
 }
 
 int orc_num_threads(void)
@@ -356,9 +357,11 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
             double atol = (i < ns) ? o->atol_Y : o->atol_T;
             if (!(fabs(d[i]) <= atol + o->rtol * fabs(xk[i]))) conv = 0;
         }
+        if (o->point_implicit) conv = 1;  /* the linearised step is taken as it is */
         if (conv) {
             int neg = 0;
-            for (int s = 0; s < ns; ++s) if (xk[s] < -o->y_neg) neg = 1;
+            if (!o->point_implicit)
+                for (int s = 0; s < ns; ++s) if (xk[s] < -o->y_neg) neg = 1;
             if (neg) break;
             if (x_be) memcpy(x_be, xk, sizeof(double) * N);
             double T;
@@ -394,6 +397,7 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
         return ORC_BAD_INPUT;
     memcpy(x, xn, sizeof(double) * N);
     int failed = 0;
+    if (o->point_implicit) L_forced = 0;  /* one step over dt, no halving */
     if (L_forced >= 0) {
         /* Replay: exactly 2^L equal sub-steps, no adaptation. */
         double h = ldexp(dt, -L_forced);

@@ -55,6 +55,11 @@ typedef struct {
     double y_neg;           /* a converged iterate with some Y_s < -y_neg is rejected */
     int k_max, L_max;
     int max_iters;          /* Newton iterations per cell before it is declared failed */
+    int point_implicit;     /* 1: the point-implicit step of Sec. 3.2 (Eq. "kinetics"): one
+                               linearised backward-Euler step over the whole dt,
+                               (I - dt J(x_n)) dx = dt f(x_n), accepted without a convergence
+                               test or a negative-Y check, then the temperature inversion; a
+                               failure (non-finite, zero pivot, T out of range) is final */
 } orc_opts;
 
 /* Per-cell status codes. */

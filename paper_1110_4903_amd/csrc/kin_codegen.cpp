@@ -375,7 +375,11 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
             "__device__ __forceinline__ kin_cptr kin_fence_k(kin_cptr p)\n{\n"
             "    asm volatile(\"\" : \"+s\"(p));\n    return p;\n}\n\n";
     consts = K.tab;
-    return head.str() + o.str() + kLaneTemplate;
+    // the launch passes the host's AdvanceArgs by value as the kernel's KinLaneArgs
+    std::ostringstream tail;
+    tail << "\nstatic_assert(sizeof(KinLaneArgs) == " << sizeof(AdvanceArgs)
+         << ", \"KinLaneArgs must mirror the host launch arguments\");\n";
+    return head.str() + o.str() + kLaneTemplate + tail.str();
 }
 
 kin_status rtc_compile(const std::string &src, const char *name, std::vector<char> &code,

@@ -158,6 +158,7 @@ struct AdvanceArgs {
     long long total;                 // cells over all spans
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
+    int point_implicit;              // 1: accept the first (linearised) update as it is
     const double *K;                 // lane layout: the mechanism's constant table
     unsigned long long *counter;     // next unclaimed cell (zero at launch)
 };

@@ -26,6 +26,7 @@ struct KinLaneArgs {
     long long total;      // cells over all spans
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
+    int point_implicit;   // 1: accept the first (linearised) update as it is
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
     unsigned long long *counter;  // next unclaimed global cell; zero at launch
 };
@@ -211,11 +212,11 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
     }
     if (!(chk2 == 0.0)) return KIN_ATTEMPT_FAILED;
     if (xk[KIN_NS] < KIN_T_MIN || xk[KIN_NS] > KIN_T_MAX) return KIN_ATTEMPT_FAILED;
-    if (!conv) return KIN_CONTINUE;
+    if (!conv && !a.point_implicit) return KIN_CONTINUE;
     bool neg = false;
 #pragma unroll
     for (int s = 0; s < KIN_NS; ++s) neg = neg || (xk[s] < -a.y_neg);
-    if (neg) return KIN_ATTEMPT_FAILED;
+    if (neg && !a.point_implicit) return KIN_ATTEMPT_FAILED;
     double T;
     if (!kin_invert_T(a.K, xk, e0, xk[KIN_NS], T)) return KIN_ATTEMPT_FAILED;
     xk[KIN_NS] = T;

@@ -168,6 +168,7 @@ void kin_default_solver_opts(kin_solver_opts *s)
     s->layout = KIN_LAYOUT_AUTO;
     s->L_forced = -1;
     s->max_iters = 100000;
+    s->point_implicit = 0;
 }
 
 const char *kin_last_error(void) { return g_err.c_str(); }
@@ -640,6 +641,11 @@ static void fill_opts(AdvanceArgs &a, const kin_solver_opts &o)
 {
     a.rtol = o.rtol; a.atol_Y = o.atol_Y; a.atol_T = o.atol_T; a.y_neg = o.y_neg;
     a.k_max = o.k_max; a.L_max = o.L_max; a.L_forced = o.L_forced; a.max_iters = o.max_iters;
+    a.point_implicit = o.point_implicit ? 1 : 0;
+    if (a.point_implicit) {  // one sub-step over dt, one (linearised) update
+        a.L_forced = 0;
+        a.k_max = 1;
+    }
 }
 
 // Effective (layout, block) of a mechanism for these options.
@@ -818,6 +824,8 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     kin_default_solver_opts(&o);
     if (sopt) o = *sopt;
     if (!opts_ok(o)) return err(KIN_EINVAL, "bad solver options");
+    if (o.point_implicit && prec != KIN_FP64)
+        return err(KIN_EINVAL, "the point-implicit step has no Newton refinement and runs in FP64 only");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     for (int k = 0; k < n; ++k) {
         auto it = ctx->insts.find(inst_ids[k]);

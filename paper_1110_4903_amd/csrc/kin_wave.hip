@@ -567,6 +567,7 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
 struct StepCtl {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max;
+    bool point_implicit;  // accept the first (linearised) update as it is
 };
 
 // One backward-Euler sub-step of size h.  xs (lane i: x_i) is updated on success.
@@ -625,9 +626,9 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
         if (__any(lane < N && !__builtin_isfinite(xk))) return false;
         const double T = rdlane(xk, ns);
         if (T < kTmin || T > kTmax) return false;
-        const bool conv = __all(lane >= N || fabs(d) <= atol + c.rtol * fabs(xk));
+        const bool conv = c.point_implicit || __all(lane >= N || fabs(d) <= atol + c.rtol * fabs(xk));
         if (conv) {
-            if (__any(lane < ns && xk < -c.y_neg)) return false;
+            if (!c.point_implicit && __any(lane < ns && xk < -c.y_neg)) return false;
             double Tn;
             if (!invert_T(t, lane, (lane < ns) ? xk : 0.0, e0, T, Tn)) return false;
             xs = (lane == ns) ? Tn : xk;
@@ -645,7 +646,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
     const int ns = t.ns, N = ns + 1;
     const Lds L = lds_map(smem + (size_t)wid * lds_doubles(N, t.ntb, NPAD), N, t.ntb, NPAD);
-    const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max};
+    const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max, a.point_implicit != 0};
     const double Ms = lane < ns ? t.M[lane] : 1.0;
     const double invMs = 1.0 / Ms;
     // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones

@@ -309,3 +309,31 @@ def test_autotune_restores_state_and_persists(ctx, tmp_path):
     with kin.Context(0, tune_cache=cache) as c2:
         mid = c2.mech_upload(m)
         assert c2.query_int(kin.Q_LAYOUT, mid) == lay and c2.query_int(kin.Q_BLOCK, mid) == blk
+
+
+def test_point_implicit_both_layouts(ctx, orc):
+    """The paper's point-implicit step (one linearised backward-Euler step over dt), FP64: mech9
+    through both layouts and mech36 through the wave layout, against the oracle.  Gate: 1e-10
+    relative plus the conditioning floor of a single linear solve
+    (tests/parity.point_implicit_floor); one iteration and level 0 everywhere.  The FP32-LU
+    form is refused for this step (no Newton refinement)."""
+    from tests.parity import compare, point_implicit_floor
+    from paper_1110_4903_amd import kin
+    prec, rtol, eps = 0, 1e-10, np.finfo(np.float64).eps
+    cases = [("mech9", synth.uniform_cells(23, 2000, 9, 1.0), 1e-7, kin.LAYOUT_LANE),
+             ("mech9", synth.uniform_cells(23, 2000, 9, 1.0), 1e-7, kin.LAYOUT_WAVE),
+             ("mech36", synth.uniform_cells(24, 300, 36, 0.5), 1e-8, kin.LAYOUT_WAVE)]
+    for name, st, dt, layout in cases:
+        m = synth.mechanism(name)
+        gpu = run_gpu(ctx, m, st, dt, prec=prec, opts=kin.solver_opts(layout=layout, point_implicit=1))
+        om, ref = run_oracle(orc, m, st, dt, point_implicit=1)
+        extra = point_implicit_floor(om, st.rho, st.Y, st.T, ref[1], ref[0], dt, eps)
+        s = compare(gpu, ref, st.rho, st.Y, dt, om, rtol, extra=extra)
+        report(f"point-implicit {name} layout={layout}", s)
+        assert np.all(gpu[3] == 0) and np.all(gpu[4][gpu[2] < 3] == 1)
+        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, s
+    m = synth.mechanism("mech9")
+    st = synth.uniform_cells(25, 8, 9, 1.0)
+    with pytest.raises(kin.KinError) as e:
+        run_gpu(ctx, m, st, 1e-7, prec=kin.FP32_LU, opts=kin.solver_opts(point_implicit=1))
+    assert e.value.status == kin.EINVAL

@@ -433,3 +433,48 @@ def test_adaptive_levels_reported(orc):
     assert np.all((s == 0) == (lv == 0))
     assert np.all(it[s == 0] <= 10)
     assert (s == 1).sum() > 0 and (s == 0).sum() > 0
+
+
+# ---------------------------------------------------------------------------------------------
+# Point-implicit step (Sec. 3.2, Eq. "kinetics"): one linearised backward-Euler step over dt
+# ---------------------------------------------------------------------------------------------
+
+def test_point_implicit_isomer_is_exact_backward_euler(orc):
+    """A <=> B is linear in Y with T fixed, so the single linearised step is the exact
+    backward-Euler step x_A = x_eq + (x_A,n - x_eq) / (1 + (k_f + k_b) dt)."""
+    kf, K, dt = 2e8, 0.7, 3e-6
+    m = isomer_mech(kf, K)
+    om = orc.OracleMech(m)
+    Y = np.array([[0.85, 0.1], [0.15, 0.9]])
+    rho, T = np.array([0.4, 0.02]), np.array([1200.0, 2400.0])
+    T1, Y1, st, lv, it = om.advance(rho, T, Y, dt, opts=orc.make_opts(point_implicit=1))
+    assert list(st) == [0, 0] and list(lv) == [0, 0] and list(it) == [1, 1]
+    kb = kf / K
+    yeq = kb / (kf + kb)
+    np.testing.assert_allclose(Y1[0], yeq + (Y[0] - yeq) / (1 + (kf + kb) * dt), rtol=1e-13)
+    np.testing.assert_allclose(T1, T, rtol=1e-13)
+
+
+def test_point_implicit_is_one_linear_solve(orc):
+    """On the 9-species mechanism, the point-implicit Y equals Y_n + dx with
+    (I - dt J(x_n)) dx = dt f(x_n) solved by LAPACK (J and f from the pinned oracle routines);
+    T is then set by the energy inversion, e(Y, T) = e0."""
+    m = synth.mechanism("mech9")
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(17, 24, m.ns, 1.0)
+    dt = 1e-7
+    e0 = om.energy_batch(st.T, st.Y)
+    T1, Y1, s1, l1, i1 = om.advance(st.rho, st.T, st.Y, dt, e0=e0, opts=orc.make_opts(point_implicit=1))
+    assert np.all(l1 == 0) and np.all(i1 == 1)
+    N = m.ns + 1
+    for c in range(st.n):
+        x = np.r_[st.Y[:, c], st.T[c]]
+        f = om.rhs(st.rho[c], x)
+        J = om.jacobian(st.rho[c], x)
+        dx = scipy.linalg.solve(np.eye(N) - dt * J, dt * f)
+        if s1[c] == 0:
+            np.testing.assert_allclose(Y1[:, c], x[:-1] + dx[:-1], rtol=1e-10, atol=1e-14)
+            assert abs(om.energy(Y1[:, c], T1[c]) - e0[c]) <= 1e-12 * abs(e0[c])
+        else:
+            assert s1[c] == 2 and np.array_equal(Y1[:, c], st.Y[:, c])
+    assert np.mean(s1 == 0) > 0.5
