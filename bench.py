@@ -16,8 +16,10 @@ temperature inversion.  Also measured and reported under "forms":
     autotuner has chosen each mechanism's layout, against 64 separate launches;
   * the serving loop: Poisson arrivals at 0.5, 0.8 and 0.95 of the measured saturated rate,
     log-normal request sizes (median 16384 cells), 70/30 mix of the two mechanisms, admission
-    by HBM footprint under a 256 MiB budget, p50/p99 latency from arrival to results in host
-    memory.
+    by HBM footprint under a 256 MiB budget, 36-species requests confined to all but 32
+    compute units, p50/p99 latency from arrival to results in host memory;
+  * the paper's point-implicit step (one linearised backward-Euler step per dt) for both
+    mechanisms, with its difference from the iterated method.
 The FP64 CPU oracle is timed on a strided sample of the headline grid on the host cores.
 Prints one JSON line.
 """
@@ -256,14 +258,18 @@ def run_batch(torch, kin, synth, args, stream):
 
 def run_serving(torch, kin, serve, synth, args):
     """Calibrate the saturated rate with every request present at t = 0, then serve Poisson
-    arrivals at fractions of it."""
+    arrivals at fractions of it.  The 36-species requests run on streams confined to all but
+    32 compute units (reserve_cu), which keeps the 9-species requests from queueing behind
+    them; one run without the reservation is kept for comparison."""
     n_req = 20 if args.quick else args.serve_requests
     budget = 256 << 20
     out = {}
+    plan = (("fp32lu", kin.FP32_LU, 32, (0.5, 0.8, 0.95)), ("fp64", kin.FP64, 32, (0.8,)),
+            ("fp32lu_no_reserve", kin.FP32_LU, 0, (0.8,)))
     with kin.Context(0, hbm_budget=budget) as ctx:
         mids = {name: ctx.mech_upload(synth.mechanism(name)) for name in ("mech9", "mech36")}
-        for name, prec, loads in (("fp32lu", kin.FP32_LU, (0.5, 0.8, 0.95)), ("fp64", kin.FP64, (0.8,))):
-            be = serve.KinBackend(ctx, mids, prec, n_slots=16)
+        for name, prec, reserve, loads in plan:
+            be = serve.KinBackend(ctx, mids, prec, n_slots=16, reserve_cu=reserve)
             reqs = synth.serving_requests(4, n_req, rate_per_s=1.0)
             jobs = serve.make_jobs(reqs, time_scale=0.0)
             for j, r in zip(jobs, reqs):
@@ -271,7 +277,7 @@ def run_serving(torch, kin, serve, synth, args):
             log(f"serving {name}: saturation run, {n_req} requests")
             sat = serve.run(jobs, be, budget, 16).summary()
             rate = sat["cells_per_s"] / synth.mean_request_cells()
-            runs = {"saturated": sat}
+            runs = {"reserve_cu": reserve, "saturated": sat}
             for load in loads:
                 reqs = synth.serving_requests(4, n_req, rate_per_s=load * rate)
                 jobs = serve.make_jobs(reqs)
@@ -279,6 +285,7 @@ def run_serving(torch, kin, serve, synth, args):
                     be.prepare(j, r.inst.states())
                 log(f"serving {name}: load {load}")
                 runs[f"load_{load}"] = serve.run(jobs, be, budget, 16).summary()
+            be.close()
             out[name] = runs
     return out
 

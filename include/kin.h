@@ -183,6 +183,15 @@ kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched,
 /* Wait for `stream` (NULL = the null stream). */
 kin_status kin_sync(kin_ctx *ctx, void *stream);
 
+/* A stream (default priority) whose kernels run only on compute units [cu_begin, cu_end) of
+ * the context's device, for a serving loop that keeps some units free of long launches so
+ * that short requests do not queue behind them (Sec. 4.3 processes the domain in segments to
+ * bound resources; this bounds compute units instead).  *stream receives a hipStream_t the
+ * caller passes to kin_advance etc. and releases with kin_stream_destroy.  KIN_EINVAL unless
+ * 0 <= cu_begin < cu_end <= number of compute units. */
+kin_status kin_stream_create(kin_ctx *ctx, int32_t cu_begin, int32_t cu_end, void **stream);
+kin_status kin_stream_destroy(kin_ctx *ctx, void *stream);
+
 /* Free an instance.  Work already enqueued on it must have completed (with a budget pool the
  * memory goes straight back to the pool, without a device synchronisation). */
 kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id);

@@ -904,6 +904,29 @@ kin_status kin_sync(kin_ctx *ctx, void *stream)
     return KIN_OK;
 }
 
+kin_status kin_stream_create(kin_ctx *ctx, int32_t cu_begin, int32_t cu_end, void **stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!stream || cu_begin < 0 || cu_end > ctx->num_cu || cu_begin >= cu_end)
+        return err(KIN_EINVAL, "need 0 <= cu_begin < cu_end <= number of compute units");
+    std::vector<uint32_t> mask((ctx->num_cu + 31) / 32, 0u);
+    for (int c = cu_begin; c < cu_end; ++c) mask[c / 32] |= 1u << (c % 32);
+    hipStream_t st = nullptr;
+    KIN_HIP(ctx, hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()));
+    *stream = st;
+    return KIN_OK;
+}
+
+kin_status kin_stream_destroy(kin_ctx *ctx, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!stream) return err(KIN_EINVAL, "NULL stream");
+    KIN_HIP(ctx, hipStreamDestroy(static_cast<hipStream_t>(stream)));
+    return KIN_OK;
+}
+
 kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id)
 {
     kin_status s = enter(ctx);

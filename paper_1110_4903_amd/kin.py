@@ -27,7 +27,8 @@ Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS, Q_LAR
 EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destroy",
            "kin_mech_upload", "kin_mech_release", "kin_state_upload", "kin_state_reset",
            "kin_advance", "kin_download", "kin_sync", "kin_instance_release", "kin_footprint",
-           "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune")
+           "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune",
+           "kin_stream_create", "kin_stream_destroy")
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -81,6 +82,8 @@ _lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, 
 _lib.kin_sync.argtypes = [_vp, _vp]
 _lib.kin_download_schedule.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
 _lib.kin_autotune.argtypes = [_vp, _i32, _i32, C.c_double, C.c_int, _vp, _vp, _vp]
+_lib.kin_stream_create.argtypes = [_vp, _i32, _i32, _vp]
+_lib.kin_stream_destroy.argtypes = [_vp, _vp]
 _lib.kin_instance_release.argtypes = [_vp, _i32]
 _lib.kin_footprint.argtypes = [_vp, _i32, _i64, C.c_int, _vp]
 _lib.kin_query.argtypes = [_vp, _i32, _i64, _vp]
@@ -271,6 +274,15 @@ class Context:
             raise ValueError("destinations must all be device tensors or all pinned host tensors")
         ptrs = [(_ptr(a)[0] if a is not None else None) for a in (T, Y, e0, status, level, iters)]
         _check(_lib.kin_download(self._h, inst_id, *ptrs, kinds.pop(), _stream_handle(stream)))
+
+    def stream_create(self, cu_begin: int, cu_end: int) -> int:
+        """A raw stream handle whose kernels run on compute units [cu_begin, cu_end)."""
+        h = C.c_void_p()
+        _check(_lib.kin_stream_create(self._h, cu_begin, cu_end, C.byref(h)))
+        return h.value
+
+    def stream_destroy(self, handle: int):
+        _check(_lib.kin_stream_destroy(self._h, handle))
 
     def sync(self, stream=None):
         _check(_lib.kin_sync(self._h, _stream_handle(stream)))

@@ -63,11 +63,16 @@ class Report:
         first = min((r.arrival for r in ok), default=0.0)
         last = max((r.done for r in ok), default=0.0)
         span = max(last - first, 1e-12)
-        return dict(requests=len(ok), rejected=len(self.records) - len(ok), cells=cells,
-                    cells_per_s=cells / span, p50_ms=1e3 * percentile(lat, 50),
-                    p99_ms=1e3 * percentile(lat, 99), mean_ms=1e3 * float(lat.mean()),
-                    max_in_flight=self.max_in_flight, max_bytes_in_use=self.max_bytes_in_use,
-                    span_s=span)
+        out = dict(requests=len(ok), rejected=len(self.records) - len(ok), cells=cells,
+                   cells_per_s=cells / span, p50_ms=1e3 * percentile(lat, 50),
+                   p99_ms=1e3 * percentile(lat, 99), mean_ms=1e3 * float(lat.mean()),
+                   max_in_flight=self.max_in_flight, max_bytes_in_use=self.max_bytes_in_use,
+                   span_s=span)
+        for mech in sorted({r.mech for r in ok}):
+            lm = [r.latency for r in ok if r.mech == mech]
+            out[f"{mech}_p50_ms"] = 1e3 * percentile(lm, 50)
+            out[f"{mech}_p99_ms"] = 1e3 * percentile(lm, 99)
+        return out
 
 
 def percentile(x, q) -> float:
@@ -152,17 +157,40 @@ def run(jobs: List[Job], backend, budget: int, n_slots: int, clock=None) -> Repo
 
 class KinBackend:
     """Requests through libkin: one stream per slot; upload from pinned host memory, advance
-    and download in stream order; completion seen through an event on the slot's stream."""
+    and download in stream order; completion seen through an event on the slot's stream.
 
-    def __init__(self, ctx, mech_ids: Dict[str, int], prec: int, n_slots: int, opts=None):
+    reserve_cu > 0: requests of the mechanisms in `heavy` (long launches) run on streams whose
+    kernels are confined to the first num_cu - reserve_cu compute units, so the remaining units
+    stay available to the other requests, which would otherwise wait for units to drain.
+    """
+
+    def __init__(self, ctx, mech_ids: Dict[str, int], prec: int, n_slots: int, opts=None,
+                 reserve_cu: int = 0, heavy=("mech36",)):
         import torch
+        from . import kin
         self.torch = torch
         self.ctx, self.mids, self.prec, self.opts = ctx, mech_ids, prec, opts
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.events = [torch.cuda.Event() for _ in range(n_slots)]
+        self.heavy = set(heavy)
+        self._raw = []
+        self.heavy_streams = None
+        if reserve_cu > 0:
+            ncu = ctx.query_int(kin.Q_NUM_CU)
+            if not 0 < reserve_cu < ncu:
+                raise ValueError(f"reserve_cu must be in 1..{ncu - 1}")
+            self._raw = [ctx.stream_create(0, ncu - reserve_cu) for _ in range(n_slots)]
+            self.heavy_streams = [torch.cuda.ExternalStream(h) for h in self._raw]
         self.slot: Dict[int, tuple] = {}
         self._ns = {name: ctx.mech_ns[mid] for name, mid in mech_ids.items()}
         self._fp: Dict[tuple, int] = {}
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        for h in self._raw:
+            self.ctx.stream_destroy(h)
+        self._raw = []
+        self.heavy_streams = None
 
     def prepare(self, job: Job, st) -> None:
         """Pinned host copies of a request's inputs and room for its outputs."""
@@ -183,6 +211,8 @@ class KinBackend:
     def start(self, job: Job, slot: int) -> bool:
         from . import kin
         s = self.streams[slot]
+        if self.heavy_streams is not None and job.mech in self.heavy:
+            s = self.heavy_streams[slot]
         d = job.state
         try:
             iid = self.ctx.state_upload(self.mids[job.mech], d["rho"], d["T"], d["Y"], stream=s)

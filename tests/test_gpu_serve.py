@@ -23,18 +23,18 @@ def _jobs(seed, n):
     return reqs, serve.make_jobs(reqs)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_alone_equals_mix(prec):
+@pytest.mark.parametrize("prec,reserve", [(0, 0), (1, 0), (1, 32)])
+def test_alone_equals_mix(prec, reserve):
     budget = 8 << 20
     ctx, mids = _setup(budget)
     try:
         reqs, jobs = _jobs(40 + prec, 24)
-        be = serve.KinBackend(ctx, mids, prec, n_slots=6)
+        be = serve.KinBackend(ctx, mids, prec, n_slots=6, reserve_cu=reserve)
         for j, r in zip(jobs, reqs):
             be.prepare(j, r.inst.states())
         rep = serve.run(jobs, be, budget, 6)
         s = rep.summary()
-        print(f"\n[serve mix prec={prec}] " + " ".join(f"{k}={v}" for k, v in s.items()), flush=True)
+        print(f"\n[serve mix prec={prec} reserve={reserve}] " + " ".join(f"{k}={v}" for k, v in s.items()), flush=True)
         assert s["rejected"] == 0 and s["requests"] == len(jobs)
         assert rep.max_bytes_in_use <= budget and ctx.bytes_in_use() == 0
         assert ctx.largest_free() == budget
@@ -47,6 +47,7 @@ def test_alone_equals_mix(prec):
             alone = rep1.records[0].result
             for a, b in zip(alone, mixed[j.rid]):
                 assert np.array_equal(a, b), (j.rid, j.mech, j.n_cells)
+        be.close()
     finally:
         ctx.close()
 
