@@ -101,7 +101,7 @@ typedef struct {
 
 /* Newton / sub-stepping controls.  Defaults (kin_default_solver_opts): rtol 1e-12,
  * atol_Y 1e-20, atol_T 1e-9 K, y_neg 1e-10, k_max 10, L_max 40, layout AUTO, L_forced -1,
- * max_iters 100000, point_implicit 0. */
+ * max_iters 100000, point_implicit 0, diverge_ratio 2. */
 typedef struct {
     double rtol;       /* Newton converged when |dx_i| <= atol_i + rtol |x_i| for all i */
     double atol_Y;
@@ -121,6 +121,9 @@ typedef struct {
                              * FP64 only: without Newton's refinement an FP32 factorisation
                              * of I - dt J carries its full rounding error into the result,
                              * so kin_advance rejects it with KIN_EINVAL for KIN_FP32_LU. */
+    double diverge_ratio;   /* an attempt fails early when an update's weighted norm
+                             * max_i |dx_i| / (atol_i + rtol |x_i|) exceeds diverge_ratio
+                             * times the previous iteration's (Newton diverging); 0 disables */
 } kin_solver_opts;
 
 void kin_default_solver_opts(kin_solver_opts *s);

@@ -72,6 +72,7 @@ void orc_default_opts(orc_opts *o)
     o->k_max = 10;
     o->L_max = 40;
     o->max_iters = 100000;
+    o->diverge_ratio = 2.0;
     o->point_implicit = 0;
 }
 
@@ -337,6 +338,7 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
     double *A = (double *)malloc(sizeof(double) * N * N);
     int rc = -1;
     memcpy(xk, x, sizeof(double) * N);
+    double r_prev = -1.0;  /* weighted norm of the previous update */
     for (int k = 0; k < o->k_max; ++k) {
         ++*iters;
         orc_rhs(m, rho, xk, f);
@@ -358,6 +360,16 @@ int orc_be_substep(const orc_mech *m, double rho, double e0, double *x, double h
             if (!(fabs(d[i]) <= atol + o->rtol * fabs(xk[i]))) conv = 0;
         }
         if (o->point_implicit) conv = 1;  /* the linearised step is taken as it is */
+        if (!conv && o->diverge_ratio > 0) {
+            double r = 0;
+            for (int i = 0; i < N; ++i) {
+                double atol = (i < ns) ? o->atol_Y : o->atol_T;
+                double ri = fabs(d[i]) / (atol + o->rtol * fabs(xk[i]));
+                if (ri > r) r = ri;
+            }
+            if (r_prev >= 0 && r > o->diverge_ratio * r_prev) break;  /* diverging */
+            r_prev = r;
+        }
         if (conv) {
             int neg = 0;
             if (!o->point_implicit)

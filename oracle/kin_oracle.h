@@ -55,6 +55,9 @@ typedef struct {
     double y_neg;           /* a converged iterate with some Y_s < -y_neg is rejected */
     int k_max, L_max;
     int max_iters;          /* Newton iterations per cell before it is declared failed */
+    double diverge_ratio;   /* an attempt fails when an update's weighted norm
+                               max_i |dx_i| / (atol_i + rtol |x_i|) exceeds diverge_ratio times
+                               the previous iteration's (Newton diverging); 0 disables */
     int point_implicit;     /* 1: the point-implicit step of Sec. 3.2 (Eq. "kinetics"): one
                                linearised backward-Euler step over the whole dt,
                                (I - dt J(x_n)) dx = dt f(x_n), accepted without a convergence

@@ -44,7 +44,7 @@ class _Mech(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
                 ("y_neg", C.c_double), ("k_max", C.c_int), ("L_max", C.c_int),
-                ("max_iters", C.c_int), ("point_implicit", C.c_int)]
+                ("max_iters", C.c_int), ("diverge_ratio", C.c_double), ("point_implicit", C.c_int)]
 
 
 _LIB = None
@@ -88,10 +88,11 @@ def default_opts() -> Opts:
 
 
 def make_opts(rtol=None, atol_Y=None, atol_T=None, y_neg=None, k_max=None, L_max=None,
-              max_iters=None, point_implicit=None) -> Opts:
+              max_iters=None, point_implicit=None, diverge_ratio=None) -> Opts:
     o = default_opts()
     for k, v in dict(rtol=rtol, atol_Y=atol_Y, atol_T=atol_T, y_neg=y_neg, k_max=k_max,
-                     L_max=L_max, max_iters=max_iters, point_implicit=point_implicit).items():
+                     L_max=L_max, max_iters=max_iters, point_implicit=point_implicit,
+                     diverge_ratio=diverge_ratio).items():
         if v is not None:
             setattr(o, k, v)
     return o

@@ -159,6 +159,7 @@ struct AdvanceArgs {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
     int point_implicit;              // 1: accept the first (linearised) update as it is
+    double diverge_ratio;            // > 0: fail an attempt whose update norm grows by more
     const double *K;                 // lane layout: the mechanism's constant table
     unsigned long long *counter;     // next unclaimed cell (zero at launch)
 };

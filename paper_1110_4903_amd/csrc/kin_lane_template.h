@@ -27,6 +27,7 @@ struct KinLaneArgs {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max, L_max, L_forced, max_iters;
     int point_implicit;   // 1: accept the first (linearised) update as it is
+    double diverge_ratio; // > 0: fail an attempt whose update norm grows by more than this
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
     unsigned long long *counter;  // next unclaimed global cell; zero at launch
 };
@@ -162,7 +163,7 @@ enum { KIN_CONTINUE = 0, KIN_ACCEPTED = 1, KIN_ATTEMPT_FAILED = 2 };
 template <bool F32>
 __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const double rho,
                                                     const double e0, const double (&x)[KIN_N],
-                                                    double (&xk)[KIN_N], const double h)
+                                                    double (&xk)[KIN_N], const double h, double &r_prev)
 {
     double f[KIN_N];
     double A[KIN_N][KIN_N];
@@ -212,7 +213,21 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
     }
     if (!(chk2 == 0.0)) return KIN_ATTEMPT_FAILED;
     if (xk[KIN_NS] < KIN_T_MIN || xk[KIN_NS] > KIN_T_MAX) return KIN_ATTEMPT_FAILED;
-    if (!conv && !a.point_implicit) return KIN_CONTINUE;
+    if (!conv && !a.point_implicit) {
+        // weighted norm of this update; growth by more than diverge_ratio over the previous
+        // update abandons the attempt (Newton diverging)
+        if (a.diverge_ratio > 0.0) {
+            double r = 0.0;
+#pragma unroll
+            for (int i = 0; i < KIN_N; ++i) {
+                const double atol = (i < KIN_NS) ? a.atol_Y : a.atol_T;
+                r = fmax(r, fabs(d[i]) / (atol + a.rtol * fabs(xk[i])));
+            }
+            if (r_prev >= 0.0 && r > a.diverge_ratio * r_prev) return KIN_ATTEMPT_FAILED;
+            r_prev = r;
+        }
+        return KIN_CONTINUE;
+    }
     bool neg = false;
 #pragma unroll
     for (int s = 0; s < KIN_NS; ++s) neg = neg || (xk[s] < -a.y_neg);
@@ -254,6 +269,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     unsigned long long t = 0, hsh = KIN_SCHED_SEED;
     int l = 0, k = 0, iters = 0, level = 0;
     bool failed = false;
+    double r_prev = -1.0;  // weighted norm of the previous update of the current attempt
 
     for (;;) {
         // ---- hand new cells to lanes that need one ----------------------------------------
@@ -321,7 +337,8 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 outcome = KIN_CONTINUE;
             } else {
                 ++iters;
-                outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(dt, -l));
+                if (k == 0) r_prev = -1.0;
+                outcome = kin_newton_iteration<F32>(a, rho, e0, x, xk, ldexp(dt, -l), r_prev);
                 if (outcome == KIN_CONTINUE && ++k >= a.k_max) outcome = KIN_ATTEMPT_FAILED;
             }
             if (outcome != KIN_CONTINUE)

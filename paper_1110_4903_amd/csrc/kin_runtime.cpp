@@ -169,6 +169,7 @@ void kin_default_solver_opts(kin_solver_opts *s)
     s->L_forced = -1;
     s->max_iters = 100000;
     s->point_implicit = 0;
+    s->diverge_ratio = 2.0;
 }
 
 const char *kin_last_error(void) { return g_err.c_str(); }
@@ -642,6 +643,7 @@ static void fill_opts(AdvanceArgs &a, const kin_solver_opts &o)
     a.rtol = o.rtol; a.atol_Y = o.atol_Y; a.atol_T = o.atol_T; a.y_neg = o.y_neg;
     a.k_max = o.k_max; a.L_max = o.L_max; a.L_forced = o.L_forced; a.max_iters = o.max_iters;
     a.point_implicit = o.point_implicit ? 1 : 0;
+    a.diverge_ratio = o.diverge_ratio;
     if (a.point_implicit) {  // one sub-step over dt, one (linearised) update
         a.L_forced = 0;
         a.k_max = 1;
@@ -688,7 +690,7 @@ static bool opts_ok(const kin_solver_opts &o)
 {
     return o.rtol >= 0 && o.atol_Y >= 0 && o.atol_T >= 0 && o.y_neg >= 0 && o.k_max >= 1 && o.L_max >= 0 &&
            o.L_max <= 62 && o.L_forced <= 30 && o.L_forced >= -1 && o.max_iters >= 1 &&
-           o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_WAVE;
+           o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_WAVE && o.diverge_ratio >= 0;
 }
 
 // Batched advance: instances grouped by (mechanism, layout), at most kMaxSpans per launch, each

@@ -567,7 +567,8 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
 struct StepCtl {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max;
-    bool point_implicit;  // accept the first (linearised) update as it is
+    bool point_implicit;   // accept the first (linearised) update as it is
+    double diverge_ratio;  // > 0: fail an attempt whose update norm grows by more than this
 };
 
 // One backward-Euler sub-step of size h.  xs (lane i: x_i) is updated on success.
@@ -578,6 +579,7 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
 {
     const int ns = t.ns, N = ns + 1, JS = NPAD;
     double xk = xs;
+    double r_prev = -1.0;  // weighted norm of the previous update
     for (int k = 0; k < c.k_max; ++k) {
         ++iters;
         eval<NPAD>(t, L, lane, rho, xk, Ms, invMs);
@@ -627,6 +629,11 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
         const double T = rdlane(xk, ns);
         if (T < kTmin || T > kTmax) return false;
         const bool conv = c.point_implicit || __all(lane >= N || fabs(d) <= atol + c.rtol * fabs(xk));
+        if (!conv && c.diverge_ratio > 0.0) {  // Newton diverging: abandon the attempt
+            const double r = wave_max(lane < N ? fabs(d) / (atol + c.rtol * fabs(xk)) : 0.0);
+            if (r_prev >= 0.0 && r > c.diverge_ratio * r_prev) return false;
+            r_prev = r;
+        }
         if (conv) {
             if (!c.point_implicit && __any(lane < ns && xk < -c.y_neg)) return false;
             double Tn;
@@ -646,7 +653,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
     const int ns = t.ns, N = ns + 1;
     const Lds L = lds_map(smem + (size_t)wid * lds_doubles(N, t.ntb, NPAD), N, t.ntb, NPAD);
-    const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max, a.point_implicit != 0};
+    const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max, a.point_implicit != 0, a.diverge_ratio};
     const double Ms = lane < ns ? t.M[lane] : 1.0;
     const double invMs = 1.0 / Ms;
     // one cell per wavefront; the hardware dispatcher hands out blocks as earlier ones

@@ -63,7 +63,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_Y", C.c_double), ("atol_T", C.c_double),
                 ("y_neg", C.c_double), ("k_max", C.c_int32), ("L_max", C.c_int32),
                 ("layout", C.c_int32), ("L_forced", C.c_int32), ("max_iters", C.c_int32),
-                ("point_implicit", C.c_int32)]
+                ("point_implicit", C.c_int32), ("diverge_ratio", C.c_double)]
 
 
 _vp, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t

@@ -29,7 +29,7 @@ def test_default_solver_opts_match_oracle_defaults(orc):
     from paper_1110_4903_amd import kin
     s = kin.solver_opts()
     o = orc.default_opts()
-    for f in ("rtol", "atol_Y", "atol_T", "y_neg", "k_max", "L_max", "max_iters", "point_implicit"):
+    for f in ("rtol", "atol_Y", "atol_T", "y_neg", "k_max", "L_max", "max_iters", "point_implicit", "diverge_ratio"):
         assert getattr(s, f) == getattr(o, f), f
     assert s.L_forced == -1 and s.layout == kin.LAYOUT_AUTO
 

@@ -337,3 +337,19 @@ def test_point_implicit_both_layouts(ctx, orc):
     with pytest.raises(kin.KinError) as e:
         run_gpu(ctx, m, st, 1e-7, prec=kin.FP32_LU, opts=kin.solver_opts(point_implicit=1))
     assert e.value.status == kin.EINVAL
+
+
+def test_divergence_test_off_matches_oracle(ctx, orc):
+    """With the Newton divergence test disabled (diverge_ratio = 0) both layouts still follow
+    the oracle (FP64 gate)."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    for name, st, layout in (("mech9", synth.uniform_cells(31, 500, 9, 1.0), kin.LAYOUT_LANE),
+                             ("mech36", synth.uniform_cells(32, 128, 36, 0.5), kin.LAYOUT_WAVE)):
+        m = synth.mechanism(name)
+        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout, diverge_ratio=0.0))
+        om, ref = run_oracle(orc, m, st, 1e-6, diverge_ratio=0.0)
+        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
+        report(f"diverge off {name}", s)
+        assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0

@@ -478,3 +478,27 @@ def test_point_implicit_is_one_linear_solve(orc):
         else:
             assert s1[c] == 2 and np.array_equal(Y1[:, c], st.Y[:, c])
     assert np.mean(s1 == 0) > 0.5
+
+
+def test_divergence_test_saves_iterations_and_keeps_invariants(orc):
+    """Abandoning attempts whose update norm grows (diverge_ratio = 2, the default) changes the
+    sub-step schedule but every accepted result is still a backward-Euler step: mass and
+    element conservation and e(Y, T) = e0 hold, and fewer Newton iterations are spent than with
+    the test disabled."""
+    m = synth.mechanism("mech36")
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(2, 40, m.ns, 0.5)
+    e0 = om.energy_batch(st.T, st.Y)
+    T1, Y1, s1, l1, i1 = om.advance(st.rho, st.T, st.Y, 1e-6, e0=e0)
+    T0, Y0, s0, l0, i0 = om.advance(st.rho, st.T, st.Y, 1e-6, e0=e0, opts=orc.make_opts(diverge_ratio=0.0))
+    assert np.all(s1 < 2) and np.all(s0 < 2)
+    assert i1.sum() < 0.85 * i0.sum()
+    comp = np.asarray(m.comp, dtype=float)
+    M = np.asarray(m.M)
+    for Y in (Y1, Y0):
+        np.testing.assert_allclose(Y.sum(0), st.Y.sum(0), rtol=0, atol=1e-12)
+        el0 = comp.T @ (st.Y / M[:, None])
+        el1 = comp.T @ (Y / M[:, None])
+        np.testing.assert_allclose(el1, el0, rtol=1e-11, atol=1e-14)
+    for c in range(st.n):
+        assert abs(om.energy(Y1[:, c], T1[c]) - e0[c]) <= 1e-12 * abs(e0[c])
