@@ -173,11 +173,13 @@ __device__ __forceinline__ Thermo thermo(const WaveTables &t, int s, double T, d
 // ---- per-wavefront LDS layout (in doubles) --------------------------------------------------
 // [0, R)            J[N][NPAD] during the evaluation (columns N.. stay zero); packed U rows
 //                   during the solve
-// W[NPAD]           net production sums, then f; the eliminated right-hand side in the solve
-// WT[NPAD]          d(net production)/dT sums
+// W[NPAD]           net production sums, then f (the T-derivative sums accumulate straight
+//                   into J's column N - 1 and are scaled there)
 // c[NPAD]           concentrations
 // g[NPAD], hh[NPAD] g/RT and h/RT for the rates, then e_s and cv_s for the energy row
-// Mc[ntbp], DTB[ntbp]  third-body concentrations and the third-body reactions' q_f - q_b
+// Mc[ntbp]          third-body concentrations; each is replaced by its reaction's q_f - q_b
+//                   (one reaction per slot reads, then writes, its own entry)
+// 14 KB for the 36-species mechanism keeps twelve wavefronts on a compute unit
 __host__ __device__ inline int round_even(int x) { return (x + 1) & ~1; }
 
 // Packed U rows hold 16-byte units; row k starts at the sum of the rounded lengths of the rows
@@ -200,11 +202,11 @@ __host__ __device__ inline int j_region(int N, int npad)
 
 __host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
 {
-    return (size_t)j_region(N, npad) + 5 * (size_t)npad + 2 * (size_t)round_even(ntb);
+    return (size_t)j_region(N, npad) + 4 * (size_t)npad + (size_t)round_even(ntb);
 }
 
 struct Lds {
-    double *J, *W, *WT, *c, *g, *hh, *Mc, *DTB;
+    double *J, *W, *c, *g, *hh, *Mc;
 };
 
 __device__ __forceinline__ Lds lds_map(double *base, int N, int ntb, int npad)
@@ -213,12 +215,10 @@ __device__ __forceinline__ Lds lds_map(double *base, int N, int ntb, int npad)
     double *p = base;
     L.J = p; p += j_region(N, npad);
     L.W = p; p += npad;
-    L.WT = p; p += npad;
     L.c = p; p += npad;
     L.g = p; p += npad;
     L.hh = p; p += npad;
-    L.Mc = p; p += round_even(ntb);
-    L.DTB = p;
+    L.Mc = p;
     return L;
 }
 
@@ -283,9 +283,9 @@ __device__ __forceinline__ double dcpow_nu(double c, int nu)
     return nu == 0 ? 0.0 : (nu == 1 ? 1.0 : (nu == 2 ? 2.0 * c : 3.0 * c * c));
 }
 
-// Rates and Jacobian terms of reaction r (lane-owned), added into W, WT and J.
+// Rates and Jacobian terms of reaction r (lane-owned), added into W and J.
 //   Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''),  dQ_r/dc_k over the participants,
-//   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  WT[s] += nu_rs dQ_r/dT.
+//   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  J[s][N-1] += nu_rs dQ_r/dT.
 template <int NPAD>
 __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
                                                const double4 &rd, unsigned ps, int npmax, double iT,
@@ -340,7 +340,7 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
     const double D = pf - pb;
     const double q = Mc * D;
     const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
-    if (x.tb >= 0) L.DTB[x.tb] = D;
+    if (x.tb >= 0) L.Mc[x.tb] = D;  // the slot's [M] has been read; the dense pass needs D
     // dQ/dc_k / M_k for each participant k
     // participant j takes d/dc of its reactant slot's term minus its product slot's term
     // (species are merged within each side, so each side has at most one slot)
@@ -364,8 +364,8 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
             const double nu = (double)x.part_nu[i];
             const double a = kc->rowc[i];
             lds_add(L.W + si, nu * q);
-            lds_add(L.WT + si, nu * qT);
             double *Jr = L.J + (size_t)si * JS;
+            lds_add(Jr + t.ns, nu * qT);
 #pragma unroll
             for (int j = 0; j < 6; ++j)
                 if (j < npmax && j < x.npart) lds_add(Jr + x.part_sp[j], a * dq[j]);
@@ -384,9 +384,9 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
     const double lPaRT = t.lnPaR - lT;  // ln(P_atm / (R T)), CGS
-    {   // clear J, W and WT (J's region ends where W begins)
+    {   // clear J and W (J's region ends where W begins)
         double2 *z = reinterpret_cast<double2 *>(L.J);
-        const int nj = N * JS / 2, n2 = nj + NPAD;
+        const int nj = N * JS / 2, n2 = nj + NPAD / 2;
         const int skip = j_region(N, NPAD) / 2 - nj;
         for (int k = lane; k < n2; k += kW) z[k < nj ? k : k + skip] = make_double2(0.0, 0.0);
     }
@@ -443,7 +443,7 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
                 v[q] = er[(size_t)e * ns];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) D[q] = L.DTB[ent[q] & 0xffff];
+            for (int q = 0; q < 8; ++q) D[q] = L.Mc[ent[q] & 0xffff];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (col && e0 + q < t.ntbe) lds_add(L.J + (size_t)(ent[q] >> 16) * JS + lane, D[q] * v[q]);
@@ -455,7 +455,7 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     if (lane < ns) {
         const double ms = Ms * irc;
         fs = L.W[lane] * ms;
-        L.J[(size_t)lane * JS + ns] = L.WT[lane] * ms;
+        L.J[(size_t)lane * JS + ns] *= ms;
         L.W[lane] = fs;
         L.g[lane] = ek;
         L.hh[lane] = cvk;
