@@ -161,6 +161,33 @@ def run_headline(torch, ctx, kin, flops, synth, args, stream):
     return res, grid, m9, dt9
 
 
+def run_config0_end_to_end(torch, ctx, kin, synth, stream):
+    """4096 cells of the 9-species mechanism (the small parity input) with host buffers at the
+    boundary: reset from host memory, advance one dt, download to host memory, wall time per
+    round over 20 rounds (PCIe-inclusive; not the reported value)."""
+    m, st, dt = synth.workload_small_mech9()
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    T = np.empty(st.n)
+    Y = np.empty((m.ns, st.n))
+    for _ in range(2):
+        ctx.state_reset(iid, st.rho, st.T, st.Y)
+        ctx.advance([iid], [dt])
+        ctx.download(iid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        ctx.state_reset(iid, st.rho, st.T, st.Y)
+        ctx.advance([iid], [dt])
+        T, Y = ctx.download(iid)[:2]
+    el = time.perf_counter() - t0
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    return dict(cells=st.n, rounds=reps, seconds=el, cells_per_s=st.n * reps / el,
+                ms_per_round=1e3 * el / reps)
+
+
 def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     n36 = (1 << 14) if args.quick else (1 << 18)
     m36, s36, dt36 = synth.workload_mech36(n36)
@@ -317,6 +344,9 @@ def run_gpu(args):
             res.update(head)
         if args.only in ("all", "mech36"):
             res.update(run_mech36(torch, ctx, kin, flops, synth, args, stream))
+        if args.only == "all":
+            log("config 0 end to end (host buffers)")
+            res["mech9_4096_end_to_end_host_buffers"] = run_config0_end_to_end(torch, ctx, kin, synth, stream)
     if args.only in ("all", "batch") and not args.no_batch:
         res["batch64"] = run_batch(torch, kin, synth, args, stream)
     if args.only in ("all", "serve") and not args.no_serve:
@@ -336,9 +366,19 @@ def cpu_baseline(grid, m9, dt9, steps, sample_stride):
     for _ in range(steps):
         T, Y, _, _, _ = om.advance(sub.rho, T, Y, dt9, e0=e0)
     el = time.time() - t0
+    # the same oracle on one thread, over every 64th cell of that sample
+    sub1 = grid.subset(idx[::64])
+    e1 = om.energy_batch(sub1.T, sub1.Y)
+    T, Y = sub1.T.copy(), sub1.Y.copy()
+    t1 = time.time()
+    for _ in range(steps):
+        T, Y, _, _, _ = om.advance(sub1.rho, T, Y, dt9, e0=e1, nthreads=1)
+    el1 = time.time() - t1
     return dict(value=idx.shape[0] * steps / el, unit="cells/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"{idx.shape[0]} cells (every {sample_stride}th of the {int(np.sqrt(grid.n))}^2 grid) x "
-                       f"{steps} steps of dt=1e-6 s, FP64, {el:.1f} s")
+                       f"{steps} steps of dt=1e-6 s, FP64, {el:.1f} s",
+                single_thread_cells_per_s=sub1.n * steps / el1,
+                single_thread_sample=f"{sub1.n} cells x {steps} steps, {el1:.1f} s")
 
 
 def kernel_source_hash() -> str:

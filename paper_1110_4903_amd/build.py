@@ -72,5 +72,17 @@ def build(verbose: bool = False) -> str:
     return SO
 
 
+def build_abi_check(verbose: bool = False) -> str:
+    """The C-only check of the ABI (tests/abi_c/kin_abi_check.c), linked against libkin.so."""
+    src = os.path.join(ROOT, "tests", "abi_c", "kin_abi_check.c")
+    exe = os.path.join(ROOT, "tests", "abi_c", "kin_abi_check")
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-I", os.path.join(ROOT, "include"), src,
+           "-L", HERE, "-lkin", "-Wl,-rpath," + HERE, "-Wl,-rpath,/opt/rocm/lib", "-lm", "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
