@@ -171,34 +171,17 @@ __device__ __forceinline__ Thermo thermo(const WaveTables &t, int s, double T, d
 }
 
 // ---- per-wavefront LDS layout (in doubles) --------------------------------------------------
-// [0, R)            J[N][NPAD] during the evaluation (columns N.. stay zero); packed U rows
-//                   during the solve
+// [0, R)            J[N][NPAD] (columns N.. stay zero); the solve itself works in registers
 // W[NPAD]           net production sums, then f (the T-derivative sums accumulate straight
 //                   into J's column N - 1 and are scaled there)
 // c[NPAD]           concentrations
 // g[NPAD], hh[NPAD] g/RT and h/RT for the rates, then e_s and cv_s for the energy row
 // Mc[ntbp]          third-body concentrations; each is replaced by its reaction's q_f - q_b
 //                   (one reaction per slot reads, then writes, its own entry)
-// 14 KB for the 36-species mechanism keeps twelve wavefronts on a compute unit
+// 13.5 KB for the 36-species mechanism keeps twelve wavefronts on a compute unit
 __host__ __device__ inline int round_even(int x) { return (x + 1) & ~1; }
 
-// Packed U rows hold 16-byte units; row k starts at the sum of the rounded lengths of the rows
-// before it, and its store may run NPAD elements past its start (the tail is overwritten by
-// later rows or falls into the slack).
-__host__ __device__ inline int u_row_len(int N, int k, int elems16) { return ((N - k) + elems16 - 1) / elems16 * elems16; }
-
-__host__ __device__ inline int u_extent_doubles(int N, int npad)
-{
-    int off = 0;
-    for (int k = 0; k + 1 < N; ++k) off += u_row_len(N, k, 2);
-    return off + npad + 2;
-}
-
-__host__ __device__ inline int j_region(int N, int npad)
-{
-    const int a = N * npad, b = u_extent_doubles(N, npad);
-    return round_even(a > b ? a : b);
-}
+__host__ __device__ inline int j_region(int N, int npad) { return round_even(N * npad); }
 
 __host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
 {
@@ -487,59 +470,54 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
 // Gaussian elimination with partial pivoting, one row per lane, and back substitution.  Lane
 // i < N enters with row i of A in a[] and b_i in bb; on return x holds solution component
 // `lane` (lanes >= N: 0).  Pivot rule: the row of largest |a_ik| among rows not yet used,
-// ties to the lowest current position.  The pivot row is broadcast from its lane's registers
-// (readlane), and stored packed at U + off_k (element m is column k + m) for the back
-// substitution; lane k keeps the pivot u_kk and the eliminated right-hand side y_k.  Returns
-// false on an exactly zero pivot.
+// ties to the lowest current position.  Rows never move between lanes: `pos` is the row's
+// current position, and the lane that supplies pivot k keeps its row, now row k of U, frozen
+// in its registers, where the back substitution reads it.  The pivot row reaches the other
+// lanes by readlane.  Returns false on an exactly zero pivot.
 template <int NPAD, typename R>
-__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, double *Ubase, R &x)
+__device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, R &x)
 {
-    constexpr int E16 = 16 / sizeof(R);
-    R *const U = reinterpret_cast<R *>(Ubase);
-    int pos = lane, myoff = 0, off = 0;
-    R dg = R(1), yv = R(0);
+    int pos = lane;
+    R dg = R(1);  // the lane's U diagonal element once it has supplied a pivot
     bool ok = true;
+    // blocks of four pivot columns; each block ends by rotating the row left by four, so the
+    // next block's pivot columns sit in a[0..3].  All NPAD / 4 rotations are made, which
+    // brings column j back to a[j] for the back substitution.
+#pragma unroll 1
     for (int blk = 0; blk < NPAD / 4; ++blk) {
-        if (4 * blk >= N) break;
+        if (4 * blk < N) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const int k = 4 * blk + kk;
-            if (k < N) {
-                bool nz;
-                const int w = pivot_lane<R>((R)fabs(a[kk]), pos >= k && lane < N, pos, nz);
-                const int p = rdlane(pos, w);
-                ok = ok && nz;
-                pos = (lane == w) ? k : (pos == k ? p : pos);
-                myoff = (lane == k) ? off : myoff;
-                const R piv = rdlane(a[kk], w);
-                const R yk = rdlane(bb, w);
-                dg = (lane == k) ? piv : dg;
-                yv = (lane == k) ? yk : yv;
-                if (lane == w) {
-                    R *row = static_cast<R *>(__builtin_assume_aligned(U + off, 16));
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * blk + kk;
+                if (k < N) {
+                    bool nz;
+                    const int w = pivot_lane<R>((R)fabs(a[kk]), pos >= k && lane < N, pos, nz);
+                    const int p = rdlane(pos, w);
+                    ok = ok && nz;
+                    pos = (lane == w) ? k : (pos == k ? p : pos);
+                    const R piv = rdlane(a[kk], w);
+                    const R yk = rdlane(bb, w);
+                    dg = (lane == w) ? piv : dg;
+                    const bool elim = pos > k;
+                    const R l = elim ? a[kk] / piv : R(0);
+                    bb = fma(-l, yk, bb);
+                    // pivot row from the pivot lane's registers, eight columns at a time;
+                    // register positions from NPAD - 4 blk on hold columns already eliminated
+                    // (rotated in from the front) and are skipped eight at a time.  Rows that
+                    // have supplied a pivot take l = 0 and stay as they are.
 #pragma unroll
-                    for (int j = kk; j < NPAD; ++j) row[j - kk] = a[j];
+                    for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
+                        if (j0 >= NPAD - 4 * blk) break;
+                        R pr[8];
+#pragma unroll
+                        for (int j = j0; j < j0 + 8 && j < NPAD; ++j) pr[j - j0] = rdlane(a[j], w);
+#pragma unroll
+                        for (int j = j0; j < j0 + 8 && j < NPAD; ++j) a[j] = fma(-l, pr[j - j0], a[j]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
-                const bool elim = pos > k;
-                const R l = elim ? a[kk] / piv : R(0);
-                bb = fma(-l, yk, bb);
-                // pivot row from the pivot lane's registers, eight columns at a time; register
-                // positions from NPAD - 4 blk on hold columns already eliminated (rotated in
-                // from the front) and are skipped eight at a time
-#pragma unroll
-                for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
-                    if (j0 >= NPAD - 4 * blk) break;
-                    R pr[8];
-#pragma unroll
-                    for (int j = j0; j < j0 + 8 && j < NPAD; ++j) pr[j - j0] = rdlane(a[j], w);
-#pragma unroll
-                    for (int j = j0; j < j0 + 8 && j < NPAD; ++j) a[j] = fma(-l, pr[j - j0], a[j]);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                off += u_row_len(N, k, E16);
             }
         }
-        // rotate the row left by four so the next block's pivot columns sit in a[0..3]
         const R t0 = a[0], t1 = a[1], t2 = a[2], t3 = a[3];
 #pragma unroll
         for (int j = 0; j + 4 < NPAD; ++j) a[j] = a[j + 4];
@@ -548,17 +526,18 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, do
         a[NPAD - 2] = t2;
         a[NPAD - 1] = t3;
     }
-    wave_sync();
-    // back substitution: lane i keeps y_i; step k forms x_k and removes it from rows i < k.
-    // The U element of the next step is loaded one step ahead.
+    // back substitution, columns from the last: the lane holding U row k forms
+    // x_k = y_k / u_kk, and every row above k removes u_ik x_k from its y_i
+    const R rdg = R(1) / dg;
     R xl = R(0);
-    R un = (lane < N - 1) ? U[myoff + (N - 1) - lane] : R(0);
-    for (int k = N - 1; k >= 0; --k) {
-        const R u = un;
-        if (lane + 1 < k) un = U[myoff + (k - 1) - lane];
-        const R xk = rdlane(yv, k) / rdlane(dg, k);
-        xl = (lane == k) ? xk : xl;
-        if (lane < k) yv = fma(-u, xk, yv);
+#pragma unroll
+    for (int k = NPAD - 1; k >= 0; --k) {
+        if (k < N) {
+            const int o = __builtin_ctzll(__ballot(pos == k));
+            const R xk = rdlane(bb, o) * rdlane(rdg, o);
+            xl = (lane == k) ? xk : xl;
+            if (pos < k) bb = fma(-a[k], xk, bb);
+        }
     }
     x = xl;
     return ok;
@@ -604,7 +583,7 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
             for (int j = 0; j < NPAD; ++j) arow[j] = 0.0;
         }
         if (__any(bad)) return false;
-        wave_sync();  // J and f are read; the solve reuses their space
+        wave_sync();  // J and f are read before the next evaluation clears them
         bool ok;
         double d;
         if (F32) {
@@ -616,10 +595,10 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
 #pragma unroll
             for (int j = 0; j < NPAD; ++j) af[j] = (float)(arow[j] * s);
             float xf;
-            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, L.J, xf);
+            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, xf);
             d = (double)xf;
         } else {
-            ok = lu_solve<NPAD, double>(arow, bi, N, lane, L.J, d);
+            ok = lu_solve<NPAD, double>(arow, bi, N, lane, d);
         }
         if (!ok) return false;
         wave_sync();
