@@ -71,6 +71,7 @@ __device__ __forceinline__ float rdlane(float v, int l)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
+constexpr int kLuBlock = 4;  // pivot steps between register rotations in the wave LU
 // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror: after the four
 // steps every lane of a 16-lane row has combined all sixteen of the row's values.
 constexpr int kDppX1 = 0xB1, kDppX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
@@ -89,28 +90,10 @@ __device__ __forceinline__ double wave_sum(double v)
 // unsigned integer, so the largest |a_ik| is an integer maximum of those patterns (rows out of
 // the search take key 0).  The lanes holding the maximum come from a ballot; when there are
 // several (an exact tie), the one of lowest current row position wins.
-template <typename R> struct PivKey;
-template <> struct PivKey<double> { using T = unsigned long long; };
-template <> struct PivKey<float> { using T = unsigned; };
-
-template <int CTRL>
-__device__ __forceinline__ unsigned long long dpp(unsigned long long v)
-{
-    const unsigned lo = (unsigned)dpp<CTRL>((int)(unsigned)v), hi = (unsigned)dpp<CTRL>((int)(unsigned)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp(unsigned v)
 {
     return (unsigned)dpp<CTRL>((int)v);
-}
-
-__device__ __forceinline__ unsigned long long rdlane(unsigned long long v, int l)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
-    return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ unsigned rdlane(unsigned v, int l) { return (unsigned)__builtin_amdgcn_readlane((int)v, l); }
@@ -139,16 +122,31 @@ __device__ __forceinline__ int wave_min(int v)
     return min(min(rdlane(v, 0), rdlane(v, 16)), min(rdlane(v, 32), rdlane(v, 48)));
 }
 
-// Lane holding the pivot row among lanes with `cand` set; `nonzero` is false when the largest
-// candidate magnitude is zero.
+// Lane holding the pivot row among lanes with `cand` set.  For doubles the maximum is taken
+// over the high words first and, among lanes that tie there, over the low words: the same
+// order as the full 64-bit keys, with 32-bit reductions that fuse with DPP.
 template <typename R>
-__device__ __forceinline__ int pivot_lane(R mag, bool cand, int pos, bool &nonzero)
+__device__ __forceinline__ int pivot_lane(R mag, bool cand, int pos)
 {
-    using K = typename PivKey<R>::T;
-    const K key = cand ? __builtin_bit_cast(K, mag) : K(0);
-    const K km = wave_max(key);
-    nonzero = km != K(0);
-    const unsigned long long m = __ballot(cand && key == km);
+    unsigned long long m;
+    if constexpr (sizeof(R) == 8) {
+        const unsigned long long k = cand ? __builtin_bit_cast(unsigned long long, mag) : 0ull;
+        // the reductions run as statements of their own: inside a && they would run on the
+        // candidate lanes only, and the cross-lane reads need every lane
+        const unsigned hi = (unsigned)(k >> 32);
+        const unsigned mh = wave_max(hi);
+        m = __ballot(cand & (hi == mh));
+        if (__builtin_popcountll(m) != 1) {
+            const bool in = (m >> __lane_id()) & 1ull;
+            const unsigned lo = in ? (unsigned)k : 0u;
+            const unsigned ml = wave_max(lo);
+            m = __ballot(in & (lo == ml));
+        }
+    } else {
+        const unsigned k = cand ? __builtin_bit_cast(unsigned, mag) : 0u;
+        const unsigned mk = wave_max(k);
+        m = __ballot(cand & (k == mk));
+    }
     if (__builtin_popcountll(m) == 1) return __builtin_ctzll(m);
     const int pmin = wave_min(((m >> __lane_id()) & 1ull) ? pos : 0x7fffffff);
     return __builtin_ctzll(__ballot(pos == pmin));
@@ -477,37 +475,41 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
 template <int NPAD, typename R>
 __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, R &x)
 {
+    constexpr int B = kLuBlock;
+    static_assert(NPAD % B == 0, "NPAD must be a multiple of the pivot block");
     int pos = lane;
     R dg = R(1);  // the lane's U diagonal element once it has supplied a pivot
     bool ok = true;
-    // blocks of four pivot columns; each block ends by rotating the row left by four, so the
-    // next block's pivot columns sit in a[0..3].  All NPAD / 4 rotations are made, which
-    // brings column j back to a[j] for the back substitution.
-#pragma unroll 1
-    for (int blk = 0; blk < NPAD / 4; ++blk) {
-        if (4 * blk < N) {
+    // blocks of B pivot columns; each block ends by rotating the row left by B, so the next
+    // block's pivot columns sit in a[0..B-1].  All NPAD / B rotations are made, which brings
+    // column j back to a[j] for the back substitution.  Up to NPAD = 40 the block loop is
+    // unrolled, which turns the rotations into register renaming and the skips into constants;
+    // larger rows keep it rolled so that the code stays within the instruction cache.
+    constexpr int kBlkUnroll = NPAD <= 40 ? NPAD / B : 1;
+#pragma unroll kBlkUnroll
+    for (int blk = 0; blk < NPAD / B; ++blk) {
+        if (B * blk < N) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * blk + kk;
+            for (int kk = 0; kk < B; ++kk) {
+                const int k = B * blk + kk;
                 if (k < N) {
-                    bool nz;
-                    const int w = pivot_lane<R>((R)fabs(a[kk]), pos >= k && lane < N, pos, nz);
+                    const int w = pivot_lane<R>((R)fabs(a[kk]), pos >= k && lane < N, pos);
                     const int p = rdlane(pos, w);
-                    ok = ok && nz;
                     pos = (lane == w) ? k : (pos == k ? p : pos);
                     const R piv = rdlane(a[kk], w);
+                    ok = ok && piv != R(0);
                     const R yk = rdlane(bb, w);
                     dg = (lane == w) ? piv : dg;
                     const bool elim = pos > k;
                     const R l = elim ? a[kk] / piv : R(0);
                     bb = fma(-l, yk, bb);
                     // pivot row from the pivot lane's registers, eight columns at a time;
-                    // register positions from NPAD - 4 blk on hold columns already eliminated
+                    // register positions from NPAD - B blk on hold columns already eliminated
                     // (rotated in from the front) and are skipped eight at a time.  Rows that
                     // have supplied a pivot take l = 0 and stay as they are.
 #pragma unroll
                     for (int j0 = kk + 1; j0 < NPAD; j0 += 8) {
-                        if (j0 >= NPAD - 4 * blk) break;
+                        if (j0 >= NPAD - B * blk) break;
                         R pr[8];
 #pragma unroll
                         for (int j = j0; j < j0 + 8 && j < NPAD; ++j) pr[j - j0] = rdlane(a[j], w);
@@ -518,13 +520,13 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, R 
                 }
             }
         }
-        const R t0 = a[0], t1 = a[1], t2 = a[2], t3 = a[3];
+        R t[B];
 #pragma unroll
-        for (int j = 0; j + 4 < NPAD; ++j) a[j] = a[j + 4];
-        a[NPAD - 4] = t0;
-        a[NPAD - 3] = t1;
-        a[NPAD - 2] = t2;
-        a[NPAD - 1] = t3;
+        for (int j = 0; j < B; ++j) t[j] = a[j];
+#pragma unroll
+        for (int j = 0; j + B < NPAD; ++j) a[j] = a[j + B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) a[NPAD - B + j] = t[j];
     }
     // back substitution, columns from the last: the lane holding U row k forms
     // x_k = y_k / u_kk, and every row above k removes u_ik x_k from its y_i
