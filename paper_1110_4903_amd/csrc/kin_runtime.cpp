@@ -329,19 +329,26 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
         }
     }
+    // dense third-body entries (slot q, row s), sorted by row so that the kernel sums a row's
+    // entries in a register and adds the sum to the Jacobian once
     std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR;
     std::vector<int> tbe;
+    for (int s = 0; s < ns; ++s) {
+        for (int r = 0; r < nr; ++r) {
+            const int q = slot[r];
+            if (q < 0) continue;
+            const Rxn &x = h.rx[r];
+            for (int j = 0; j < x.npart; ++j) {
+                if (!x.part[j].nu || x.part[j].sp != s) continue;
+                const double cs = (double)x.part[j].nu * h.M[s];
+                tbe.push_back(q | (s << 16));
+                for (int k = 0; k < ns; ++k) effR.push_back(cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k]);
+            }
+        }
+    }
     for (int r = 0; r < nr; ++r) {
         const int q = slot[r];
         if (q < 0) continue;
-        const Rxn &x = h.rx[r];
-        for (int j = 0; j < x.npart; ++j) {
-            if (!x.part[j].nu) continue;
-            const int s = x.part[j].sp;
-            const double cs = (double)x.part[j].nu * h.M[s];
-            tbe.push_back(q | (s << 16));
-            for (int k = 0; k < ns; ++k) effR.push_back(cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k]);
-        }
         for (int k = 0; k < ns; ++k) effT[(size_t)k * ntb + q] = h.eff[(size_t)slot_row[q] * ns + k];
     }
     const int ntbe = (int)tbe.size();

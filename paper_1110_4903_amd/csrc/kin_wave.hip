@@ -36,6 +36,14 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Read-only tables indexed by wave-uniform values go through the constant address space,
+// which lets the compiler use scalar loads for them.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *uniform_table(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // ---- cross-lane helpers (all lanes of the wavefront must be active) ------------------------
 template <int CTRL>
 __device__ __forceinline__ int dpp(int v)
@@ -337,10 +345,13 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
             dq[j] = 0.0;
         }
     }
+    // Participant slots past the reaction's own count (the pass runs to its largest count) have
+    // species 0, nu = 0 and zero coefficients: they add exact zeros, which costs less than
+    // masking lanes per slot.
     const int JS = NPAD;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        if (i < npmax && i < x.npart && x.part_nu[i] != 0) {
+        if (i < npmax) {
             const int si = x.part_sp[i];
             const double nu = (double)x.part_nu[i];
             const double a = kc->rowc[i];
@@ -349,7 +360,7 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
             lds_add(Jr + t.ns, nu * qT);
 #pragma unroll
             for (int j = 0; j < 6; ++j)
-                if (j < npmax && j < x.npart) lds_add(Jr + x.part_sp[j], a * dq[j]);
+                if (j < npmax) lds_add(Jr + x.part_sp[j], a * dq[j]);
         }
     }
 }
@@ -403,32 +414,47 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
             const RxnRec x = xn;
             const double4 rd = rn;
             const unsigned ps = pn;
-            const int npmax = t.chunk_np[r0 / kW];
+            const int npmax = uniform_table(t.chunk_np)[r0 / kW];
             if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; pn = t.pslot[r + kW]; }
             if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, ps, npmax, iT, lT, lPaRT);
         }
     }
     wave_sync();
-    // dense third-body terms: lane k adds nu_rs M_s (q_f - q_b) eff_rk / M_k to J[s][k], one
-    // (reaction, row) entry per step, eight entries per batch so that their loads overlap
+    // dense third-body terms: J[s][k] gains D_q effR[q,s][k] for every slot q whose reaction has
+    // s among its participants (D_q = q_f - q_b, effR = nu_qs M_s eff_qk / M_k).  Entries come
+    // sorted by row: lane k sums a row's entries in a register and adds the sum once; entries
+    // are loaded eight per batch so that their loads overlap
     {
         const bool col = lane < ns;
         const double *er = t.effR + (col ? lane : 0);
+        const auto *tbe = uniform_table(t.tbe);
+        int cur = t.ntbe > 0 ? (tbe[0] >> 16) : 0;
+        double acc = 0.0;
         for (int e0 = 0; e0 < t.ntbe; e0 += 8) {
             int ent[8];
             double v[8], D[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int e = e0 + q < t.ntbe ? e0 + q : t.ntbe - 1;
-                ent[q] = t.tbe[e];
+                ent[q] = tbe[e];
                 v[q] = er[(size_t)e * ns];
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) D[q] = L.Mc[ent[q] & 0xffff];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (col && e0 + q < t.ntbe) lds_add(L.J + (size_t)(ent[q] >> 16) * JS + lane, D[q] * v[q]);
+            for (int q = 0; q < 8; ++q) {
+                if (e0 + q < t.ntbe) {
+                    const int s = ent[q] >> 16;
+                    if (s != cur) {
+                        if (col) lds_add(L.J + (size_t)cur * JS + lane, acc);
+                        acc = 0.0;
+                        cur = s;
+                    }
+                    acc = fma(D[q], v[q], acc);
+                }
+            }
         }
+        if (col && t.ntbe > 0) lds_add(L.J + (size_t)cur * JS + lane, acc);
     }
     wave_sync();
     // species rows of f and the temperature column; e_s and cv_s replace g and h
