@@ -259,17 +259,13 @@ __device__ __forceinline__ bool invert_T(const WaveTables &t, int lane, double x
     return true;
 }
 
-// c^nu for nu in 0..3
-__device__ __forceinline__ double cpow_nu(double c, int nu)
+// c^nu and d(c^nu)/dc = nu c^(nu-1) for nu in 0..3, without branches: h = c^(nu-1) (1 for
+// nu <= 1) is a product of selected factors, then c^nu = (nu >= 1 ? c : 1) h.
+__device__ __forceinline__ void cpow_nu(double c, int nu, double &p, double &dp)
 {
-    const double c2 = c * c;
-    return nu == 0 ? 1.0 : (nu == 1 ? c : (nu == 2 ? c2 : c2 * c));
-}
-
-// d(c^nu)/dc = nu c^(nu-1)
-__device__ __forceinline__ double dcpow_nu(double c, int nu)
-{
-    return nu == 0 ? 0.0 : (nu == 1 ? 1.0 : (nu == 2 ? 2.0 * c : 3.0 * c * c));
+    const double h = (nu >= 2 ? c : 1.0) * (nu >= 3 ? c : 1.0);
+    p = (nu >= 1 ? c : 1.0) * h;
+    dp = (double)nu * h;
 }
 
 // Rates and Jacobian terms of reaction r (lane-owned), added into W and J.
@@ -290,8 +286,7 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
     for (int m = 0; m < 3; ++m) {
         const int nu = m < x.nreac ? x.reac_nu[m] : 0;
         cr[m] = L.c[x.reac_sp[m]];
-        pr[m] = cpow_nu(cr[m], nu);
-        dr[m] = dcpow_nu(cr[m], nu);
+        cpow_nu(cr[m], nu, pr[m], dr[m]);
     }
     const double pf = kf * (pr[0] * pr[1] * pr[2]);
     double dpf[3];
@@ -301,12 +296,22 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
     double pb = 0.0, dlKc = 0.0, dpb[3] = {0.0, 0.0, 0.0};
     if (x.rev) {
         double sg = 0.0, sh = 0.0;
+        double gv[6], hv[6];  // all reads first, so that they overlap
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            if (j < npmax && j < x.npart) {
+            gv[j] = 0.0;
+            hv[j] = 0.0;
+            if (j < npmax) {
+                gv[j] = L.g[x.part_sp[j]];
+                hv[j] = L.hh[x.part_sp[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (j < npmax) {  // padding slots have nu = 0
                 const double nu = (double)x.part_nu[j];
-                sg = fma(nu, L.g[x.part_sp[j]], sg);
-                sh = fma(nu, L.hh[x.part_sp[j]], sh);
+                sg = fma(nu, gv[j], sg);
+                sh = fma(nu, hv[j], sh);
             }
         }
         const double lKc = dnu * lPaRT - sg;
@@ -317,15 +322,15 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
         for (int m = 0; m < 3; ++m) {
             const int nu = m < x.nprod ? x.prod_nu[m] : 0;
             cp[m] = L.c[x.prod_sp[m]];
-            pp[m] = cpow_nu(cp[m], nu);
-            dp[m] = dcpow_nu(cp[m], nu);
+            cpow_nu(cp[m], nu, pp[m], dp[m]);
         }
         pb = kb * (pp[0] * pp[1] * pp[2]);
         dpb[0] = kb * (dp[0] * pp[1] * pp[2]);
         dpb[1] = kb * (pp[0] * dp[1] * pp[2]);
         dpb[2] = kb * (pp[0] * pp[1] * dp[2]);
     }
-    const double Mc = (x.tb >= 0) ? L.Mc[x.tb] : 1.0;
+    const double Mc_read = (t.ntb > 0) ? L.Mc[x.tb >= 0 ? x.tb : 0] : 1.0;  // read on every lane
+    const double Mc = (x.tb >= 0) ? Mc_read : 1.0;
     const double D = pf - pb;
     const double q = Mc * D;
     const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
