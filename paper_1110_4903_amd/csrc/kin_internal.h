@@ -69,19 +69,24 @@ namespace kin {
 // initial-energy kernel).  All pointers point into one allocation.
 constexpr int kChunk = 64;   // reactions evaluated per wavefront pass
 
-// Compact reaction record (32 bytes): counts, third-body row, merged reactant and product
-// lists and the participant list with net coefficients, all as small integers.
+// Compact reaction record (48 bytes).  A reaction has six species slots: reactants in slots
+// 0-2 and products in slots 3-5 (species merged within each side; unused slots have nu = 0
+// and species 0).  nu holds the slot's signed stoichiometric coefficient (-nu' for a reactant,
+// +nu'' for a product); coff and roff are byte offsets of the slot's species in a species
+// vector (8 s) and of its row in the Jacobian (8 s NPAD, NPAD the padded row length).
 struct RxnRec {
-    int8_t rev, nreac, nprod, npart;
+    int8_t rev, pad0;
     int16_t tb;
-    int8_t reac_sp[3], reac_nu[3], prod_sp[3], prod_nu[3];
-    int8_t part_sp[6], part_nu[6];
-    int8_t pad2[2];
+    int8_t nu[6];
+    int8_t pad1[2];
+    uint16_t coff[6];
+    uint16_t roff[6];
+    int8_t pad2[12];
 };
-static_assert(sizeof(RxnRec) == 32, "reaction record must stay 32 bytes");
+static_assert(sizeof(RxnRec) == 48, "reaction record must stay 48 bytes");
 
-// Per-reaction coefficients of the Jacobian scatter, one slot per participant j: the row factor
-// nu_rj M_j (zero when the net coefficient is zero) and the column factor 1 / M_j.
+// Per-reaction coefficients of the Jacobian scatter, one entry per slot: the row factor
+// nu M_s (signed, zero for unused slots) and the column factor 1 / M_s (zero for unused slots).
 struct RxnCoef {
     double rowc[6];
     double colc[6];
@@ -94,15 +99,16 @@ struct WaveTables {
     const double *nasa;     // [ns][14]
     const double *Tmid;     // [ns]
     const double *M;        // [ns] g/mol
-    // reaction tables are stored in order of participant count (not the mechanism's order)
+    // reaction tables are stored in order of (reactant count, product count), not in the
+    // mechanism's order
     const double *rxd;      // [nr][4]: ln A, b, Ta, sum nu
     const RxnRec *rxc;      // [nr]
     const RxnCoef *rxk;     // [nr]
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
     const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
     const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
-    const unsigned *pslot;  // [nr] per participant j, bits 4j..4j+3: reactant slot | product slot << 2 (3 = none)
-    const int *chunk_np;    // [nchunk] largest participant count of each pass of 64 reactions
+    const int *chunk_rp;    // [nchunk] largest reactant count | largest product count << 8, per
+                            // pass of 64 reactions
 };
 
 // Device layout of one instance's arena (n cells, ns species), from its base address:

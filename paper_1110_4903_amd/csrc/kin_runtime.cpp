@@ -277,56 +277,50 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             slot_row.push_back(h.rx[r].tb);
         }
     const int ntb = (int)slot_row.size();
-    // reactions in order of participant count, so that each pass of 64 lanes is homogeneous
-    // and its loops over participants stop at the pass's largest count
+    // reactions in order of (reactant count, product count), so that each pass of 64 lanes is
+    // homogeneous and its loops over slots stop at the pass's largest counts
+    const int npad = wave_npad(ns + 1);
     std::vector<int> perm(nr);
     for (int r = 0; r < nr; ++r) perm[r] = r;
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return h.rx[a].npart < h.rx[b].npart; });
-    std::vector<int> chunk_np(nchunk, 0);
-    for (int i = 0; i < nr; ++i) chunk_np[i / kChunk] = std::max(chunk_np[i / kChunk], h.rx[perm[i]].npart);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        const Rxn &x = h.rx[a], &y = h.rx[b];
+        return x.nreac != y.nreac ? x.nreac < y.nreac : x.nprod < y.nprod;
+    });
+    std::vector<int> chunk_rp(nchunk, 0);
+    for (int i = 0; i < nr; ++i) {
+        const Rxn &x = h.rx[perm[i]];
+        int &c = chunk_rp[i / kChunk];
+        c = std::max(c & 0xff, x.nreac) | (std::max(c >> 8, x.nprod) << 8);
+    }
     std::vector<double> rxd((size_t)nr * 4);
     std::vector<RxnRec> rxc(nr);
-    std::vector<unsigned> pslot(nr, 0u);
+    std::vector<RxnCoef> rxk(nr);
     for (int i = 0; i < nr; ++i) {
         const int r = perm[i];
         const Rxn &x = h.rx[r];
-        // per participant j, 4 bits: reactant slot (bits 0-1, 3 = none), product slot (bits 2-3)
-        unsigned ps = 0;
-        for (int j = 0; j < 6; ++j) {
-            unsigned rs = 3, qs = 3;
-            if (j < x.npart) {
-                for (int m = 0; m < x.nreac; ++m) if (x.reac_sp[m] == x.part[j].sp) rs = (unsigned)m;
-                for (int m = 0; m < x.nprod; ++m) if (x.prod_sp[m] == x.part[j].sp) qs = (unsigned)m;
-            }
-            ps |= (rs | (qs << 2)) << (4 * j);
-        }
-        pslot[i] = ps;
         rxd[4 * i + 0] = x.lnA;
         rxd[4 * i + 1] = x.b;
         rxd[4 * i + 2] = x.Ta;
         rxd[4 * i + 3] = (double)x.dnu;
         RxnRec &p = rxc[i];
-        std::memset(&p, 0, sizeof p);
-        p.rev = (int8_t)x.rev; p.nreac = (int8_t)x.nreac; p.nprod = (int8_t)x.nprod;
-        p.npart = (int8_t)x.npart; p.tb = (int16_t)slot[r];
-        for (int j = 0; j < 3; ++j) {
-            p.reac_sp[j] = (int8_t)(j < x.nreac ? x.reac_sp[j] : 0);
-            p.reac_nu[j] = (int8_t)(j < x.nreac ? x.reac_nu[j] : 0);
-            p.prod_sp[j] = (int8_t)(j < x.nprod ? x.prod_sp[j] : 0);
-            p.prod_nu[j] = (int8_t)(j < x.nprod ? x.prod_nu[j] : 0);
-        }
-        for (int j = 0; j < 6; ++j) {
-            p.part_sp[j] = (int8_t)(j < x.npart ? x.part[j].sp : 0);
-            p.part_nu[j] = (int8_t)(j < x.npart ? x.part[j].nu : 0);
-        }
-    }
-    std::vector<RxnCoef> rxk(nr);
-    for (int i = 0; i < nr; ++i) {
-        const Rxn &x = h.rx[perm[i]];
         RxnCoef &k = rxk[i];
-        for (int j = 0; j < 6; ++j) {
-            k.rowc[j] = j < x.npart ? (double)x.part[j].nu * h.M[x.part[j].sp] : 0.0;
-            k.colc[j] = j < x.npart ? 1.0 / h.M[x.part[j].sp] : 0.0;
+        std::memset(&p, 0, sizeof p);
+        std::memset(&k, 0, sizeof k);
+        p.rev = (int8_t)x.rev;
+        p.tb = (int16_t)slot[r];
+        for (int m = 0; m < 3; ++m) {
+            for (int side = 0; side < 2; ++side) {
+                const int n = side ? x.nprod : x.nreac;
+                if (m >= n) continue;
+                const int sp = side ? x.prod_sp[m] : x.reac_sp[m];
+                const int nu = side ? x.prod_nu[m] : -x.reac_nu[m];
+                const int q = 3 * side + m;
+                p.nu[q] = (int8_t)nu;
+                p.coff[q] = (uint16_t)(8 * sp);
+                p.roff[q] = (uint16_t)(8 * sp * npad);
+                k.rowc[q] = (double)nu * h.M[sp];
+                k.colc[q] = 1.0 / h.M[sp];
+            }
         }
     }
     // dense third-body entries (slot q, row s), sorted by row so that the kernel sums a row's
@@ -361,8 +355,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
-        {tbe.data(), sizeof(int) * tbe.size(), 0}, {pslot.data(), sizeof(unsigned) * pslot.size(), 0},
-        {chunk_np.data(), sizeof(int) * chunk_np.size(), 0}};
+        {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -383,8 +376,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.effT = reinterpret_cast<const double *>(b + pc[6].off);
     t.effR = reinterpret_cast<const double *>(b + pc[7].off);
     t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
-    t.pslot = reinterpret_cast<const unsigned *>(b + pc[9].off);
-    t.chunk_np = reinterpret_cast<const int *>(b + pc[10].off);
+    t.chunk_rp = reinterpret_cast<const int *>(b + pc[9].off);
     return KIN_OK;
 }
 

@@ -269,103 +269,83 @@ __device__ __forceinline__ void cpow_nu(double c, int nu, double &p, double &dp)
 }
 
 // Rates and Jacobian terms of reaction r (lane-owned), added into W and J.
-//   Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''),  dQ_r/dc_k over the participants,
-//   J[s][k] += (nu_rs M_s)(dQ_r/dc_k / M_k),  W[s] += nu_rs Q_r,  J[s][N-1] += nu_rs dQ_r/dT.
+//   Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''),  dQ_r/dc over the six species slots,
+//   J[s][k] += (nu_s M_s)(dQ_r/dc_k / M_k),  W[s] += nu_s Q_r,  J[s][N-1] += nu_s dQ_r/dT.
+// Slots 0-2 are the reactants, 3-5 the products; a species on both sides appears in one slot
+// of each, and its two terms add up in J.  The loops over slots stop at the pass's largest
+// counts (rmax reactants, pmax products); shorter reactions' unused slots add exact zeros.
 template <int NPAD>
 __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
-                                               const double4 &rd, unsigned ps, int npmax, double iT,
+                                               const double4 &rd, int rmax, int pmax, double iT,
                                                double lT, double lPaRT)
 {
     const double lnA = rd.x, b = rd.y, Ta = rd.z, dnu = rd.w;
     const RxnCoef *kc = t.rxk + r;
+    const char *cb = reinterpret_cast<const char *>(L.c);
+    const char *gb = reinterpret_cast<const char *>(L.g);
+    const char *hb = reinterpret_cast<const char *>(L.hh);
+    const auto used = [&](int q) { return q < 3 ? q < rmax : q - 3 < pmax; };
     const double lkf = fma(-Ta, iT, fma(b, lT, lnA));
     const double kf = exp(lkf);
     const double dlkf = fma(Ta, iT, b) * iT;
-    double cr[3], pr[3], dr[3];
+    // slot concentrations, their powers c^|nu| and derivatives, and the equilibrium sums
+    double pw[6], dpw[6], gv[6], hv[6];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const int nu = m < x.nreac ? x.reac_nu[m] : 0;
-        cr[m] = L.c[x.reac_sp[m]];
-        cpow_nu(cr[m], nu, pr[m], dr[m]);
+    for (int q = 0; q < 6; ++q) {
+        double c = 1.0;
+        gv[q] = 0.0;
+        hv[q] = 0.0;
+        if (used(q)) {
+            c = *reinterpret_cast<const double *>(cb + x.coff[q]);
+            gv[q] = *reinterpret_cast<const double *>(gb + x.coff[q]);
+            hv[q] = *reinterpret_cast<const double *>(hb + x.coff[q]);
+        }
+        cpow_nu(c, q < 3 ? -x.nu[q] : x.nu[q], pw[q], dpw[q]);
     }
-    const double pf = kf * (pr[0] * pr[1] * pr[2]);
-    double dpf[3];
-    dpf[0] = kf * (dr[0] * pr[1] * pr[2]);
-    dpf[1] = kf * (pr[0] * dr[1] * pr[2]);
-    dpf[2] = kf * (pr[0] * pr[1] * dr[2]);
-    double pb = 0.0, dlKc = 0.0, dpb[3] = {0.0, 0.0, 0.0};
-    if (x.rev) {
-        double sg = 0.0, sh = 0.0;
-        double gv[6], hv[6];  // all reads first, so that they overlap
+    const double pf = kf * (pw[0] * pw[1] * pw[2]);
+    double dq[6];
+    dq[0] = kf * (dpw[0] * pw[1] * pw[2]);
+    dq[1] = kf * (pw[0] * dpw[1] * pw[2]);
+    dq[2] = kf * (pw[0] * pw[1] * dpw[2]);
+    double sg = 0.0, sh = 0.0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            gv[j] = 0.0;
-            hv[j] = 0.0;
-            if (j < npmax) {
-                gv[j] = L.g[x.part_sp[j]];
-                hv[j] = L.hh[x.part_sp[j]];
-            }
+    for (int q = 0; q < 6; ++q) {
+        if (used(q)) {
+            const double nu = (double)x.nu[q];
+            sg = fma(nu, gv[q], sg);
+            sh = fma(nu, hv[q], sh);
         }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            if (j < npmax) {  // padding slots have nu = 0
-                const double nu = (double)x.part_nu[j];
-                sg = fma(nu, gv[j], sg);
-                sh = fma(nu, hv[j], sh);
-            }
-        }
-        const double lKc = dnu * lPaRT - sg;
-        const double kb = exp(lkf - lKc);
-        dlKc = (sh - dnu) * iT;
-        double cp[3], pp[3], dp[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const int nu = m < x.nprod ? x.prod_nu[m] : 0;
-            cp[m] = L.c[x.prod_sp[m]];
-            cpow_nu(cp[m], nu, pp[m], dp[m]);
-        }
-        pb = kb * (pp[0] * pp[1] * pp[2]);
-        dpb[0] = kb * (dp[0] * pp[1] * pp[2]);
-        dpb[1] = kb * (pp[0] * dp[1] * pp[2]);
-        dpb[2] = kb * (pp[0] * pp[1] * dp[2]);
     }
+    const double lKc = dnu * lPaRT - sg;
+    const double kb = exp(lkf - lKc);
+    const double dlKc = (sh - dnu) * iT;
+    // irreversible reactions take k_b = 0 by selection (k_b itself may overflow)
+    const bool rev = x.rev != 0;
+    const double pb = rev ? kb * (pw[3] * pw[4] * pw[5]) : 0.0;
+    dq[3] = rev ? -kb * (dpw[3] * pw[4] * pw[5]) : 0.0;
+    dq[4] = rev ? -kb * (pw[3] * dpw[4] * pw[5]) : 0.0;
+    dq[5] = rev ? -kb * (pw[3] * pw[4] * dpw[5]) : 0.0;
     const double Mc_read = (t.ntb > 0) ? L.Mc[x.tb >= 0 ? x.tb : 0] : 1.0;  // read on every lane
     const double Mc = (x.tb >= 0) ? Mc_read : 1.0;
     const double D = pf - pb;
     const double q = Mc * D;
     const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
     if (x.tb >= 0) L.Mc[x.tb] = D;  // the slot's [M] has been read; the dense pass needs D
-    // dQ/dc_k / M_k for each participant k
-    // participant j takes d/dc of its reactant slot's term minus its product slot's term
-    // (species are merged within each side, so each side has at most one slot)
-    double dq[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        if (j < npmax) {
-            const unsigned rs = (ps >> (4 * j)) & 3u, qs = (ps >> (4 * j + 2)) & 3u;
-            const double gf = rs == 0 ? dpf[0] : (rs == 1 ? dpf[1] : (rs == 2 ? dpf[2] : 0.0));
-            const double gb = qs == 0 ? dpb[0] : (qs == 1 ? dpb[1] : (qs == 2 ? dpb[2] : 0.0));
-            dq[j] = Mc * (gf - gb) * kc->colc[j];
-        } else {
-            dq[j] = 0.0;
-        }
-    }
-    // Participant slots past the reaction's own count (the pass runs to its largest count) have
-    // species 0, nu = 0 and zero coefficients: they add exact zeros, which costs less than
-    // masking lanes per slot.
-    const int JS = NPAD;
+    for (int k = 0; k < 6; ++k) dq[k] = Mc * dq[k] * kc->colc[k];  // dQ/dc_k / M_k
+    char *Jb = reinterpret_cast<char *>(L.J);
+    char *Wb = reinterpret_cast<char *>(L.W);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        if (i < npmax) {
-            const int si = x.part_sp[i];
-            const double nu = (double)x.part_nu[i];
+        if (used(i)) {
+            const double nu = (double)x.nu[i];
             const double a = kc->rowc[i];
-            lds_add(L.W + si, nu * q);
-            double *Jr = L.J + (size_t)si * JS;
-            lds_add(Jr + t.ns, nu * qT);
+            lds_add(reinterpret_cast<double *>(Wb + x.coff[i]), nu * q);
+            char *Jr = Jb + x.roff[i];
+            lds_add(reinterpret_cast<double *>(Jr + 8 * t.ns), nu * qT);
 #pragma unroll
             for (int j = 0; j < 6; ++j)
-                if (j < npmax) lds_add(Jr + x.part_sp[j], a * dq[j]);
+                if (used(j)) lds_add(reinterpret_cast<double *>(Jr + x.coff[j]), a * dq[j]);
         }
     }
 }
@@ -412,16 +392,14 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         const double4 *rxd4 = reinterpret_cast<const double4 *>(t.rxd);
         RxnRec xn{};
         double4 rn{};
-        unsigned pn = 0u;
-        if (lane < t.nr) { xn = t.rxc[lane]; rn = rxd4[lane]; pn = t.pslot[lane]; }
+        if (lane < t.nr) { xn = t.rxc[lane]; rn = rxd4[lane]; }
         for (int r0 = 0; r0 < t.nr; r0 += kW) {
             const int r = r0 + lane;
             const RxnRec x = xn;
             const double4 rd = rn;
-            const unsigned ps = pn;
-            const int npmax = uniform_table(t.chunk_np)[r0 / kW];
-            if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; pn = t.pslot[r + kW]; }
-            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, ps, npmax, iT, lT, lPaRT);
+            const int rp = uniform_table(t.chunk_rp)[r0 / kW];
+            if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; }
+            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, rp & 0xff, rp >> 8, iT, lT, lPaRT);
         }
     }
     wave_sync();
