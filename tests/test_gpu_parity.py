@@ -353,3 +353,56 @@ def test_divergence_test_off_matches_oracle(ctx, orc):
         report(f"diverge off {name}", s)
         assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
         assert s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+@pytest.mark.parametrize("ns,nr,ne", [(20, 120, 3), (28, 200, 4), (45, 360, 4), (60, 480, 4)])
+def test_wave_layout_other_row_lengths(ctx, orc, ns, nr, ne):
+    """Generated mechanisms whose padded Jacobian rows (24, 32, 48, 64 columns) select the other
+    instantiations of the wave kernel, 128 cells, FP64 and FP32-LU, against the oracle."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m = synth.make_mechanism(synth.MechRecipe(f"gen{ns}", seed=100 + ns, n_elements=ne, n_species=ns,
+                                              n_reactions=nr, frac_third_body=0.15,
+                                              frac_irreversible=0.3))
+    st = synth.uniform_cells(200 + ns, 128, ns, 0.5)
+    om, ref = run_oracle(orc, m, st, 1e-6)
+    for prec, rtol in ((kin.FP64, 1e-10), (kin.FP32_LU, 1e-6)):
+        gpu = run_gpu(ctx, m, st, 1e-6, prec=prec)
+        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, rtol)
+        report(f"gen{ns} prec {prec}", s)
+        if prec == kin.FP64:
+            assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0
+
+
+def both_sides_mech():
+    """H, H2, O, OH, H2O, O2: a third-order reaction with H on both sides (3 H => H2 + H), a
+    product with nu = 2, an irreversible reaction and a third-body reaction."""
+    from tests.test_oracle_pins import nasa_const
+    nas = [nasa_const(2.5, 2600.0, 14.0), nasa_const(3.5, 0.0, 16.0), nasa_const(2.5, 3000.0, 19.0),
+           nasa_const(3.6, 450.0, 22.0), nasa_const(4.0, -2900.0, 23.0), nasa_const(3.5, 0.0, 25.0)]
+    comp = [[1, 0], [2, 0], [0, 1], [1, 1], [2, 1], [0, 2]]
+    rx = [dict(reac=[(0, 3)], prod=[(1, 1), (0, 1)], A=1e15, b=-0.5, Ta=0.0),
+          dict(reac=[(2, 1), (4, 1)], prod=[(3, 2)], A=3e13, b=0.0, Ta=9000.0),
+          dict(reac=[(1, 1), (5, 1)], prod=[(3, 2)], A=1e12, b=0.5, Ta=20000.0, reversible=False),
+          dict(reac=[(0, 1), (3, 1)], prod=[(4, 1)], A=2e17, b=-1.0, Ta=0.0, tb=0),
+          dict(reac=[(0, 1), (5, 1)], prod=[(3, 1), (2, 1)], A=2e14, b=0.0, Ta=8000.0)]
+    return synth.mechanism_from_lists("bothsides", ("H", "O"), comp, nas, rx,
+                                      eff=[[1.0, 2.5, 1.0, 1.0, 6.0, 1.0]])
+
+
+def test_species_on_both_sides_both_layouts(ctx, orc):
+    """A species on both sides of a reaction enters the wave layout's reactant and product
+    slots separately; both layouts against the oracle, FP64."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    m = both_sides_mech()
+    st = synth.uniform_cells(77, 300, m.ns, 1.0)
+    om, ref = run_oracle(orc, m, st, 1e-6)
+    assert np.all(ref[2] < 2)
+    for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
+        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout))
+        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
+        report(f"both sides layout {layout}", s)
+        assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2, (layout, s)
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0, (layout, s)
