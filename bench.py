@@ -188,6 +188,48 @@ def run_config0_end_to_end(torch, ctx, kin, synth, stream):
                 ms_per_round=1e3 * el / reps)
 
 
+def run_conserved_adapter(torch, ctx, kin, synth, args, stream):
+    """The chemistry sub-step of the operator split on the headline grid, FP64: partial
+    densities and sensible energy in (device buffers), advance one dt, partial densities and
+    sensible energy out.  The conserved input is made by the library itself from the grid's
+    state.  Reports the time of the two conversions beside the advance."""
+    nx = 256 if args.quick else 1024
+    m, grid, dt = synth.workload_grid_mech9(nx, nx)
+    mid = ctx.mech_upload(m)
+    st = device_state(torch, grid)
+    iid = ctx.state_upload(mid, st["rho"], st["T"], st["Y"], stream=stream)
+    rho_s = torch.empty((m.ns, grid.n), dtype=torch.float64, device="cuda")
+    E = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    ctx.download_conserved_device(iid, rho_s, E, stream=stream)
+    out_s = torch.empty_like(rho_s)
+    out_E = torch.empty_like(E)
+    for _ in range(2):
+        ctx.state_reset_conserved(iid, rho_s, E, stream=stream)
+        ctx.advance([iid], [dt], stream=stream)
+        ctx.download_conserved_device(iid, out_s, out_E, stream=stream)
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.state_reset_conserved(iid, rho_s, E, stream=stream)
+        ev[3 * k + 1].record(stream)
+        ctx.advance([iid], [dt], stream=stream)
+        ev[3 * k + 2].record(stream)
+        ctx.download_conserved_device(iid, out_s, out_E, stream=stream)
+        ev[3 * k + 3].record(stream)
+    torch.cuda.synchronize()
+    t_in = sum(ev[3 * k].elapsed_time(ev[3 * k + 1]) for k in range(steps)) / steps
+    t_adv = sum(ev[3 * k + 1].elapsed_time(ev[3 * k + 2]) for k in range(steps)) / steps
+    t_out = sum(ev[3 * k + 2].elapsed_time(ev[3 * k + 3]) for k in range(steps)) / steps
+    total = t_in + t_adv + t_out
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    return dict(cells=grid.n, steps=steps, ms_conserved_in=t_in, ms_advance=t_adv,
+                ms_conserved_out=t_out, cells_per_s=grid.n / (total * 1e-3),
+                adapter_share=(t_in + t_out) / total)
+
+
 def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     n36 = (1 << 14) if args.quick else (1 << 18)
     m36, s36, dt36 = synth.workload_mech36(n36)
@@ -347,6 +389,9 @@ def run_gpu(args):
         if args.only == "all":
             log("config 0 end to end (host buffers)")
             res["mech9_4096_end_to_end_host_buffers"] = run_config0_end_to_end(torch, ctx, kin, synth, stream)
+        if args.only in ("all", "adapter"):
+            log("operator-split adapter on the headline grid")
+            res["mech9_conserved_adapter_fp64"] = run_conserved_adapter(torch, ctx, kin, synth, args, stream)
     if args.only in ("all", "batch") and not args.no_batch:
         res["batch64"] = run_batch(torch, kin, synth, args, stream)
     if args.only in ("all", "serve") and not args.no_serve:
@@ -414,7 +459,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--quick", action="store_true", help="small sizes, for smoke runs")
-    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "batch", "serve", "copy"),
+    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "batch", "serve", "copy"),
                     help="run one part (for profiler runs); the JSON line needs the headline")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -183,6 +183,40 @@ kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, dou
 kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched, kin_mem where,
                                  void *stream);
 
+/* Operator-split adapter (Sec. 2: the energy equation and the operator-splitting equation).
+ * The fluid side of the split carries partial densities and an energy that leaves out the
+ * species formation energies; the chemistry sub-step changes the partial densities and must
+ * account for the change of formation energy in that energy.  Here the left-out part of each
+ * species' internal energy is its value at T_ref = 298.15 K, e_s(T_ref) (J/kg, NASA-7 h with
+ * the formation enthalpy), so the fluid-side energy is the sensible internal energy
+ *     E_sens = sum_s rho_s (e_s(T) - e_s(T_ref))        (J/m^3, kinetic energy excluded).
+ *
+ * kin_state_upload_conserved creates an instance from rho_s [Ns][n] (kg/m^3, species-major)
+ * and E_sens [n]: rho = sum_s rho_s, Y_s = rho_s / rho, e0 = E_sens / rho + sum_s Y_s
+ * e_s(T_ref), and T the root of e(Y, T) = e0 in [200, 6000] K found by Newton from T_guess [n]
+ * (NULL: 1500 K) with a bisection fallback; a cell without a root gets T = NaN, which the next
+ * kin_advance reports as bad input.  All three arrays live where `where` says (host copies
+ * complete before return); the conversion runs on the device on `stream`.  Errors as
+ * kin_state_upload. */
+kin_status kin_state_upload_conserved(kin_ctx *ctx, int32_t mech_id, int64_t n_cells,
+                                      const double *rho_s, const double *E_sens,
+                                      const double *T_guess, kin_mem where, void *stream,
+                                      int32_t *inst_id);
+
+/* The same conversion into an existing instance of the same cell count, without allocating. */
+kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double *rho_s,
+                                     const double *E_sens, const double *T_guess, kin_mem where,
+                                     void *stream);
+
+/* The inverse conversion of an instance's current state into caller buffers: rho_s [Ns][n] =
+ * rho Y_s and E_sens [n] = rho (e0 - sum_s Y_s e_s(T_ref)).  Since kin_advance holds rho and e0,
+ * E_sens after a step differs from E_sens before it by minus the change of formation energy,
+ * sum_s (rho_s,before - rho_s,after) e_s(T_ref): the source term of the energy equation.
+ * Device destinations: computed in place on `stream`.  Host or pinned destinations: through a
+ * stream-ordered device staging buffer; host copies complete before return. */
+kin_status kin_download_conserved(kin_ctx *ctx, int32_t inst_id, double *rho_s, double *E_sens,
+                                  kin_mem where, void *stream);
+
 /* Wait for `stream` (NULL = the null stream). */
 kin_status kin_sync(kin_ctx *ctx, void *stream);
 

@@ -98,6 +98,11 @@ def make_opts(rtol=None, atol_Y=None, atol_T=None, y_neg=None, k_max=None, L_max
     return o
 
 
+# Reference temperature of the fluid side's sensible energy (K): the species formation
+# energies it leaves out are e_s(T_REF).
+T_REF = 298.15
+
+
 class OracleMech:
     """Holds contiguous copies of a synth.Mechanism's arrays and the C view of them."""
 
@@ -177,6 +182,45 @@ class OracleMech:
         lib().orc_term_scale(self.ref, float(rho), _p(np.ascontiguousarray(Y_prev, np.float64)),
                              _p(np.ascontiguousarray(x, np.float64)), float(h), _p(S))
         return S
+
+    # -- operator-split adapter (Sec. 2: the energy equation and the operator-splitting
+    #    equation; the fluid side's energy leaves out the species formation energies) ---------
+    def formation_energies(self):
+        """e_s(T_ref) in J/kg at T_ref = 298.15 K: the part of each species' internal energy
+        (NASA-7 h with the formation enthalpy, minus RT) that the fluid-side energy leaves out."""
+        unit = np.eye(self.ns)
+        return np.array([self.energy(unit[s], T_REF) for s in range(self.ns)])
+
+    def from_conserved(self, rho_s, E_sens, T_guess=None):
+        """(rho, Y, T, e0, ok) from partial densities rho_s[Ns][n] (kg/m^3) and the sensible
+        energy E_sens[n] = sum_s rho_s (e_s(T) - e_s(T_ref)) (J/m^3): rho = sum rho_s,
+        Y = rho_s / rho, e0 = E_sens / rho + sum_s Y_s e_s(T_ref), T the root of e(Y, T) = e0
+        (Newton from T_guess or 1500 K, then bisection); ok is False (and T NaN) without a root."""
+        rho_s = np.asarray(rho_s, np.float64)
+        E_sens = np.asarray(E_sens, np.float64)
+        n = rho_s.shape[1]
+        ef = self.formation_energies()
+        rho = rho_s.sum(axis=0)
+        Y = rho_s / rho
+        e0 = E_sens / rho + ef @ Y
+        T = np.full(n, np.nan)
+        ok = np.zeros(n, bool)
+        for i in range(n):
+            start = 1500.0 if T_guess is None else float(T_guess[i])
+            if not 200.0 <= start <= 6000.0:
+                start = 1500.0
+            rc, Ti = self.invert_T(Y[:, i], e0[i], start)
+            if rc == 0:
+                T[i], ok[i] = Ti, True
+        return rho, Y, T, e0, ok
+
+    def to_conserved(self, rho, Y, e0):
+        """(rho_s[Ns][n], E_sens[n]) of cells with density rho, mass fractions Y and internal
+        energy e0 (formation energies included): rho_s = rho Y, E_sens = rho (e0 - sum Y e_s(T_ref))."""
+        ef = self.formation_energies()
+        rho = np.asarray(rho, np.float64)
+        Y = np.asarray(Y, np.float64)
+        return rho * Y, rho * (np.asarray(e0, np.float64) - ef @ Y)
 
     # -- batch ------------------------------------------------------------------------------
     def energy_batch(self, T, Y):

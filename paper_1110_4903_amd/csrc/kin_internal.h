@@ -104,6 +104,7 @@ struct WaveTables {
     const double *rxd;      // [nr][4]: ln A, b, Ta, sum nu
     const RxnRec *rxc;      // [nr]
     const RxnCoef *rxk;     // [nr]
+    const double *ef;       // [ns] e_s(T_ref) at T_ref = 298.15 K, J/kg (conserved-variable adapter)
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
     const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
     const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
@@ -172,6 +173,11 @@ struct AdvanceArgs {
 
 // Host launchers of the precompiled kernels (kin_wave.hip).
 int wave_npad(int n);
+hipError_t launch_conserved_in(const WaveTables &t, long long n, long long ld, double *rho, double *T,
+                               double *Y, double *e0, bool have_guess, hipStream_t s);
+hipError_t launch_conserved_out(const WaveTables &t, long long n, long long ld, const double *rho,
+                                const double *Y, const double *e0, double *rho_s, double *E_sens,
+                                hipStream_t s);
 hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,
                          const double *Y, double *e0, hipStream_t stream);
 hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, int waves_per_block,

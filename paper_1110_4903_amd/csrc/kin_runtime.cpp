@@ -325,6 +325,14 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     }
     // dense third-body entries (slot q, row s), sorted by row so that the kernel sums a row's
     // entries in a register and adds the sum to the Jacobian once
+    // e_s(T_ref) at T_ref = 298.15 K (J/kg) for the conserved-variable adapter
+    std::vector<double> ef(ns);
+    for (int s = 0; s < ns; ++s) {
+        const double Tr = 298.15;
+        const double *a = &h.nasa[(size_t)14 * s + (Tr < h.Tmid[s] ? 0 : 7)];
+        const double h_RT = a[0] + Tr * (a[1] / 2 + Tr * (a[2] / 3 + Tr * (a[3] / 4 + Tr * a[4] / 5))) + a[5] / Tr;
+        ef[s] = 8.31446261815324e3 / h.M[s] * Tr * (h_RT - 1.0);
+    }
     std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR;
     std::vector<int> tbe;
     for (int s = 0; s < ns; ++s) {
@@ -355,7 +363,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
-        {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0}};
+        {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0},
+        {ef.data(), sizeof(double) * ns, 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -377,6 +386,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.effR = reinterpret_cast<const double *>(b + pc[7].off);
     t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
     t.chunk_rp = reinterpret_cast<const int *>(b + pc[9].off);
+    t.ef = reinterpret_cast<const double *>(b + pc[10].off);
     return KIN_OK;
 }
 
@@ -575,18 +585,10 @@ static kin_status fill_state(kin_ctx *ctx, Inst &in, const Mech &m, const double
     return KIN_OK;
 }
 
-kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, const double *rho,
-                            const double *T, const double *Y, const double *e0, kin_mem where,
-                            void *stream, int32_t *inst_id)
+// An instance's arena: from the budget pool when the context has one, else its own hipMalloc.
+static kin_status alloc_inst(kin_ctx *ctx, int32_t mech_id, const Mech &m, int64_t n_cells,
+                             std::unique_ptr<Inst> &out)
 {
-    kin_status s = enter(ctx);
-    if (s != KIN_OK) return s;
-    if (!inst_id || n_cells < 1 || !rho || !T || !Y) return err(KIN_EINVAL, "bad state arguments");
-    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    auto it = ctx->mechs.find(mech_id);
-    if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
-    Mech &m = *it->second;
     const uint64_t bytes = inst_bytes(m.h.ns, n_cells);
     if (ctx->budget && ctx->in_use + bytes > ctx->budget)
         return err(KIN_ENOMEM, "instance of " + std::to_string(bytes) + " bytes exceeds the context budget");
@@ -601,24 +603,138 @@ kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, cons
     } else {
         KIN_HIP(ctx, hipMalloc(&in->buf, bytes));
     }
-    char *b = static_cast<char *>(in->buf);
-    const Arena ar = arena_at(b, n_cells, m.h.ns);
-    const size_t i = align256(sizeof(int) * (size_t)n_cells);
+    const Arena ar = arena_at(static_cast<char *>(in->buf), n_cells, m.h.ns);
     in->rho = ar.rho; in->e0 = ar.e0; in->T = ar.T; in->Y = ar.Y; in->sched = ar.sched;
     in->status = ar.status; in->level = ar.level; in->iters = ar.iters; in->counter = ar.counter;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if ((s = fill_state(ctx, *in, m, rho, T, Y, e0, where, st)) != KIN_OK) {
-        if (ctx->pool) pool_free(ctx, in->buf, bytes);
-        else hipFree(in->buf);
-        return s;
-    }
+    out = std::move(in);
+    return KIN_OK;
+}
+
+static void free_inst_buf(kin_ctx *ctx, Inst &in)
+{
+    if (ctx->pool) pool_free(ctx, in.buf, in.bytes);
+    else hipFree(in.buf);
+}
+
+// Conserved state into an instance's arena: rho_s goes into the Y slot, E_sens into e0 and the
+// start temperatures into T, and the conversion kernel rewrites them in place.
+static kin_status fill_conserved(kin_ctx *ctx, Inst &in, const Mech &m, const double *rho_s,
+                                 const double *E_sens, const double *T_guess, kin_mem where,
+                                 hipStream_t st)
+{
+    const size_t nb = sizeof(double) * (size_t)in.n;
+    kin_status s;
+    if ((s = copy_in(ctx, in.Y, rho_s, nb * m.h.ns, where, st)) != KIN_OK) return s;
+    if ((s = copy_in(ctx, in.e0, E_sens, nb, where, st)) != KIN_OK) return s;
+    if (T_guess && (s = copy_in(ctx, in.T, T_guess, nb, where, st)) != KIN_OK) return s;
+    KIN_HIP(ctx, launch_conserved_in(m.tab, in.n, in.ld, in.rho, in.T, in.Y, in.e0, T_guess != nullptr, st));
+    return KIN_OK;
+}
+
+// Clear the per-cell diagnostics and register a filled instance.
+static kin_status commit_inst(kin_ctx *ctx, Mech &m, std::unique_ptr<Inst> &in, kin_mem where,
+                              hipStream_t st, int32_t *inst_id)
+{
+    const size_t i = align256(sizeof(int) * (size_t)in->n);
     KIN_HIP(ctx, hipMemsetAsync(in->status, 0, 3 * i, st));
     if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
     m.refs++;
-    ctx->in_use += bytes;
+    ctx->in_use += in->bytes;
     const int id = ctx->next_inst++;
     ctx->insts[id] = std::move(in);
     *inst_id = id;
+    return KIN_OK;
+}
+
+kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, const double *rho,
+                            const double *T, const double *Y, const double *e0, kin_mem where,
+                            void *stream, int32_t *inst_id)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!inst_id || n_cells < 1 || !rho || !T || !Y) return err(KIN_EINVAL, "bad state arguments");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->mechs.find(mech_id);
+    if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
+    Mech &m = *it->second;
+    std::unique_ptr<Inst> in;
+    if ((s = alloc_inst(ctx, mech_id, m, n_cells, in)) != KIN_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = fill_state(ctx, *in, m, rho, T, Y, e0, where, st)) != KIN_OK) {
+        free_inst_buf(ctx, *in);
+        return s;
+    }
+    return commit_inst(ctx, m, in, where, st, inst_id);
+}
+
+kin_status kin_state_upload_conserved(kin_ctx *ctx, int32_t mech_id, int64_t n_cells,
+                                      const double *rho_s, const double *E_sens,
+                                      const double *T_guess, kin_mem where, void *stream,
+                                      int32_t *inst_id)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!inst_id || n_cells < 1 || !rho_s || !E_sens) return err(KIN_EINVAL, "bad conserved-state arguments");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->mechs.find(mech_id);
+    if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
+    Mech &m = *it->second;
+    std::unique_ptr<Inst> in;
+    if ((s = alloc_inst(ctx, mech_id, m, n_cells, in)) != KIN_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = fill_conserved(ctx, *in, m, rho_s, E_sens, T_guess, where, st)) != KIN_OK) {
+        free_inst_buf(ctx, *in);
+        return s;
+    }
+    return commit_inst(ctx, m, in, where, st, inst_id);
+}
+
+kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double *rho_s,
+                                     const double *E_sens, const double *T_guess, kin_mem where,
+                                     void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!rho_s || !E_sens) return err(KIN_EINVAL, "NULL conserved-state array");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->insts.find(inst_id);
+    if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
+    Inst &in = *it->second;
+    const Mech &m = *ctx->mechs[in.mech];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = fill_conserved(ctx, in, m, rho_s, E_sens, T_guess, where, st)) != KIN_OK) return s;
+    if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
+    return KIN_OK;
+}
+
+kin_status kin_download_conserved(kin_ctx *ctx, int32_t inst_id, double *rho_s, double *E_sens,
+                                  kin_mem where, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!rho_s || !E_sens) return err(KIN_EINVAL, "NULL destination");
+    if (!mem_ok(where)) return err(KIN_EINVAL, "bad memory kind");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->insts.find(inst_id);
+    if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
+    const Inst &in = *it->second;
+    const Mech &m = *ctx->mechs[in.mech];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (where == KIN_MEM_DEVICE) {
+        KIN_HIP(ctx, launch_conserved_out(m.tab, in.n, in.ld, in.rho, in.Y, in.e0, rho_s, E_sens, st));
+        return KIN_OK;
+    }
+    const size_t nb = sizeof(double) * (size_t)in.n;
+    double *stage = nullptr;
+    KIN_HIP(ctx, hipMallocAsync(reinterpret_cast<void **>(&stage), nb * (m.h.ns + 1), st));
+    KIN_HIP(ctx, launch_conserved_out(m.tab, in.n, in.ld, in.rho, in.Y, in.e0, stage, stage + (size_t)in.n * m.h.ns, st));
+    KIN_HIP(ctx, hipMemcpyAsync(rho_s, stage, nb * m.h.ns, hipMemcpyDeviceToHost, st));
+    KIN_HIP(ctx, hipMemcpyAsync(E_sens, stage + (size_t)in.n * m.h.ns, nb, hipMemcpyDeviceToHost, st));
+    KIN_HIP(ctx, hipFreeAsync(stage, st));
+    if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
     return KIN_OK;
 }
 

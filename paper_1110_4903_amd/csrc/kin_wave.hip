@@ -723,6 +723,88 @@ __global__ void energy_kernel(WaveTables t, long long n, long long ld, const dou
     e0[i] = e;
 }
 
+// ---- conserved-variable adapter (one thread per cell) -----------------------------------------
+__device__ __forceinline__ void cell_energy(const WaveTables &t, long long ld, long long i, const double *Y,
+                                            double T, double &e, double &cv)
+{
+    e = 0.0;
+    cv = 0.0;
+    const double iT = 1.0 / T;
+    for (int s = 0; s < t.ns; ++s) {
+        const Thermo th = thermo(t, s, T, iT, 0.0);
+        const double rm = 8.31446261815324e3 / t.M[s];
+        const double y = Y[(size_t)s * ld + i];
+        e = fma(y, rm * T * (th.h - 1.0), e);
+        cv = fma(y, rm * (th.cp - 1.0), cv);
+    }
+}
+
+// In: Y holds rho_s, e0 holds E_sens and T the starting temperature.  Out: rho, Y, e0 and T of
+// the cell (T = NaN when e(Y, T) = e0 has no root in range).
+__global__ void conserved_in_kernel(WaveTables t, long long n, long long ld, double *rho, double *T,
+                                    double *Y, double *e0, int have_guess)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = 0.0;
+    for (int s = 0; s < t.ns; ++s) r += Y[(size_t)s * ld + i];
+    const double ir = 1.0 / r;
+    double ef = 0.0;
+    for (int s = 0; s < t.ns; ++s) {
+        const double y = Y[(size_t)s * ld + i] * ir;
+        Y[(size_t)s * ld + i] = y;
+        ef = fma(y, t.ef[s], ef);
+    }
+    const double e_t = e0[i] * ir + ef;
+    rho[i] = r;
+    e0[i] = e_t;
+    // Newton on e(Y, T) = e0 from the start value, then bisection on [kTmin, kTmax]
+    double Tk = have_guess ? T[i] : 1500.0;
+    if (!(Tk >= kTmin && Tk <= kTmax)) Tk = 1500.0;
+    double Tout = __builtin_nan("");
+    bool done = false;
+    for (int it = 0; it < 20 && !done; ++it) {
+        double e, cv;
+        cell_energy(t, ld, i, Y, Tk, e, cv);
+        if (!(cv > 0.0)) break;
+        const double dT = (e - e_t) / cv;
+        Tk -= dT;
+        if (!__builtin_isfinite(Tk) || Tk < kTmin || Tk > kTmax) break;
+        if (fabs(dT) <= 1e-13 * Tk) { Tout = Tk; done = true; }
+    }
+    if (!done) {
+        double lo = kTmin, hi = kTmax, e, cv;
+        cell_energy(t, ld, i, Y, lo, e, cv);
+        const double flo = e - e_t;
+        cell_energy(t, ld, i, Y, hi, e, cv);
+        const double fhi = e - e_t;
+        if (flo <= 0.0 && fhi >= 0.0) {
+            for (int it = 0; it < 200 && hi - lo > 1e-13 * lo; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                cell_energy(t, ld, i, Y, mid, e, cv);
+                if (e - e_t > 0.0) hi = mid; else lo = mid;
+            }
+            Tout = 0.5 * (lo + hi);
+        }
+    }
+    T[i] = Tout;
+}
+
+__global__ void conserved_out_kernel(WaveTables t, long long n, long long ld, const double *rho,
+                                     const double *Y, const double *e0, double *rho_s, double *E_sens)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double r = rho[i];
+    double ef = 0.0;
+    for (int s = 0; s < t.ns; ++s) {
+        const double y = Y[(size_t)s * ld + i];
+        rho_s[(size_t)s * n + i] = r * y;
+        ef = fma(y, t.ef[s], ef);
+    }
+    E_sens[i] = r * (e0[i] - ef);
+}
+
 template <int NPAD, bool F32>
 hipError_t launch_t(const WaveTables &t, const AdvanceArgs &a, int wpb, int grid, hipStream_t s)
 {
@@ -780,6 +862,29 @@ hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const d
     const int block = 256;
     const long long grid = (n + block - 1) / block;
     hipLaunchKernelGGL(energy_kernel, dim3((unsigned)grid), dim3(block), 0, s, t, n, ld, T, Y, e0);
+    return hipGetLastError();
+}
+
+hipError_t launch_conserved_in(const WaveTables &t, long long n, long long ld, double *rho, double *T,
+                               double *Y, double *e0, bool have_guess, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const long long grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(conserved_in_kernel, dim3((unsigned)grid), dim3(block), 0, s, t, n, ld, rho, T, Y,
+                       e0, have_guess ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_conserved_out(const WaveTables &t, long long n, long long ld, const double *rho,
+                                const double *Y, const double *e0, double *rho_s, double *E_sens,
+                                hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const long long grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(conserved_out_kernel, dim3((unsigned)grid), dim3(block), 0, s, t, n, ld, rho, Y,
+                       e0, rho_s, E_sens);
     return hipGetLastError();
 }
 

@@ -406,3 +406,57 @@ def test_species_on_both_sides_both_layouts(ctx, orc):
         report(f"both sides layout {layout}", s)
         assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2, (layout, s)
         assert s["fail_Y"] == 0 and s["fail_T"] == 0, (layout, s)
+
+
+@pytest.mark.parametrize("name", ["mech9", "mech36"])
+def test_conserved_adapter_against_oracle(ctx, orc, name):
+    """Operator-split adapter: partial densities and sensible energy in, one step of 1e-6 s,
+    partial densities and sensible energy out, against the oracle's same pipeline (FP64, 1e-10
+    relative on the scale of the energy terms); device and host destinations agree bitwise.
+    Cells with no density, or with an energy beyond 6000 K, come out as bad input."""
+    import torch
+    from tests.parity import compare
+    m = synth.mechanism(name)
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(41, 256, m.ns, 1.0 if name == "mech9" else 0.5)
+    dt = 1e-6
+    e0 = om.energy_batch(st.T, st.Y)
+    rho_s, E = om.to_conserved(st.rho, st.Y, e0)
+    rho_s[:, 5] = 0.0            # no density
+    E[7] = 1e3 * abs(E[7]) + 1e9  # no temperature in [200, 6000] K
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rho, Y, T, e0o, ok = om.from_conserved(rho_s, E)
+    assert not ok[7]
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload_conserved(mid, rho_s, E)
+    T_up = ctx.download(iid)[0]
+    good = np.ones(st.n, bool)
+    good[[5, 7]] = False
+    np.testing.assert_allclose(T_up[good], T[good], rtol=1e-12)
+    assert np.isnan(T_up[7])
+    ctx.advance([iid], [dt])
+    gpu = ctx.download(iid) + (ctx.download_schedule(iid),)
+    g_rho_s, g_E = ctx.download_conserved(iid)
+    d_rho_s = torch.empty((m.ns, st.n), dtype=torch.float64, device="cuda")
+    d_E = torch.empty(st.n, dtype=torch.float64, device="cuda")
+    ctx.download_conserved_device(iid, d_rho_s, d_E)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_rho_s.cpu().numpy(), g_rho_s, equal_nan=True)
+    assert np.array_equal(d_E.cpu().numpy(), g_E, equal_nan=True)
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    assert gpu[2][5] == 3 and gpu[2][7] == 3
+    T_in = np.where(good, T, st.T)
+    Y_in = np.where(good[None, :], Y, st.Y)
+    rho_in = np.where(good, rho, st.rho)
+    ref = om.advance(rho_in, T_in, Y_in, dt, e0=np.where(good, e0o, e0), with_sched=True)
+    s = compare(tuple(a[..., good] for a in gpu), tuple(a[..., good] for a in ref), rho_in[good],
+                Y_in[:, good], dt, om, 1e-10)
+    report(f"{name} adapter", s)
+    assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2 and s["fail_Y"] == 0 and s["fail_T"] == 0
+    r_rho_s, r_E = om.to_conserved(rho_in, ref[1], np.where(good, e0o, e0))
+    same = good & (gpu[5] == ref[5])
+    ef = om.formation_energies()
+    scale = np.abs(r_E) + rho_in * (np.abs(ef) @ np.abs(ref[1]))
+    assert np.all(np.abs(g_E[same] - r_E[same]) <= 1e-10 * scale[same])
+    np.testing.assert_allclose(g_rho_s[:, same], r_rho_s[:, same], rtol=1e-10, atol=1e-14 * rho_in.max())

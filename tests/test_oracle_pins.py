@@ -502,3 +502,91 @@ def test_divergence_test_saves_iterations_and_keeps_invariants(orc):
         np.testing.assert_allclose(el1, el0, rtol=1e-11, atol=1e-14)
     for c in range(st.n):
         assert abs(om.energy(Y1[:, c], T1[c]) - e0[c]) <= 1e-12 * abs(e0[c])
+
+
+# ---------------------------------------------------------------------------------------------
+# Operator-split adapter (Sec. 2: the energy equation leaves out the formation energies, and
+# the chemistry source must carry their change; operator-splitting equation)
+# ---------------------------------------------------------------------------------------------
+
+R_J = 8.31446261815324e3  # J/(kmol K), with molar masses in g/mol = kg/kmol
+
+
+def test_sensible_energy_is_cv_integral(orc):
+    """One species at T: E_sens / rho equals the integral of c_v from 298.15 K to T, computed
+    by adaptive quadrature of the NASA-7 cp (independent of the closed-form energy)."""
+    from scipy.integrate import quad
+    m = synth.mechanism("mech9")
+    om = orc.OracleMech(m)
+    unit = np.eye(m.ns)
+    for s in range(m.ns):
+        cv = lambda T: R_J / m.M[s] * (om.thermo(T)[0][s] - 1.0)
+        for T in (500.0, 1500.0, 2800.0, 4500.0):
+            ref, _ = quad(cv, orc.T_REF, T, points=[m.T_mid[s]] if T > m.T_mid[s] else None,
+                          epsabs=0.0, epsrel=1e-13, limit=200)
+            rho = 0.37
+            E = om.to_conserved(np.array([rho]), unit[s][:, None], np.array([om.energy(unit[s], T)]))[1][0]
+            assert abs(E / rho - ref) <= 1e-11 * abs(ref), (s, T)
+
+
+def test_conserved_round_trip(orc):
+    """(rho, Y, T) -> (rho_s, E_sens) -> (rho, Y, T) on config 0's states: partial densities
+    sum to rho and the inversion recovers T to 1e-12 relative."""
+    m = synth.mechanism("mech9")
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(31, 200, m.ns, 1.0)
+    e0 = om.energy_batch(st.T, st.Y)
+    rho_s, E = om.to_conserved(st.rho, st.Y, e0)
+    np.testing.assert_allclose(rho_s.sum(0), st.rho, rtol=1e-15)
+    rho, Y, T, e1, ok = om.from_conserved(rho_s, E, T_guess=np.full(st.n, 2000.0))
+    assert ok.all()
+    np.testing.assert_allclose(rho, st.rho, rtol=1e-15)
+    np.testing.assert_allclose(Y, st.Y, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(T, st.T, rtol=1e-12)
+    np.testing.assert_allclose(e1, e0, rtol=1e-13)
+
+
+def two_species_heat_release(dh_R):
+    """A <=> B with equal constant cp/R = 3.5 and equal molar mass; B's formation enthalpy is
+    lower by dh_R (K), so A -> B releases dh_R R per unit of moles converted."""
+    a = nasa_const(3.5, 1000.0, 30.0)
+    b = nasa_const(3.5, 1000.0 - dh_R, 28.0)
+    return synth.mechanism_from_lists("heat", ("H",), [[2], [2]], [a, b],
+                                      [dict(reac=[(0, 1)], prod=[(1, 1)], A=2e6, b=0.0, Ta=0.0)])
+
+
+def test_conserved_constant_cp_closed_form(orc):
+    """With constant cp, E_sens = sum rho_s c_v,s (T - T_ref); the inversion must return
+    T = T_ref + E_sens / sum rho_s c_v,s."""
+    m = two_species_heat_release(3000.0)
+    om = orc.OracleMech(m)
+    cv = R_J / m.M * (3.5 - 1.0)
+    rho_s = np.array([[0.2, 0.01, 0.7], [0.05, 0.3, 0.0]])
+    E = np.array([3.0e5, 2.5e6, 9.0e5])
+    rho, Y, T, e0, ok = om.from_conserved(rho_s, E)
+    assert ok.all()
+    np.testing.assert_allclose(T, orc.T_REF + E / (cv @ rho_s), rtol=1e-12)
+
+
+def test_formation_energy_source(orc):
+    """Exothermic A -> B over one step from the conserved state: mass and the total energy
+    E_sens + sum rho_s e_s(T_ref) are unchanged, E_sens rises by the formation energy released,
+    (rho_A - rho_A') (e_A(T_ref) - e_B(T_ref)), and the new T is the constant-cp closed form."""
+    dh = 3000.0
+    m = two_species_heat_release(dh)
+    om = orc.OracleMech(m)
+    cv = R_J / m.M[0] * 2.5
+    rho_s = np.array([[0.2, 0.9, 0.5], [0.0, 0.1, 0.5]])
+    E = np.array([3.0e5, 1.2e6, 2.0e6])
+    rho, Y, T, e0, ok = om.from_conserved(rho_s, E)
+    T1, Y1, s1 = om.advance(rho, T, Y, 1e-6, e0=e0)[:3]
+    assert np.all(s1 < 2)
+    rho_s1, E1 = om.to_conserved(rho, Y1, e0)
+    ef = om.formation_energies()
+    np.testing.assert_allclose(ef[0] - ef[1], R_J / m.M[0] * dh, rtol=1e-12)
+    np.testing.assert_allclose(rho_s1.sum(0), rho_s.sum(0), rtol=1e-14)
+    np.testing.assert_allclose(E1 + ef @ rho_s1, E + ef @ rho_s, rtol=1e-13)
+    released = (rho_s[0] - rho_s1[0]) * R_J / m.M[0] * dh
+    assert np.all(released > 0)
+    np.testing.assert_allclose(E1 - E, released, rtol=1e-9)
+    np.testing.assert_allclose(T1, orc.T_REF + E1 / (rho * cv), rtol=1e-12)
