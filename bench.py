@@ -230,6 +230,43 @@ def run_conserved_adapter(torch, ctx, kin, synth, args, stream):
                 adapter_share=(t_in + t_out) / total)
 
 
+def run_global_tier(torch, ctx, kin, flops, synth, args, stream):
+    """The global-memory layout (one thread per cell, the cell's matrix in HBM; the paper's
+    first kinetics kernel) on a generated 100-species / 600-reaction mechanism, beyond the
+    wave layout's 63 species: one FP64 step of 1e-6 s on 65536 cells (Dirichlet(0.5), seed 7).
+    Achieved bandwidth = the algorithmic bytes of a Newton iteration (flops.global_tier_bytes)
+    times the iterations of the launch, over its duration."""
+    n = 4096 if args.quick else 65536
+    m = synth.make_mechanism(synth.MechRecipe("gen100", seed=1100, n_elements=5, n_species=100,
+                                              n_reactions=600, frac_third_body=0.15,
+                                              frac_irreversible=0.3))
+    mid = ctx.mech_upload(m)
+    st = device_state(torch, synth.uniform_cells(7, n, m.ns, 0.5))
+    warm = device_state(torch, synth.uniform_cells(8, 1024, m.ns, 0.5))
+    wid = ctx.state_upload(mid, warm["rho"], warm["T"], warm["Y"], stream=stream)
+    ctx.advance([wid], [0.0], stream=stream)  # a zero step (one iteration) sets up the workspace pool
+    iid = ctx.state_upload(mid, st["rho"], st["T"], st["Y"], stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.advance([iid], [1e-6], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    out = ctx.download(iid)
+    iters = float(out[4].astype(np.float64).sum())
+    b = flops.global_tier_bytes(m)
+    gbs = b["total"] * iters / sec / 1e9
+    res = dict(mechanism="generated 100 species / 600 reactions", cells=n, seconds=sec, cells_per_s=n / sec,
+               newton_iters_per_cell=iters / n, status_hist=np.bincount(out[2], minlength=4).tolist(),
+               layout=ctx.query_int(kin.Q_LAYOUT, mid), bytes_per_iteration=b["total"],
+               achieved_GB_s=gbs, hbm_peak_GB_s=8000.0, frac=gbs / 8000.0)
+    for i in (wid, iid):
+        ctx.instance_release(i)
+    ctx.mech_release(mid)
+    return res
+
+
 def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     n36 = (1 << 14) if args.quick else (1 << 18)
     m36, s36, dt36 = synth.workload_mech36(n36)
@@ -392,6 +429,9 @@ def run_gpu(args):
         if args.only in ("all", "adapter"):
             log("operator-split adapter on the headline grid")
             res["mech9_conserved_adapter_fp64"] = run_conserved_adapter(torch, ctx, kin, synth, args, stream)
+        if args.only in ("all", "global"):
+            log("global-memory layout, 100 species, 65536 cells")
+            res["gen100_global_fp64"] = run_global_tier(torch, ctx, kin, flops, synth, args, stream)
     if args.only in ("all", "batch") and not args.no_batch:
         res["batch64"] = run_batch(torch, kin, synth, args, stream)
     if args.only in ("all", "serve") and not args.no_serve:
@@ -459,7 +499,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--quick", action="store_true", help="small sizes, for smoke runs")
-    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "batch", "serve", "copy"),
+    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "global", "batch", "serve", "copy"),
                     help="run one part (for profiler runs); the JSON line needs the headline")
     args = ap.parse_args()
     if args.gpus != 1:

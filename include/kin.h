@@ -50,9 +50,13 @@ typedef enum { KIN_FP64 = 0, KIN_FP32_LU = 1 } kin_precision;
  * alive and unchanged until the stream has passed the copy. */
 typedef enum { KIN_MEM_HOST = 0, KIN_MEM_DEVICE = 1, KIN_MEM_PINNED = 2 } kin_mem;
 
-/* Kernel layouts: one cell per lane with the Newton matrix in registers, or one cell per
- * 64-wide wavefront with one matrix row per lane and the Jacobian staged in LDS. */
-typedef enum { KIN_LAYOUT_AUTO = 0, KIN_LAYOUT_LANE = 1, KIN_LAYOUT_WAVE = 2 } kin_layout;
+/* Kernel layouts: one cell per lane with the Newton matrix in registers (ns <= 15), one cell
+ * per 64-wide wavefront with one matrix row per lane and the Jacobian staged in LDS
+ * (ns <= 63), or one cell per thread with the cell's whole matrix in global memory, the
+ * paper's first kinetics kernel (Sec. 4.2; any ns up to 255, the automatic choice above 63).
+ * The global layout allocates its workspace (at most 16 GiB) stream-ordered on the launch
+ * stream, or with the graph of a batched advance, and is bound by HBM bandwidth. */
+typedef enum { KIN_LAYOUT_AUTO = 0, KIN_LAYOUT_LANE = 1, KIN_LAYOUT_WAVE = 2, KIN_LAYOUT_GLOBAL = 3 } kin_layout;
 
 /* Per-cell status codes written by kin_advance. */
 enum {
@@ -79,7 +83,7 @@ typedef struct {
  * unused entries have index -1.  A reaction with tb[r] >= 0 multiplies its net rate by the
  * third-body concentration sum_s eff[tb[r]][s] X_s (Sec. 3.2, rate-of-progress equation). */
 typedef struct {
-    int32_t ns;                /* species, 1..63 */
+    int32_t ns;                /* species, 1..255 (over 63: the global-memory layout only) */
     int32_t ne;                /* elements, >= 1 */
     int32_t nr;                /* reactions, >= 1 */
     int32_t ntb;               /* rows of eff */
@@ -249,7 +253,8 @@ typedef enum {
 
 kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
 
-/* Set a mechanism's layout and block size (what the autotuner decides). */
+/* Set a mechanism's layout and block size (what the autotuner decides): lane 64/128/256
+ * threads, wave 1..4 wavefronts, global 64 threads per block. */
 kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
 
 /* Autotuner: time one advance of an existing instance with every admissible kernel layout

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define ORC_NS_MAX 127
+#define ORC_NS_MAX 255
 
 typedef struct {
     int ns, nr, ntb;

@@ -36,7 +36,7 @@ kin_status mech_from_desc(const kin_mech_desc *d, MechHost &m, std::string &msg)
 {
     auto fail = [&](const std::string &s) { msg = "mechanism: " + s; return KIN_EINVAL; };
     if (!d) return fail("NULL descriptor");
-    if (d->ns < 1 || d->ns > kNsMax) return fail("ns must be in 1..63");
+    if (d->ns < 1 || d->ns > kNsMax) return fail("ns must be in 1..255");
     if (d->ne < 1 || d->nr < 1 || d->ntb < 0) return fail("ne >= 1, nr >= 1, ntb >= 0 required");
     if (!d->M || !d->elem || !d->nasa || !d->T_mid || !d->reac_idx || !d->reac_nu ||
         !d->prod_idx || !d->prod_nu || !d->A || !d->b || !d->Ta || !d->reversible || !d->tb ||

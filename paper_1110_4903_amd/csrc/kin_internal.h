@@ -11,7 +11,8 @@
 
 namespace kin {
 
-constexpr int kNsMax = 63;          // N = Ns + 1 <= 64: one matrix row per wavefront lane
+constexpr int kNsMax = 255;         // species of a mechanism (the global-memory layout)
+constexpr int kWaveNsMax = 63;      // N = Ns + 1 <= 64: one matrix row per wavefront lane
 constexpr int kLaneNsMax = 15;      // lane layout holds the whole matrix in registers
 constexpr double kRu = 8.31446261815324;          // J/(mol K)
 constexpr double kRuCgs = 8.31446261815324e7;     // erg/(mol K)
@@ -178,6 +179,11 @@ hipError_t launch_conserved_in(const WaveTables &t, long long n, long long ld, d
 hipError_t launch_conserved_out(const WaveTables &t, long long n, long long ld, const double *rho,
                                 const double *Y, const double *e0, double *rho_s, double *E_sens,
                                 hipStream_t s);
+// Global-memory layout (kin_global.hip): workspace doubles per slot, and the launch over
+// `slots` threads with a workspace of slots * global_work_doubles_per_slot doubles.
+size_t global_work_doubles_per_slot(int ns, int ntb);
+hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, double *work,
+                         long long slots, hipStream_t stream);
 hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,
                          const double *Y, double *e0, hipStream_t stream);
 hipError_t launch_wave(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, int waves_per_block,

@@ -60,6 +60,7 @@ static uint64_t inst_bytes(int ns, long long n) { return (uint64_t)arena_bytes(n
 struct Plan {
     hipGraphExec_t exec = nullptr;
     std::vector<int> insts;
+    void *gwork = nullptr;  // workspace of the plan's global-layout launches (if any)
 };
 
 }  // namespace kin
@@ -209,7 +210,10 @@ void kin_destroy(kin_ctx *ctx)
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         hipSetDevice(ctx->device);
         hipDeviceSynchronize();
-        for (auto &kv : ctx->plans) hipGraphExecDestroy(kv.second.exec);
+        for (auto &kv : ctx->plans) {
+            hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.gwork) hipFree(kv.second.gwork);
+        }
         for (hipStream_t st : ctx->cap) hipStreamDestroy(st);
         for (hipEvent_t ev : ctx->join) hipEventDestroy(ev);
         if (ctx->fork) hipEventDestroy(ctx->fork);
@@ -317,7 +321,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
                 const int q = 3 * side + m;
                 p.nu[q] = (int8_t)nu;
                 p.coff[q] = (uint16_t)(8 * sp);
-                p.roff[q] = (uint16_t)(8 * sp * npad);
+                p.roff[q] = (uint16_t)(npad > 0 ? 8 * sp * npad : 0);  // wave layout only
                 k.rowc[q] = (double)nu * h.M[sp];
                 k.colc[q] = 1.0 / h.M[sp];
             }
@@ -486,16 +490,19 @@ kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_i
             hipFree(m->kconst);
             return s;
         }
-    } else {
+    } else if (m->h.ns <= kWaveNsMax) {
         m->layout = KIN_LAYOUT_WAVE;
         m->block = 1;
+    } else {
+        m->layout = KIN_LAYOUT_GLOBAL;
+        m->block = 64;
     }
     {   // a tuned choice (FP64 entry) from the cache file, if any
         const auto cache = tune_read(ctx->tune_cache);
         auto it = cache.find(tune_key(ctx, *m, KIN_FP64));
         if (it != cache.end() && it->second.size() >= 2) {
             const int lay = (int)it->second[0], blk = (int)it->second[1];
-            if (lay == KIN_LAYOUT_WAVE && blk >= 1 && blk <= 4) {
+            if (lay == KIN_LAYOUT_WAVE && blk >= 1 && blk <= 4 && m->h.ns <= kWaveNsMax) {
                 m->layout = lay;
                 m->block = blk;
             } else if (lay == KIN_LAYOUT_LANE && m->h.ns <= kLaneNsMax && (blk == 64 || blk == 128 || blk == 256)) {
@@ -540,11 +547,14 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
         if (block != 64 && block != 128 && block != 256) return err(KIN_EINVAL, "lane block must be 64, 128 or 256");
         if ((s = build_lane(ctx, m, block)) != KIN_OK) return s;
     } else if (layout == KIN_LAYOUT_WAVE) {
+        if (m.h.ns > kWaveNsMax) return err(KIN_EINVAL, "wave layout needs ns <= 63");
         if (block < 1 || block > 4) return err(KIN_EINVAL, "wave layout takes 1..4 wavefronts per block");
         if (wave_lds_bytes(m.tab, false) * (size_t)block > 65536)
             return err(KIN_EINVAL, "that many wavefronts per block exceed 64 KiB of LDS for this mechanism");
+    } else if (layout == KIN_LAYOUT_GLOBAL) {
+        if (block != 64) return err(KIN_EINVAL, "global layout runs 64 threads per block");
     } else {
-        return err(KIN_EINVAL, "layout must be LANE or WAVE");
+        return err(KIN_EINVAL, "layout must be LANE, WAVE or GLOBAL");
     }
     m.layout = layout;
     m.block = block;
@@ -770,13 +780,32 @@ static void layout_of(const Mech &m, const kin_solver_opts &o, int &layout, int 
 {
     layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
     if (layout == KIN_LAYOUT_LANE) block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
-    else block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 1;
+    else if (layout == KIN_LAYOUT_WAVE) block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 1;
+    else block = 64;
+}
+
+// Global-memory layout: threads (workspace slots) of a launch over `total` cells, at most
+// what fits in kGlobalWorkBytes of workspace.
+constexpr size_t kGlobalWorkBytes = size_t(16) << 30;
+
+static long long global_slots(const Mech &m, long long total)
+{
+    const size_t per = sizeof(double) * global_work_doubles_per_slot(m.h.ns, m.tab.ntb);
+    long long cap = (long long)(kGlobalWorkBytes / per) / 64 * 64;
+    if (cap < 64) cap = 64;
+    return std::min((total + 63) / 64 * 64, cap);
+}
+
+static size_t global_work_doubles(const Mech &m, long long total)
+{
+    return global_work_doubles_per_slot(m.h.ns, m.tab.ntb) * (size_t)global_slots(m, total);
 }
 
 // Launch one kernel over the spans in a (all of mechanism m) on stream st.  The work counter
-// a.counter must already be zero (stream order).
+// a.counter must already be zero (stream order).  gwork: the workspace of a global-layout
+// launch (global_work_doubles doubles); NULL allocates it stream-ordered on st.
 static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precision prec, int layout,
-                               int block, hipStream_t st)
+                               int block, hipStream_t st, double *gwork = nullptr)
 {
     const bool f32 = prec == KIN_FP32_LU;
     a.ns = m.h.ns;
@@ -793,7 +822,18 @@ static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precis
         a.K = m.kconst;
         void *params[] = {&a};
         KIN_HIP(ctx, hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
+    } else if (layout == KIN_LAYOUT_GLOBAL) {
+        const long long S = global_slots(m, a.total);
+        if (gwork) {
+            KIN_HIP(ctx, launch_global(m.tab, a, f32, gwork, S, st));
+        } else {
+            double *w = nullptr;
+            KIN_HIP(ctx, hipMallocAsync(reinterpret_cast<void **>(&w), sizeof(double) * global_work_doubles(m, a.total), st));
+            KIN_HIP(ctx, launch_global(m.tab, a, f32, w, S, st));
+            KIN_HIP(ctx, hipFreeAsync(w, st));
+        }
     } else {
+        if (m.h.ns > kWaveNsMax) return err(KIN_EINVAL, "wave layout needs ns <= 63");
         const long long blocks = (a.total + block - 1) / block;
         if (blocks > 0x7fffffffLL) return err(KIN_EINVAL, "too many cells for one wave-layout launch");
         KIN_HIP(ctx, launch_wave(m.tab, a, f32, block, (int)blocks, st));
@@ -805,7 +845,7 @@ static bool opts_ok(const kin_solver_opts &o)
 {
     return o.rtol >= 0 && o.atol_Y >= 0 && o.atol_T >= 0 && o.y_neg >= 0 && o.k_max >= 1 && o.L_max >= 0 &&
            o.L_max <= 62 && o.L_forced <= 30 && o.L_forced >= -1 && o.max_iters >= 1 &&
-           o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_WAVE && o.diverge_ratio >= 0;
+           o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_GLOBAL && o.diverge_ratio >= 0;
 }
 
 // Batched advance: instances grouped by (mechanism, layout), at most kMaxSpans per launch, each
@@ -867,7 +907,10 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
     if (pit == ctx->plans.end()) {
         if (ctx->ncounters < nl) {
             // existing graphs point at the old counters
-            for (auto &kv : ctx->plans) KIN_HIP(ctx, hipGraphExecDestroy(kv.second.exec));
+            for (auto &kv : ctx->plans) {
+                KIN_HIP(ctx, hipGraphExecDestroy(kv.second.exec));
+                if (kv.second.gwork) KIN_HIP(ctx, hipFree(kv.second.gwork));
+            }
             ctx->plans.clear();
             if (ctx->counters) KIN_HIP(ctx, hipFree(ctx->counters));
             ctx->ncounters = std::max(nl, 16);
@@ -882,12 +925,21 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
             ctx->join.push_back(ev);
         }
         if (!ctx->fork) KIN_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
-        // compile lane modules outside the capture
-        for (Launch &L : launches)
+        // compile lane modules and allocate the global layout's workspace outside the capture
+        std::vector<size_t> goff(nl, 0);
+        size_t gtotal = 0;
+        for (int q = 0; q < nl; ++q) {
+            Launch &L = launches[q];
             if (L.layout == KIN_LAYOUT_LANE) {
                 kin_status s = build_lane(ctx, *L.m, L.block);
                 if (s != KIN_OK) return s;
+            } else if (L.layout == KIN_LAYOUT_GLOBAL) {
+                goff[q] = gtotal;
+                gtotal += global_work_doubles(*L.m, L.a.total);
             }
+        }
+        double *gw = nullptr;
+        if (gtotal) KIN_HIP(ctx, hipMalloc(reinterpret_cast<void **>(&gw), sizeof(double) * gtotal));
         hipStream_t c0 = ctx->cap[0];
         KIN_HIP(ctx, hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
         kin_status cs = KIN_OK;
@@ -899,7 +951,8 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
             launches[q].a.counter = ctx->counters + q;
             he = launch_zero_u64(ctx->counters + q, 1, sq);
             if (he != hipSuccess) break;
-            cs = launch_spans(ctx, *launches[q].m, launches[q].a, prec, launches[q].layout, launches[q].block, sq);
+            cs = launch_spans(ctx, *launches[q].m, launches[q].a, prec, launches[q].layout, launches[q].block, sq,
+                              launches[q].layout == KIN_LAYOUT_GLOBAL ? gw + goff[q] : nullptr);
             if (cs == KIN_OK && q > 0) {
                 he = hipEventRecord(ctx->join[q], sq);
                 if (he == hipSuccess) he = hipStreamWaitEvent(c0, ctx->join[q], 0);
@@ -909,17 +962,21 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
         hipError_t he2 = hipStreamEndCapture(c0, &graph);
         if (cs != KIN_OK) {
             if (graph) hipGraphDestroy(graph);
+            if (gw) hipFree(gw);
             return cs;
         }
         if (he != hipSuccess || he2 != hipSuccess) {
             if (graph) hipGraphDestroy(graph);
+            if (gw) hipFree(gw);
             ctx->poisoned = true;
             return err(KIN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(he != hipSuccess ? he : he2));
         }
         Plan plan;
+        plan.gwork = gw;
         hipError_t he3 = hipGraphInstantiate(&plan.exec, graph, nullptr, nullptr, 0);
         hipGraphDestroy(graph);
         if (he3 != hipSuccess) {
+            if (gw) hipFree(gw);
             ctx->poisoned = true;
             return err(KIN_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(he3));
         }
@@ -1054,6 +1111,7 @@ kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id)
     for (auto pit = ctx->plans.begin(); pit != ctx->plans.end();) {
         if (std::find(pit->second.insts.begin(), pit->second.insts.end(), inst_id) != pit->second.insts.end()) {
             KIN_HIP(ctx, hipGraphExecDestroy(pit->second.exec));
+            if (pit->second.gwork) KIN_HIP(ctx, hipFree(pit->second.gwork));
             pit = ctx->plans.erase(pit);
         } else {
             ++pit;
@@ -1132,8 +1190,12 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     std::vector<std::pair<int, int>> cand;
     if (m.h.ns <= kLaneNsMax)
         for (int b : {64, 128, 256}) cand.push_back({KIN_LAYOUT_LANE, b});
-    for (int b : {1, 2, 4})
-        if (wave_lds_bytes(m.tab, false) * (size_t)b <= 65536) cand.push_back({KIN_LAYOUT_WAVE, b});
+    if (m.h.ns <= kWaveNsMax) {
+        for (int b : {1, 2, 4})
+            if (wave_lds_bytes(m.tab, false) * (size_t)b <= 65536) cand.push_back({KIN_LAYOUT_WAVE, b});
+    } else {
+        cand.push_back({KIN_LAYOUT_GLOBAL, 64});
+    }
     void *save = nullptr;
     KIN_HIP(ctx, hipMalloc(&save, in.bytes));
     KIN_HIP(ctx, hipMemcpy(save, in.buf, in.bytes, hipMemcpyDeviceToDevice));

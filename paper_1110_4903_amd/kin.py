@@ -20,7 +20,7 @@ SO = os.path.join(HERE, "libkin.so")
 OK, EINVAL, ENOMEM, EBUSY, ENOTFOUND, EDEVICE, ECOMPILE = range(7)
 FP64, FP32_LU = 0, 1
 MEM_HOST, MEM_DEVICE, MEM_PINNED = 0, 1, 2
-LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_WAVE = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_WAVE, LAYOUT_GLOBAL = 0, 1, 2, 3
 CELL_OK, CELL_OK_HALVED, CELL_FAILED, CELL_BAD_INPUT = 0, 1, 2, 3
 Q_BYTES_IN_USE, Q_LAYOUT, Q_BLOCK, Q_NUM_CU, Q_DEVICE_PTRS, Q_JIT_SECONDS, Q_LARGEST_FREE = range(7)
 

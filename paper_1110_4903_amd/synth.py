@@ -28,8 +28,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 # Standard atomic weights (g/mol) of the elements the synthetic species are built from.
-ELEMENT_MASS = {"H": 1.008, "O": 15.999, "N": 14.007, "C": 12.011}
-ELEMENT_ORDER = ("H", "O", "N", "C")
+ELEMENT_MASS = {"H": 1.008, "O": 15.999, "N": 14.007, "C": 12.011, "S": 32.06}
+ELEMENT_ORDER = ("H", "O", "N", "C", "S")
 
 # NASA-7 fit interval used for every synthetic species (K).
 T_FIT_LO, T_FIT_MID, T_FIT_HI = 300.0, 1000.0, 5000.0

@@ -460,3 +460,37 @@ def test_conserved_adapter_against_oracle(ctx, orc, name):
     scale = np.abs(r_E) + rho_in * (np.abs(ef) @ np.abs(ref[1]))
     assert np.all(np.abs(g_E[same] - r_E[same]) <= 1e-10 * scale[same])
     np.testing.assert_allclose(g_rho_s[:, same], r_rho_s[:, same], rtol=1e-10, atol=1e-14 * rho_in.max())
+
+
+def big_mech(ns, nr):
+    """Generated mechanism beyond the wave layout's 63 species (5 elements)."""
+    return synth.make_mechanism(synth.MechRecipe(f"gen{ns}", seed=1000 + ns, n_elements=5, n_species=ns,
+                                                 n_reactions=nr, frac_third_body=0.15,
+                                                 frac_irreversible=0.3))
+
+
+@pytest.mark.parametrize("case", ["mech9", "mech36", "gen100"])
+def test_global_layout_against_oracle(ctx, orc, case):
+    """The global-memory layout (one thread per cell, Jacobian in HBM): the 9- and 36-species
+    mechanisms forced onto it, and a 100-species mechanism that selects it by itself, FP64 and
+    FP32-LU, against the oracle."""
+    from tests.parity import compare
+    from paper_1110_4903_amd import kin
+    if case == "gen100":
+        m, n, alpha = big_mech(100, 600), 64, 0.5
+    else:
+        m, n, alpha = synth.mechanism(case), 128, 1.0 if case == "mech9" else 0.5
+    st = synth.uniform_cells(500 + m.ns, n, m.ns, alpha)
+    om, ref = run_oracle(orc, m, st, 1e-6)
+    mid = ctx.mech_upload(m)
+    if case == "gen100":
+        assert ctx.query_int(kin.Q_LAYOUT, mid) == kin.LAYOUT_GLOBAL
+    opts = kin.solver_opts(layout=kin.LAYOUT_GLOBAL)
+    for prec, rtol in ((kin.FP64, 1e-10), (kin.FP32_LU, 1e-6)):
+        gpu = run_gpu(ctx, m, st, 1e-6, prec=prec, opts=opts, mech_id=mid)
+        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, rtol)
+        report(f"global {case} prec {prec}", s)
+        if prec == kin.FP64:
+            assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0
+    ctx.mech_release(mid)
