@@ -494,3 +494,39 @@ def test_global_layout_against_oracle(ctx, orc, case):
             assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
         assert s["fail_Y"] == 0 and s["fail_T"] == 0
     ctx.mech_release(mid)
+
+
+def test_batched_graph_with_global_layout(ctx):
+    """A batch mixing a 70-species mechanism (global-memory layout, two instances sharing one
+    launch and the graph's workspace) with mech36 (wave layout) equals, bitwise, advancing
+    each instance alone; a second call replays the cached graph."""
+    from paper_1110_4903_amd import kin
+    big = big_mech(70, 400)
+    m36 = synth.mechanism("mech36")
+    mb, m3 = ctx.mech_upload(big), ctx.mech_upload(m36)
+    assert ctx.query_int(kin.Q_LAYOUT, mb) == kin.LAYOUT_GLOBAL
+    cases = [(mb, big, synth.uniform_cells(61, 70, big.ns, 0.5), 1e-6),
+             (mb, big, synth.uniform_cells(62, 33, big.ns, 0.5), 3e-7),
+             (m3, m36, synth.uniform_cells(63, 100, m36.ns, 0.5), 1e-6)]
+    ids = [ctx.state_upload(mid, st.rho, st.T, st.Y) for mid, _, st, _ in cases]
+    dts = [dt for *_, dt in cases]
+    runs = []
+    for _ in range(2):
+        for i, (_, _, st, _) in zip(ids, cases):
+            ctx.state_reset(i, st.rho, st.T, st.Y)
+        ctx.advance(ids, dts)
+        runs.append([ctx.download(i) + (ctx.download_schedule(i),) for i in ids])
+    for i, (_, _, st, _) in zip(ids, cases):
+        ctx.state_reset(i, st.rho, st.T, st.Y)
+    for i, dt in zip(ids, dts):
+        ctx.advance([i], [dt])
+    single = [ctx.download(i) + (ctx.download_schedule(i),) for i in ids]
+    for run in runs:
+        for k, (a, c) in enumerate(zip(run, single)):
+            for x, z in zip(a, c):
+                assert np.array_equal(x, z, equal_nan=True), k
+    assert all(np.all(s[2] < 2) for s in single)
+    for i in ids:
+        ctx.instance_release(i)
+    ctx.mech_release(mb)
+    ctx.mech_release(m3)
