@@ -20,6 +20,7 @@ namespace kin {
 namespace {
 
 constexpr double gTmin = 200.0, gTmax = 6000.0;
+constexpr int kGRows = 8;  // rows eliminated per pass of the pivot row
 
 // Workspace of S slots, entry-major: entry e of slot s sits at base[e * S + s].
 struct GWork {
@@ -265,22 +266,22 @@ __device__ bool glu_solve(const GWork &w, long long sl, int N)
         }
         const R piv = (R)Aat(k, k);
         const R yk = (R)b[(size_t)k * S];
-        // rows in groups of four: each pivot-row element is loaded once per group, and the
-        // group's sixteen loads per column pair are independent, which keeps enough memory
-        // operations in flight per thread
+        // rows in groups of kGRows: each pivot-row element is loaded once per group, and the
+        // group's loads per column pair are independent, which keeps enough memory operations
+        // in flight per thread
         int i = k + 1;
-        for (; i + 4 <= N; i += 4) {
-            R l[4];
+        for (; i + kGRows <= N; i += kGRows) {
+            R l[kGRows];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) l[r] = (R)Aat(i + r, k) / piv;
+            for (int r = 0; r < kGRows; ++r) l[r] = (R)Aat(i + r, k) / piv;
             int j = k + 1;
             for (; j + 2 <= N; j += 2) {
                 const R a0 = (R)Aat(k, j), a1 = (R)Aat(k, j + 1);
-                R v[4][2];
+                R v[kGRows][2];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) { v[r][0] = (R)Aat(i + r, j); v[r][1] = (R)Aat(i + r, j + 1); }
+                for (int r = 0; r < kGRows; ++r) { v[r][0] = (R)Aat(i + r, j); v[r][1] = (R)Aat(i + r, j + 1); }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < kGRows; ++r) {
                     Aat(i + r, j) = (double)fma(-l[r], a0, v[r][0]);
                     Aat(i + r, j + 1) = (double)fma(-l[r], a1, v[r][1]);
                 }
@@ -288,10 +289,10 @@ __device__ bool glu_solve(const GWork &w, long long sl, int N)
             for (; j < N; ++j) {
                 const R a0 = (R)Aat(k, j);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Aat(i + r, j) = (double)fma(-l[r], a0, (R)Aat(i + r, j));
+                for (int r = 0; r < kGRows; ++r) Aat(i + r, j) = (double)fma(-l[r], a0, (R)Aat(i + r, j));
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) b[(size_t)(i + r) * S] = (double)fma(-l[r], yk, (R)b[(size_t)(i + r) * S]);
+            for (int r = 0; r < kGRows; ++r) b[(size_t)(i + r) * S] = (double)fma(-l[r], yk, (R)b[(size_t)(i + r) * S]);
         }
         for (; i < N; ++i) {
             const R l = (R)Aat(i, k) / piv;
