@@ -60,6 +60,9 @@ __device__ __forceinline__ kin_cptr kin_launder(const double *p)
     return (kin_cptr)p;
 }
 
+// Unknown held at position i of the solved system: T first, then the species.
+#define KIN_VAR(i) ((i) == 0 ? KIN_NS : (i) - 1)
+
 #define KIN_T_MIN 200.0
 #define KIN_T_MAX 6000.0
 
@@ -181,6 +184,18 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
         }
     }
     if (!(chk == 0.0)) return KIN_ATTEMPT_FAILED;  // some entry of A or G is not finite
+    // The system is solved with the unknowns in the order (T, Y_1..Y_Ns): the temperature
+    // row, whose entries are the largest, is then the first pivot row instead of being
+    // exchanged upwards through the first columns, and most wavefronts skip the exchange
+    // selects in more columns.  The order is a compile-time renaming of registers; the
+    // solution is the same, up to rounding.
+    double P[KIN_N][KIN_N], q[KIN_N];
+#pragma unroll
+    for (int i = 0; i < KIN_N; ++i) {
+        q[i] = b[KIN_VAR(i)];
+#pragma unroll
+        for (int j = 0; j < KIN_N; ++j) P[i][j] = A[KIN_VAR(i)][KIN_VAR(j)];
+    }
     double d[KIN_N];
     if (F32) {
         float Af[KIN_N][KIN_N], bf[KIN_N];
@@ -188,19 +203,19 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
         for (int i = 0; i < KIN_N; ++i) {
             double m = 0.0;
 #pragma unroll
-            for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(A[i][j]));
+            for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(P[i][j]));
             const double s = 1.0 / m;
 #pragma unroll
-            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(A[i][j] * s);
-            bf[i] = (float)(b[i] * s);
+            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(P[i][j] * s);
+            bf[i] = (float)(q[i] * s);
         }
         if (!kin_lu_solve<float>(Af, bf)) return KIN_ATTEMPT_FAILED;
 #pragma unroll
-        for (int i = 0; i < KIN_N; ++i) d[i] = (double)bf[i];
+        for (int i = 0; i < KIN_N; ++i) d[KIN_VAR(i)] = (double)bf[i];
     } else {
-        if (!kin_lu_solve<double>(A, b)) return KIN_ATTEMPT_FAILED;
+        if (!kin_lu_solve<double>(P, q)) return KIN_ATTEMPT_FAILED;
 #pragma unroll
-        for (int i = 0; i < KIN_N; ++i) d[i] = b[i];
+        for (int i = 0; i < KIN_N; ++i) d[KIN_VAR(i)] = q[i];
     }
     bool conv = true;
     double chk2 = 0.0;
