@@ -56,3 +56,20 @@ def test_mechanism_validation():
         kin.jit_check(bad)
     with pytest.raises(kin.KinError):
         kin.jit_check(synth.mechanism("mech36"))  # 36 species exceed the lane layout
+
+
+def test_c_program_compiles_against_header(tmp_path):
+    """The plain-C check program (tests/abi_c/kin_abi_check.c) compiles and links against
+    include/kin.h and libkin.so with a C compiler alone (its GPU run is a separate test)."""
+    import shutil
+    import subprocess
+    from paper_1110_4903_amd import kin
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = tmp_path / "kin_abi_check"
+    src = os.path.join(ROOT, "tests", "abi_c", "kin_abi_check.c")
+    libdir = os.path.dirname(kin.SO)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), src,
+                        "-L", libdir, "-lkin", "-lm", "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
