@@ -231,8 +231,8 @@ def run_conserved_adapter(torch, ctx, kin, synth, args, stream):
 
 
 def run_global_tier(torch, ctx, kin, flops, synth, args, stream):
-    """The global-memory layout (one thread per cell, the cell's matrix in HBM; the paper's
-    first kinetics kernel) on a generated 100-species / 600-reaction mechanism, beyond the
+    """The global-memory layout (one wavefront per cell, the cell's matrix in HBM, as in the
+    paper's first kinetics kernel) on a generated 100-species / 600-reaction mechanism, beyond the
     wave layout's 63 species: one FP64 step of 1e-6 s on 65536 cells (Dirichlet(0.5), seed 7).
     Achieved bandwidth = the algorithmic bytes of a Newton iteration (flops.global_tier_bytes)
     times the iterations of the launch, over its duration."""

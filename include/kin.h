@@ -52,10 +52,11 @@ typedef enum { KIN_MEM_HOST = 0, KIN_MEM_DEVICE = 1, KIN_MEM_PINNED = 2 } kin_me
 
 /* Kernel layouts: one cell per lane with the Newton matrix in registers (ns <= 15), one cell
  * per 64-wide wavefront with one matrix row per lane and the Jacobian staged in LDS
- * (ns <= 63), or one cell per thread with the cell's whole matrix in global memory, the
- * paper's first kinetics kernel (Sec. 4.2; any ns up to 255, the automatic choice above 63).
- * The global layout allocates its workspace (at most 16 GiB) stream-ordered on the launch
- * stream, or with the graph of a batched advance, and is bound by HBM bandwidth. */
+ * (ns <= 63), or one cell per wavefront with the cell's whole matrix in global memory, which
+ * is what the paper's first kinetics kernel keeps there (Sec. 4.2; any ns up to 255, the
+ * automatic choice above 63).  The global layout allocates its workspace (at most 16 GiB)
+ * stream-ordered on the launch stream, or with the graph of a batched advance, and is bound
+ * by HBM bandwidth. */
 typedef enum { KIN_LAYOUT_AUTO = 0, KIN_LAYOUT_LANE = 1, KIN_LAYOUT_WAVE = 2, KIN_LAYOUT_GLOBAL = 3 } kin_layout;
 
 /* Per-cell status codes written by kin_advance. */

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libkin.so")
 SOURCES = ["kin_runtime.cpp", "kin_codegen.cpp", "kin_wave.hip", "kin_global.hip"]
-HEADERS = ["kin_internal.h", "kin_lane_template.h"]
+HEADERS = ["kin_internal.h", "kin_lane_template.h", "kin_xlane.h"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("KIN_OFFLOAD_ARCH", "gfx950")

@@ -1,11 +1,11 @@
-// kin_global.hip -- the global-memory tier, for mechanisms beyond the wave layout's 63 species
-// (up to 255).  It follows the first of the paper's two kinetics kernels (Sec. 4.2): one
-// thread per cell, the cell's whole Jacobian in global memory, stored entry-major so that the
-// 64 cells of a wavefront touch one entry in one coalesced access.  Gaussian elimination with
-// partial pivoting streams the matrix through memory, so this tier is bound by HBM bandwidth,
-// not by the vector ALUs.  The working set of a launch (matrix, vectors) lives in a workspace
-// of S slots, one per thread; a cell occupies a slot from its first to its last Newton
-// iteration, and a slot that finishes its cell takes the next one from the work counter.
+// kin_global.hip -- the global-memory layout, for mechanisms beyond the wave layout's 63
+// species (up to 255).  The paper's first kinetics kernel (Sec. 4.2) keeps each cell's whole
+// Jacobian in global memory with one thread per cell; here a cell gets a whole wavefront, and
+// its matrix sits in global memory column-major, so that one column of one cell is one
+// coalesced access and the wavefront's 64 lanes share each elimination step.  Every trailing
+// element is read and written once per pivot step, which makes the layout bound by HBM
+// bandwidth.  The matrices of a launch live in a workspace of slots, one per wavefront; a
+// wavefront that finishes its cell takes the next from the work counter.
 //
 // Method as in the other layouts: Newton iterations on backward Euler in x = (Y, T) for a
 // constant-(rho, e) cell, (I - hJ) dx = -G, dyadic sub-step halving on failure (Sec. 3.2,
@@ -19,38 +19,9 @@
 namespace kin {
 namespace {
 
+#include "kin_xlane.h"
+
 constexpr double gTmin = 200.0, gTmax = 6000.0;
-constexpr int kGRows = 8;  // rows eliminated per pass of the pivot row
-
-// Workspace of S slots, entry-major: entry e of slot s sits at base[e * S + s].
-struct GWork {
-    double *J;   // [N * N]  Jacobian, then the Newton matrix and its LU factors
-    double *f;   // [N]      production sums, then f, then the right-hand side and the update
-    double *x;   // [N]      last accepted state
-    double *xk;  // [N]      Newton iterate
-    double *c;   // [ns]     concentrations
-    double *g;   // [ns]     g/RT, then e_s
-    double *hh;  // [ns]     h/RT, then c_v,s
-    double *Mc;  // [ntb]    third-body concentrations, then q_f - q_b of the slot's reaction
-    long long S;
-};
-
-__device__ __forceinline__ GWork gwork_map(double *base, int ns, int ntb, long long S)
-{
-    const size_t N = (size_t)ns + 1;
-    GWork w;
-    double *p = base;
-    w.J = p; p += N * N * (size_t)S;
-    w.f = p; p += N * (size_t)S;
-    w.x = p; p += N * (size_t)S;
-    w.xk = p; p += N * (size_t)S;
-    w.c = p; p += (size_t)ns * S;
-    w.g = p; p += (size_t)ns * S;
-    w.hh = p; p += (size_t)ns * S;
-    w.Mc = p;
-    w.S = S;
-    return w;
-}
 
 struct GThermo {
     double cp, h, s, dcp;
@@ -76,29 +47,83 @@ __device__ __forceinline__ void gpow(double c, int nu, double &p, double &dp)
     dp = (double)nu * h;
 }
 
-// Mixture e (J/kg) and c_v (J/kg/K) of slot `sl`'s iterate at T.
-__device__ __forceinline__ void genergy(const WaveTables &t, const GWork &w, long long sl, double T,
-                                       double &e, double &cv)
+enum { G_CONTINUE = 0, G_ACCEPTED = 1, G_FAILED = 2 };
+
+// ==== one wavefront per cell ======================================================================
+// The cell's matrix sits in global memory column-major with column stride NP = N rounded up to
+// 64, so that one column of one cell is one coalesced access of its wavefront.  Lane l owns
+// rows (and unknowns) l, l + 64, l + 128, l + 192 (at most RW per lane).  Species vectors
+// and the pivot row are staged in LDS; rows stay in place during the elimination (a row's
+// current position is `pos`, as in the wave layout), so a step reads and writes every
+// trailing element once and reads the pivot row once.
+
+__device__ __forceinline__ int gnp(int N) { return (N + 63) & ~63; }
+
+// element (row i, column j) of the slot's matrix
+__device__ __forceinline__ double *gm(double *M, int NP, int i, int j) { return M + (size_t)j * NP + i; }
+
+__device__ __forceinline__ double gw_sum(double v) { return wave_sum(v); }
+
+template <int RW, typename T>
+__device__ __forceinline__ T pick(const T (&v)[RW], int m)
 {
-    e = 0.0;
-    cv = 0.0;
-    const double iT = 1.0 / T;
-    for (int s = 0; s < t.ns; ++s) {
-        const GThermo th = gthermo(t, s, T, iT, 0.0);
-        const double rm = 8.31446261815324e3 / t.M[s];
-        const double y = w.xk[(size_t)s * w.S + sl];
-        e = fma(y, rm * T * (th.h - 1.0), e);
-        cv = fma(y, rm * (th.cp - 1.0), cv);
-    }
+    T r = v[0];
+#pragma unroll
+    for (int q = 1; q < RW; ++q) r = (m == q) ? v[q] : r;
+    return r;
 }
 
-__device__ bool ginvert_T(const WaveTables &t, const GWork &w, long long sl, double e0, double T0,
-                          double &T_out)
+struct GLds {
+    double *c, *g, *hh, *W, *Mc, *prow;
+};
+
+// LDS doubles per wavefront: c, g, hh (ns each), W and the pivot row (N each), the [M] slots
+__host__ __device__ inline size_t glds_doubles(int ns, int ntb)
+{
+    return 3 * (size_t)ns + 2 * ((size_t)ns + 1) + (size_t)(ntb > 0 ? ntb : 1);
+}
+
+__device__ __forceinline__ GLds glds_map(double *p, int ns, int ntb)
+{
+    GLds L;
+    L.c = p; p += ns;
+    L.g = p; p += ns;
+    L.hh = p; p += ns;
+    L.W = p; p += ns + 1;
+    L.prow = p; p += ns + 1;
+    L.Mc = p;
+    return L;
+}
+
+// Mixture e and c_v at T for the state held in x[] (lane l: unknowns l + 64 m); wave-uniform.
+template <int RW>
+__device__ __forceinline__ void gw_energy(const WaveTables &t, int lane, const double (&x)[RW], double T,
+                                          double &e, double &cv)
+{
+    double es = 0.0, cs = 0.0;
+    const double iT = 1.0 / T;
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int s = lane + 64 * m;
+        if (s < t.ns) {
+            const GThermo th = gthermo(t, s, T, iT, 0.0);
+            const double rm = 8.31446261815324e3 / t.M[s];
+            es = fma(x[m], rm * T * (th.h - 1.0), es);
+            cs = fma(x[m], rm * (th.cp - 1.0), cs);
+        }
+    }
+    e = gw_sum(es);
+    cv = gw_sum(cs);
+}
+
+template <int RW>
+__device__ bool gw_invert_T(const WaveTables &t, int lane, const double (&x)[RW], double e0, double T0,
+                            double &T_out)
 {
     double T = T0;
     for (int it = 0; it < 20; ++it) {
         double e, cv;
-        genergy(t, w, sl, T, e, cv);
+        gw_energy<RW>(t, lane, x, T, e, cv);
         if (!(cv > 0.0)) break;
         const double dT = (e - e0) / cv;
         T -= dT;
@@ -106,49 +131,65 @@ __device__ bool ginvert_T(const WaveTables &t, const GWork &w, long long sl, dou
         if (fabs(dT) <= 1e-13 * T) { T_out = T; return true; }
     }
     double lo = gTmin, hi = gTmax, e, cv;
-    genergy(t, w, sl, lo, e, cv);
+    gw_energy<RW>(t, lane, x, lo, e, cv);
     const double flo = e - e0;
-    genergy(t, w, sl, hi, e, cv);
+    gw_energy<RW>(t, lane, x, hi, e, cv);
     const double fhi = e - e0;
     if (!(flo <= 0.0 && fhi >= 0.0)) return false;
     for (int it = 0; it < 200 && hi - lo > 1e-13 * lo; ++it) {
         const double mid = 0.5 * (lo + hi);
-        genergy(t, w, sl, mid, e, cv);
+        gw_energy<RW>(t, lane, x, mid, e, cv);
         if (e - e0 > 0.0) hi = mid; else lo = mid;
     }
     T_out = 0.5 * (lo + hi);
     return true;
 }
 
-// f = dx/dt into w.f and J = df/dx into w.J at the iterate w.xk.
-__device__ void geval(const WaveTables &t, const GWork &w, long long sl, double rho)
+// f (lane l: f of unknowns l + 64 m, into f[]) and the Jacobian into the slot's matrix, at xk.
+template <int RW>
+__device__ void gw_eval(const WaveTables &t, const GLds &L, double *Mx, int lane, double rho,
+                        const double (&xk)[RW], double (&f)[RW])
 {
-    const int ns = t.ns, N = ns + 1;
-    const size_t S = (size_t)w.S;
-    double *J = w.J + sl, *f = w.f + sl;
-    const auto Jat = [&](int i, int j) -> double & { return J[((size_t)i * N + j) * S]; };
-    const double T = w.xk[(size_t)ns * S + sl];
+    const int ns = t.ns, N = ns + 1, NP = gnp(N);
+    const double T = rdlane(pick<RW>(xk, ns >> 6), ns & 63);
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
     const double lPaRT = t.lnPaR - lT;
-    for (int s = 0; s < ns; ++s) {
-        const GThermo th = gthermo(t, s, T, iT, lT);
-        w.c[(size_t)s * S + sl] = w.xk[(size_t)s * S + sl] * (rc / t.M[s]);
-        w.g[(size_t)s * S + sl] = th.h - th.s;
-        w.hh[(size_t)s * S + sl] = th.h;
+    double ek[RW], cvk[RW], dcvk[RW];
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int s = lane + 64 * m;
+        ek[m] = cvk[m] = dcvk[m] = 0.0;
+        if (s < ns) {
+            const GThermo th = gthermo(t, s, T, iT, lT);
+            const double rm = 8.31446261815324e3 / t.M[s];
+            L.c[s] = xk[m] * (rc / t.M[s]);
+            L.g[s] = th.h - th.s;
+            L.hh[s] = th.h;
+            ek[m] = rm * T * (th.h - 1.0);
+            cvk[m] = rm * (th.cp - 1.0);
+            dcvk[m] = rm * th.dcp;
+        }
+        if (s < N) L.W[s] = 0.0;
     }
-    for (size_t e = 0; e < (size_t)N * N; ++e) J[e * S] = 0.0;
-    for (int i = 0; i < N; ++i) f[(size_t)i * S] = 0.0;
-    // third-body concentrations [M]_q = sum_s eff_qs c_s
-    for (int q = 0; q < t.ntb; ++q) {
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int m = 0; m < RW; ++m)
+            if (lane + 64 * m < N) *gm(Mx, NP, lane + 64 * m, j) = 0.0;
+    wave_sync();
+    for (int q = lane; q < t.ntb; q += 64) {
         double acc = 0.0;
-        for (int s = 0; s < ns; ++s) acc = fma(t.effT[(size_t)s * t.ntb + q], w.c[(size_t)s * S + sl], acc);
-        w.Mc[(size_t)q * S + sl] = acc;
+        for (int s = 0; s < ns; ++s) acc = fma(t.effT[(size_t)s * t.ntb + q], L.c[s], acc);
+        L.Mc[q] = acc;
     }
-    // reactions: Q_r = [M]_r (k_f prod c^nu' - k_b prod c^nu''), six species slots per
-    // reaction (reactants 0-2, products 3-5, unused slots have nu = 0)
+    // the zeroing stores complete before the atomic adds
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wave_sync();
+    // reactions, one per lane; Jacobian terms by atomic adds into the slot's matrix
     const double4 *rxd4 = reinterpret_cast<const double4 *>(t.rxd);
-    for (int r = 0; r < t.nr; ++r) {
+    for (int r0 = 0; r0 < t.nr; r0 += 64) {
+        const int r = r0 + lane;
+        if (r >= t.nr) continue;
         const RxnRec x = t.rxc[r];
         const double4 rd = rxd4[r];
         const RxnCoef *kc = t.rxk + r;
@@ -157,13 +198,14 @@ __device__ void geval(const WaveTables &t, const GWork &w, long long sl, double 
         const double dlkf = fma(rd.z, iT, rd.y) * iT;
         double pw[6], dpw[6], sg = 0.0, sh = 0.0;
         int sp[6];
+#pragma unroll
         for (int q = 0; q < 6; ++q) {
             sp[q] = x.coff[q] >> 3;
             double cq = 1.0;
             if (x.nu[q] != 0) {
-                cq = w.c[(size_t)sp[q] * S + sl];
-                sg = fma((double)x.nu[q], w.g[(size_t)sp[q] * S + sl], sg);
-                sh = fma((double)x.nu[q], w.hh[(size_t)sp[q] * S + sl], sh);
+                cq = L.c[sp[q]];
+                sg = fma((double)x.nu[q], L.g[sp[q]], sg);
+                sh = fma((double)x.nu[q], L.hh[sp[q]], sh);
             }
             gpow(cq, q < 3 ? -x.nu[q] : x.nu[q], pw[q], dpw[q]);
         }
@@ -180,212 +222,203 @@ __device__ void geval(const WaveTables &t, const GWork &w, long long sl, double 
         dq[3] = rev ? -kb * (dpw[3] * pw[4] * pw[5]) : 0.0;
         dq[4] = rev ? -kb * (pw[3] * dpw[4] * pw[5]) : 0.0;
         dq[5] = rev ? -kb * (pw[3] * pw[4] * dpw[5]) : 0.0;
-        const double Mc = x.tb >= 0 ? w.Mc[(size_t)x.tb * S + sl] : 1.0;
+        const double Mc = x.tb >= 0 ? L.Mc[x.tb] : 1.0;
         const double D = pf - pb;
-        const double q = Mc * D;
+        const double qr = Mc * D;
         const double qT = Mc * (pf * dlkf - pb * (dlkf - dlKc));
-        if (x.tb >= 0) w.Mc[(size_t)x.tb * S + sl] = D;
+        if (x.tb >= 0) L.Mc[x.tb] = D;
+#pragma unroll
         for (int k = 0; k < 6; ++k) dq[k] = Mc * dq[k] * kc->colc[k];
+#pragma unroll
         for (int i = 0; i < 6; ++i) {
             if (x.nu[i] == 0) continue;
             const double nu = (double)x.nu[i];
             const double a = kc->rowc[i];
-            f[(size_t)sp[i] * S] += nu * q;
-            Jat(sp[i], ns) += nu * qT;
+            __hip_atomic_fetch_add(L.W + sp[i], nu * qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            atomicAdd(gm(Mx, NP, sp[i], ns), nu * qT);
+#pragma unroll
             for (int j = 0; j < 6; ++j)
-                if (x.nu[j] != 0) Jat(sp[i], sp[j]) += a * dq[j];
+                if (x.nu[j] != 0) atomicAdd(gm(Mx, NP, sp[i], sp[j]), a * dq[j]);
         }
     }
-    // dense third-body terms: J[s][k] += D_q nu_qs M_s eff_qk / M_k
-    for (int e = 0; e < t.ntbe; ++e) {
-        const int ent = t.tbe[e];
-        const double D = w.Mc[(size_t)(ent & 0xffff) * S + sl];
-        const int row = ent >> 16;
-        const double *er = t.effR + (size_t)e * ns;
-        for (int k = 0; k < ns; ++k) Jat(row, k) += D * er[k];
+    // the atomic adds complete, and no stale copy of their lines stays in this CU's cache
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    wave_sync();
+    // dense third-body terms, entries sorted by row: lane k sums a row's entries for its
+    // columns in registers and adds each sum once
+    {
+        int cur = t.ntbe > 0 ? (t.tbe[0] >> 16) : 0;
+        double acc[RW];
+#pragma unroll
+        for (int m = 0; m < RW; ++m) acc[m] = 0.0;
+        for (int e = 0; e < t.ntbe; ++e) {
+            const int ent = t.tbe[e];
+            const int row = ent >> 16;
+            if (row != cur) {
+#pragma unroll
+                for (int m = 0; m < RW; ++m)
+                    if (lane + 64 * m < ns) { *gm(Mx, NP, cur, lane + 64 * m) += acc[m]; acc[m] = 0.0; }
+                cur = row;
+            }
+            const double D = L.Mc[ent & 0xffff];
+            const double *er = t.effR + (size_t)e * ns;
+#pragma unroll
+            for (int m = 0; m < RW; ++m)
+                if (lane + 64 * m < ns) acc[m] = fma(D, er[lane + 64 * m], acc[m]);
+        }
+        if (t.ntbe > 0)
+#pragma unroll
+            for (int m = 0; m < RW; ++m)
+                if (lane + 64 * m < ns) *gm(Mx, NP, cur, lane + 64 * m) += acc[m];
     }
     // species rows of f and the temperature column; e_s and c_v,s replace g and h
-    double cv = 0.0, dcv = 0.0, de = 0.0;
-    for (int s = 0; s < ns; ++s) {
-        const GThermo th = gthermo(t, s, T, iT, lT);
-        const double rm = 8.31446261815324e3 / t.M[s];
-        const double ms = t.M[s] * irc;
-        const double fs = f[(size_t)s * S] * ms;
-        f[(size_t)s * S] = fs;
-        Jat(s, ns) *= ms;
-        const double ek = rm * T * (th.h - 1.0), cvk = rm * (th.cp - 1.0);
-        w.g[(size_t)s * S + sl] = ek;
-        w.hh[(size_t)s * S + sl] = cvk;
-        const double xs = w.xk[(size_t)s * S + sl];
-        cv = fma(xs, cvk, cv);
-        dcv = fma(xs, rm * th.dcp, dcv);
-        de = fma(ek, fs, de);
+    double de = 0.0, cv = 0.0, dcv = 0.0;
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int s = lane + 64 * m;
+        f[m] = 0.0;
+        if (s < ns) {
+            const double ms = t.M[s] * irc;
+            f[m] = L.W[s] * ms;
+            *gm(Mx, NP, s, ns) *= ms;
+            L.g[s] = ek[m];
+            L.hh[s] = cvk[m];
+            de = fma(ek[m], f[m], de);
+            cv = fma(xk[m], cvk[m], cv);
+            dcv = fma(xk[m], dcvk[m], dcv);
+        }
     }
+    cv = gw_sum(cv);
+    dcv = gw_sum(dcv);
+    de = gw_sum(de);
     const double fT = -de / cv, icv = 1.0 / cv;
-    // energy row: J[ns][k] = -(sum_s e_s J[s][k] + f_T c_v,k) / c_v
-    for (int k = 0; k < ns; ++k) {
-        double acc = 0.0;
-        for (int s = 0; s < ns; ++s) acc = fma(w.g[(size_t)s * S + sl], Jat(s, k), acc);
-        Jat(ns, k) = -fma(fT, w.hh[(size_t)k * S + sl], acc) * icv;
+    wave_sync();
+    // energy row: J[ns][k] = -(sum_s e_s J[s][k] + f_T c_v,k) / c_v, one column per step
+    for (int k = 0; k <= ns; ++k) {
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int s = lane + 64 * m;
+            if (s < ns) {
+                part = fma(L.g[s], *gm(Mx, NP, s, k), part);
+                if (k == ns) part = fma(L.hh[s], f[m], part);
+            }
+        }
+        const double acc = gw_sum(part);
+        const double v = (k < ns) ? -fma(fT, L.hh[k], acc) * icv : -fma(fT, dcv, acc) * icv;
+        if (lane == 0) *gm(Mx, NP, ns, k) = v;
     }
-    double acc = 0.0;
-    for (int s = 0; s < ns; ++s)
-        acc = fma(w.hh[(size_t)s * S + sl], f[(size_t)s * S], fma(w.g[(size_t)s * S + sl], Jat(s, ns), acc));
-    Jat(ns, ns) = -fma(fT, dcv, acc) * icv;
-    f[(size_t)ns * S] = fT;
+    if ((ns & 63) == lane) f[ns >> 6] = fT;
+    wave_sync();
 }
 
-// Gaussian elimination with partial pivoting (first row of largest |a_ik|) on the slot's
-// Newton matrix, applied to the right-hand side in w.f, then back substitution: w.f holds the
-// update on return.  Rows are exchanged in memory.  F32: the factorisation and solves run in
-// FP32 on values rounded from the FP64 matrix (already row-equilibrated by the caller).
-template <bool F32>
-__device__ bool glu_solve(const GWork &w, long long sl, int N)
+// Gaussian elimination with partial pivoting over the slot's matrix, rows in place; b[] holds
+// the right-hand side of the lane's rows and returns the update of its unknowns.
+template <bool F32, int RW>
+__device__ bool gw_solve(const GLds &L, double *Mx, int lane, int N, double (&b)[RW])
 {
     using R = typename std::conditional<F32, float, double>::type;
-    const size_t S = (size_t)w.S;
-    double *A = w.J + sl, *b = w.f + sl;
-    const auto Aat = [&](int i, int j) -> double & { return A[((size_t)i * N + j) * S]; };
+    const int NP = gnp(N);
+    int pos[RW];
+    double dg[RW];
+#pragma unroll
+    for (int m = 0; m < RW; ++m) { pos[m] = lane + 64 * m; dg[m] = 1.0; }
+    bool ok = true;
     for (int k = 0; k < N; ++k) {
-        int p = k;
-        R amax = (R)fabs((R)Aat(k, k));
-        for (int i = k + 1; i < N; ++i) {
-            const R v = (R)fabs((R)Aat(i, k));
-            if (v > amax) { amax = v; p = i; }
-        }
-        if (amax == R(0)) return false;
-        if (p != k) {
-            for (int j = k; j < N; ++j) {
-                const double tk = Aat(k, j);
-                Aat(k, j) = Aat(p, j);
-                Aat(p, j) = tk;
+        // the lane's best candidate row in column k: largest |a|, ties to the lowest position
+        double v[RW];
+        R best = R(-1);
+        int bpos = 0x7fffffff, bm = 0;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int i = lane + 64 * m;
+            v[m] = 0.0;
+            if (i < N) {
+                v[m] = *gm(Mx, NP, i, k);
+                const R a = (R)fabs((R)v[m]);
+                if (pos[m] >= k && (a > best || (a == best && pos[m] < bpos))) { best = a; bpos = pos[m]; bm = m; }
             }
-            const double tb = b[(size_t)k * S];
-            b[(size_t)k * S] = b[(size_t)p * S];
-            b[(size_t)p * S] = tb;
         }
-        const R piv = (R)Aat(k, k);
-        const R yk = (R)b[(size_t)k * S];
-        // rows in groups of kGRows: each pivot-row element is loaded once per group, and the
-        // group's loads per column pair are independent, which keeps enough memory operations
-        // in flight per thread
-        int i = k + 1;
-        for (; i + kGRows <= N; i += kGRows) {
-            R l[kGRows];
+        const bool cand = bpos != 0x7fffffff;
+        const int w = pivot_lane<R>(cand ? best : R(0), cand, cand ? bpos : 0x7fffffff);
+        const int mw = rdlane(bm, w);
+        const int p = w + 64 * mw;                       // physical pivot row
+        const int pos_p = rdlane(pick<RW>(pos, mw), w);
+        const double piv_d = rdlane(pick<RW>(v, mw), w);
+        const R piv = (R)piv_d;
+        if (piv == R(0)) ok = false;
+        const double yk = rdlane(pick<RW>(b, mw), w);
 #pragma unroll
-            for (int r = 0; r < kGRows; ++r) l[r] = (R)Aat(i + r, k) / piv;
-            int j = k + 1;
-            for (; j + 2 <= N; j += 2) {
-                const R a0 = (R)Aat(k, j), a1 = (R)Aat(k, j + 1);
-                R v[kGRows][2];
+        for (int m = 0; m < RW; ++m) {
+            const int i = lane + 64 * m;
+            const bool isp = i == p;
+            dg[m] = isp ? piv_d : dg[m];
+            pos[m] = isp ? k : (pos[m] == k ? pos_p : pos[m]);
+        }
+        // the pivot row's trailing part into LDS
+        for (int j = k + 1 + lane; j < N; j += 64) L.prow[j] = *gm(Mx, NP, p, j);
+        wave_sync();
+        R l[RW];
 #pragma unroll
-                for (int r = 0; r < kGRows; ++r) { v[r][0] = (R)Aat(i + r, j); v[r][1] = (R)Aat(i + r, j + 1); }
+        for (int m = 0; m < RW; ++m) {
+            l[m] = (lane + 64 * m < N && pos[m] > k) ? (R)v[m] / piv : R(0);
+            b[m] = (double)fma(-l[m], (R)yk, (R)b[m]);
+        }
+        for (int j = k + 1; j < N; ++j) {
+            const R pj = (R)L.prow[j];
 #pragma unroll
-                for (int r = 0; r < kGRows; ++r) {
-                    Aat(i + r, j) = (double)fma(-l[r], a0, v[r][0]);
-                    Aat(i + r, j + 1) = (double)fma(-l[r], a1, v[r][1]);
+            for (int m = 0; m < RW; ++m) {
+                if (l[m] != R(0)) {
+                    double *e = gm(Mx, NP, lane + 64 * m, j);
+                    *e = (double)fma(-l[m], pj, (R)*e);
                 }
             }
-            for (; j < N; ++j) {
-                const R a0 = (R)Aat(k, j);
-#pragma unroll
-                for (int r = 0; r < kGRows; ++r) Aat(i + r, j) = (double)fma(-l[r], a0, (R)Aat(i + r, j));
-            }
-#pragma unroll
-            for (int r = 0; r < kGRows; ++r) b[(size_t)(i + r) * S] = (double)fma(-l[r], yk, (R)b[(size_t)(i + r) * S]);
         }
-        for (; i < N; ++i) {
-            const R l = (R)Aat(i, k) / piv;
-            for (int j = k + 1; j < N; ++j) Aat(i, j) = (double)fma(-l, (R)Aat(k, j), (R)Aat(i, j));
-            b[(size_t)i * S] = (double)fma(-l, yk, (R)b[(size_t)i * S]);
+        wave_sync();
+    }
+    // back substitution by columns: the row at position k gives x_k, which every row above
+    // it removes from its right-hand side
+    double xl[RW];
+#pragma unroll
+    for (int m = 0; m < RW; ++m) xl[m] = 0.0;
+    for (int k = N - 1; k >= 0; --k) {
+        int o = -1, om = 0;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const unsigned long long bal = __ballot(lane + 64 * m < N && pos[m] == k);
+            if (bal) { o = __builtin_ctzll(bal); om = m; }
+        }
+        const double xk = (double)((R)rdlane(pick<RW>(b, om), o) / (R)rdlane(pick<RW>(dg, om), o));
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int i = lane + 64 * m;
+            if (i == k) xl[m] = xk;
+            if (i < N && pos[m] < k) b[m] = (double)fma(-(R)*gm(Mx, NP, i, k), (R)xk, (R)b[m]);
         }
     }
-    for (int i = N - 1; i >= 0; --i) {
-        R s = (R)b[(size_t)i * S];
-        for (int j = i + 1; j < N; ++j) s = fma(-(R)Aat(i, j), (R)b[(size_t)j * S], s);
-        b[(size_t)i * S] = (double)(s / (R)Aat(i, i));
-    }
-    return true;
+#pragma unroll
+    for (int m = 0; m < RW; ++m) b[m] = xl[m];
+    return ok;
 }
 
-enum { G_CONTINUE = 0, G_ACCEPTED = 1, G_FAILED = 2 };
-
-// One Newton iteration of slot sl on the backward-Euler system of sub-step h.
-template <bool F32>
-__device__ int gnewton(const WaveTables &t, const AdvanceArgs &a, const GWork &w, long long sl, double rho,
-                       double e0, double h, double &r_prev)
+template <bool F32, int RW>
+__global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, double *wsbase, long long S)
 {
-    const int ns = t.ns, N = ns + 1;
-    const size_t S = (size_t)w.S;
-    geval(t, w, sl, rho);
-    double *A = w.J + sl, *b = w.f + sl;
-    double chk = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double gi = -((w.xk[(size_t)i * S + sl] - w.x[(size_t)i * S + sl]) - h * b[(size_t)i * S]);
-        double m = 0.0;
-        for (int j = 0; j < N; ++j) {
-            double &aij = A[((size_t)i * N + j) * S];
-            const double v = (i == j ? 1.0 : 0.0) - h * aij;
-            aij = v;
-            chk += v - v;
-            m = fmax(m, fabs(v));
-        }
-        chk += gi - gi;
-        if (F32) {  // row equilibration before rounding to FP32
-            const double sc = 1.0 / m;
-            for (int j = 0; j < N; ++j) A[((size_t)i * N + j) * S] *= sc;
-            b[(size_t)i * S] = gi * sc;
-        } else {
-            b[(size_t)i * S] = gi;
-        }
-    }
-    if (!(chk == 0.0)) return G_FAILED;
-    if (!glu_solve<F32>(w, sl, N)) return G_FAILED;
-    bool conv = true;
-    double chk2 = 0.0, r = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double d = b[(size_t)i * S];
-        const double xi = w.xk[(size_t)i * S + sl] + d;
-        w.xk[(size_t)i * S + sl] = xi;
-        chk2 += xi - xi;
-        const double atol = (i < ns) ? a.atol_Y : a.atol_T;
-        conv = conv && (fabs(d) <= atol + a.rtol * fabs(xi));
-        r = fmax(r, fabs(d) / (atol + a.rtol * fabs(xi)));
-    }
-    if (!(chk2 == 0.0)) return G_FAILED;
-    const double Tk = w.xk[(size_t)ns * S + sl];
-    if (Tk < gTmin || Tk > gTmax) return G_FAILED;
-    if (!conv && !a.point_implicit) {
-        if (a.diverge_ratio > 0.0) {
-            if (r_prev >= 0.0 && r > a.diverge_ratio * r_prev) return G_FAILED;
-            r_prev = r;
-        }
-        return G_CONTINUE;
-    }
-    if (!a.point_implicit)
-        for (int s = 0; s < ns; ++s)
-            if (w.xk[(size_t)s * S + sl] < -a.y_neg) return G_FAILED;
-    double Tn;
-    if (!ginvert_T(t, w, sl, e0, Tk, Tn)) return G_FAILED;
-    w.xk[(size_t)ns * S + sl] = Tn;
-    return G_ACCEPTED;
-}
-
-// Persistent slots: every loop trip performs one Newton iteration for the cell each thread
-// holds; a thread that finishes its cell stores it and takes the next cell index from the
-// work counter.  Controller as in the other layouts (dyadic sub-steps, halving on failure).
-template <bool F32>
-__global__ void __launch_bounds__(64) global_kernel(WaveTables t, AdvanceArgs a, double *wsbase, long long S)
-{
-    const long long sl = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (sl >= S) return;
-    const GWork w = gwork_map(wsbase, t.ns, t.ntb, S);
-    const int ns = t.ns, N = ns + 1;
+    extern __shared__ double gsmem[];
+    const long long slot = blockIdx.x;
+    if (slot >= S) return;
+    const int lane = threadIdx.x;
+    const int ns = t.ns, N = ns + 1, NP = gnp(N);
+    double *Mx = wsbase + (size_t)slot * NP * N;
+    const GLds L = glds_map(gsmem, ns, t.ntb);
     const bool adapt = a.L_forced < 0;
     const int Lc = adapt ? a.L_max : a.L_forced;
     const unsigned long long end = 1ull << Lc;
     for (;;) {
-        const unsigned long long gi = atomicAdd(a.counter, 1ull);
+        unsigned long long gi = 0;
+        if (lane == 0) gi = atomicAdd(a.counter, 1ull);
+        gi = __shfl(gi, 0);
         if (gi >= (unsigned long long)a.total) break;
         int j = 0;
         while (j + 1 < a.nspan && (unsigned long long)a.span[j + 1].start <= gi) ++j;
@@ -394,19 +427,27 @@ __global__ void __launch_bounds__(64) global_kernel(WaveTables t, AdvanceArgs a,
         const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
         const long long ld = a.span[j].n;
         const double rho = ar.rho[cell], e0 = ar.e0[cell];
-        double chk = rho - rho + e0 - e0 + dt - dt;
-        for (int s = 0; s < N; ++s) {
-            const double v = (s < ns) ? ar.Y[(size_t)s * ld + cell] : ar.T[cell];
-            w.x[(size_t)s * w.S + sl] = v;
-            w.xk[(size_t)s * w.S + sl] = v;
-            chk += v - v;
+        double x[RW], xk[RW];
+        bool fin = true;
+#pragma unroll
+        for (int m = 0; m < RW; ++m) {
+            const int i = lane + 64 * m;
+            x[m] = 0.0;
+            if (i < ns) x[m] = ar.Y[(size_t)i * ld + cell];
+            else if (i == ns) x[m] = ar.T[cell];
+            xk[m] = x[m];
+            fin = fin && __builtin_isfinite(x[m]);
         }
         const double T0 = ar.T[cell];
-        if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || T0 < gTmin || T0 > gTmax) {
-            ar.status[cell] = 3;
-            ar.level[cell] = 0;
-            ar.iters[cell] = 0;
-            ar.sched[cell] = 0xcbf29ce484222325ull;
+        const bool bad = __any(!fin) || !__builtin_isfinite(rho) || !(rho > 0.0) || !__builtin_isfinite(e0) ||
+                         !__builtin_isfinite(dt) || !(dt >= 0.0) || T0 < gTmin || T0 > gTmax;
+        if (bad) {
+            if (lane == 0) {
+                ar.status[cell] = 3;
+                ar.level[cell] = 0;
+                ar.iters[cell] = 0;
+                ar.sched[cell] = 0xcbf29ce484222325ull;
+            }
             continue;
         }
         unsigned long long tt = 0, hsh = 0xcbf29ce484222325ull;
@@ -417,18 +458,103 @@ __global__ void __launch_bounds__(64) global_kernel(WaveTables t, AdvanceArgs a,
             if (k == 0 && iters >= a.max_iters) { st = 2; break; }
             ++iters;
             if (k == 0) r_prev = -1.0;
-            int outcome = gnewton<F32>(t, a, w, sl, rho, e0, ldexp(dt, -l), r_prev);
+            const double h = ldexp(dt, -l);
+            // one Newton iteration
+            int outcome = G_CONTINUE;
+            double f[RW], bv[RW];
+            gw_eval<RW>(t, L, Mx, lane, rho, xk, f);
+            double chk = 0.0;
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int i = lane + 64 * m;
+                bv[m] = 0.0;
+                if (i < N) {
+                    bv[m] = -((xk[m] - x[m]) - h * f[m]);
+                    chk += bv[m] - bv[m];
+                }
+            }
+            double rmax[RW];
+#pragma unroll
+            for (int m = 0; m < RW; ++m) rmax[m] = 0.0;
+            for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+                for (int m = 0; m < RW; ++m) {
+                    const int i = lane + 64 * m;
+                    if (i < N) {
+                        double *e = gm(Mx, NP, i, jc);
+                        const double v = (i == jc ? 1.0 : 0.0) - h * *e;
+                        *e = v;
+                        chk += v - v;
+                        rmax[m] = fmax(rmax[m], fabs(v));
+                    }
+                }
+            if (F32) {  // row equilibration before the FP32 factorisation
+#pragma unroll
+                for (int m = 0; m < RW; ++m) rmax[m] = (lane + 64 * m < N) ? 1.0 / rmax[m] : 1.0;
+                for (int jc = 0; jc < N; ++jc)
+#pragma unroll
+                    for (int m = 0; m < RW; ++m)
+                        if (lane + 64 * m < N) *gm(Mx, NP, lane + 64 * m, jc) *= rmax[m];
+#pragma unroll
+                for (int m = 0; m < RW; ++m) bv[m] *= rmax[m];
+            }
+            if (__any(!(chk == 0.0))) {
+                outcome = G_FAILED;
+            } else if (!gw_solve<F32, RW>(L, Mx, lane, N, bv)) {
+                outcome = G_FAILED;
+            } else {
+                bool conv = true, finx = true;
+                double r = 0.0;
+#pragma unroll
+                for (int m = 0; m < RW; ++m) {
+                    const int i = lane + 64 * m;
+                    if (i < N) {
+                        xk[m] += bv[m];
+                        finx = finx && __builtin_isfinite(xk[m]);
+                        const double atol = (i < ns) ? a.atol_Y : a.atol_T;
+                        conv = conv && (fabs(bv[m]) <= atol + a.rtol * fabs(xk[m]));
+                        r = fmax(r, fabs(bv[m]) / (atol + a.rtol * fabs(xk[m])));
+                    }
+                }
+                const double Tk = rdlane(pick<RW>(xk, ns >> 6), ns & 63);
+                const bool allconv = __all(conv);
+                if (__any(!finx) || Tk < gTmin || Tk > gTmax) {
+                    outcome = G_FAILED;
+                } else if (!allconv && !a.point_implicit) {
+                    const double rw = wave_max(r);
+                    if (a.diverge_ratio > 0.0 && r_prev >= 0.0 && rw > a.diverge_ratio * r_prev) outcome = G_FAILED;
+                    else { if (a.diverge_ratio > 0.0) r_prev = rw; outcome = G_CONTINUE; }
+                } else {
+                    bool neg = false;
+#pragma unroll
+                    for (int m = 0; m < RW; ++m)
+                        if (lane + 64 * m < ns) neg = neg || xk[m] < -a.y_neg;
+                    double Tn;
+                    if (!a.point_implicit && __any(neg)) {
+                        outcome = G_FAILED;
+                    } else if (!gw_invert_T<RW>(t, lane, xk, e0, Tk, Tn)) {
+                        outcome = G_FAILED;
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < RW; ++m)
+                            if (lane + 64 * m == ns) xk[m] = Tn;
+                        outcome = G_ACCEPTED;
+                    }
+                }
+            }
             if (outcome == G_CONTINUE && ++k >= a.k_max) outcome = G_FAILED;
             if (outcome == G_CONTINUE) continue;
             hsh = (hsh ^ (unsigned long long)(2 * l + (outcome == G_ACCEPTED ? 1 : 0))) * 0x100000001b3ull;
             k = 0;
             if (outcome == G_ACCEPTED) {
-                for (int s = 0; s < N; ++s) w.x[(size_t)s * w.S + sl] = w.xk[(size_t)s * w.S + sl];
+#pragma unroll
+                for (int m = 0; m < RW; ++m) x[m] = xk[m];
                 tt += 1ull << (Lc - l);
                 if (adapt && l > 0 && (tt & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
                 if (tt >= end) st = failed ? 1 : 0;
             } else {
-                for (int s = 0; s < N; ++s) w.xk[(size_t)s * w.S + sl] = w.x[(size_t)s * w.S + sl];
+#pragma unroll
+                for (int m = 0; m < RW; ++m) xk[m] = x[m];
                 if (!adapt) {
                     st = 2;
                 } else {
@@ -440,34 +566,53 @@ __global__ void __launch_bounds__(64) global_kernel(WaveTables t, AdvanceArgs a,
             }
         }
         if (st < 2) {
-            for (int s = 0; s < ns; ++s) ar.Y[(size_t)s * ld + cell] = w.x[(size_t)s * w.S + sl];
-            ar.T[cell] = w.x[(size_t)ns * w.S + sl];
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int i = lane + 64 * m;
+                if (i < ns) ar.Y[(size_t)i * ld + cell] = x[m];
+                else if (i == ns) ar.T[cell] = x[m];
+            }
         }
-        ar.status[cell] = st;
-        ar.level[cell] = level;
-        ar.iters[cell] = iters;
-        ar.sched[cell] = hsh;
+        if (lane == 0) {
+            ar.status[cell] = st;
+            ar.level[cell] = level;
+            ar.iters[cell] = iters;
+            ar.sched[cell] = hsh;
+        }
     }
 }
-
 }  // namespace
 
 size_t global_work_doubles_per_slot(int ns, int ntb)
 {
-    const size_t N = (size_t)ns + 1;
-    return N * N + 3 * N + 3 * (size_t)ns + (size_t)(ntb > 0 ? ntb : 1);
+    (void)ntb;
+    const size_t N = (size_t)ns + 1, NP = (N + 63) & ~(size_t)63;
+    return NP * N;
 }
 
 hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool f32, double *work, long long slots,
                          hipStream_t s)
 {
     if (slots <= 0) return hipSuccess;
-    const int block = 64;
-    const long long grid = (slots + block - 1) / block;
-    if (f32)
-        hipLaunchKernelGGL((global_kernel<true>), dim3((unsigned)grid), dim3(block), 0, s, t, a, work, slots);
-    else
-        hipLaunchKernelGGL((global_kernel<false>), dim3((unsigned)grid), dim3(block), 0, s, t, a, work, slots);
+    if (slots > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * glds_doubles(t.ns, t.ntb);
+    if (lds > 65536) return hipErrorInvalidConfiguration;
+#define KIN_GW(RWV)                                                                                  \
+    case RWV:                                                                                        \
+        if (f32)                                                                                     \
+            hipLaunchKernelGGL((gwave_kernel<true, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots); \
+        else                                                                                         \
+            hipLaunchKernelGGL((gwave_kernel<false, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots); \
+        break;
+    switch ((t.ns + 1 + 63) / 64) {
+        KIN_GW(1)
+        KIN_GW(2)
+        KIN_GW(3)
+        KIN_GW(4)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef KIN_GW
     return hipGetLastError();
 }
 

@@ -790,10 +790,11 @@ constexpr size_t kGlobalWorkBytes = size_t(16) << 30;
 
 static long long global_slots(const Mech &m, long long total)
 {
+    // one wavefront per slot; more slots than wavefronts resident on the device only queue
     const size_t per = sizeof(double) * global_work_doubles_per_slot(m.h.ns, m.tab.ntb);
-    long long cap = (long long)(kGlobalWorkBytes / per) / 64 * 64;
-    if (cap < 64) cap = 64;
-    return std::min((total + 63) / 64 * 64, cap);
+    long long cap = std::min<long long>((long long)(kGlobalWorkBytes / per), 16384);
+    if (cap < 1) cap = 1;
+    return std::min(std::max(total, 1LL), cap);
 }
 
 static size_t global_work_doubles(const Mech &m, long long total)
