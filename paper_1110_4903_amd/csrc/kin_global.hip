@@ -2,10 +2,12 @@
 // species (up to 255).  The paper's first kinetics kernel (Sec. 4.2) keeps each cell's whole
 // Jacobian in global memory with one thread per cell; here a cell gets a whole wavefront, and
 // its matrix sits in global memory column-major, so that one column of one cell is one
-// coalesced access and the wavefront's 64 lanes share each elimination step.  Every trailing
-// element is read and written once per pivot step, which makes the layout bound by HBM
-// bandwidth.  The matrices of a launch live in a workspace of slots, one per wavefront; a
-// wavefront that finishes its cell takes the next from the work counter.
+// coalesced access and the wavefront's 64 lanes share each elimination step.  The Jacobian
+// is assembled by atomic adds, completed and turned into the Newton matrix in one pass over
+// its columns, and factored by a blocked elimination that reads and writes each trailing
+// column once per panel of pivot steps.  The matrices of a launch live in a workspace of
+// slots, one per wavefront; a wavefront that finishes its cell takes the next from the work
+// counter.
 //
 // Method as in the other layouts: Newton iterations on backward Euler in x = (Y, T) for a
 // constant-(rho, e) cell, (I - hJ) dx = -G, dyadic sub-step halving on failure (Sec. 3.2,
@@ -50,14 +52,21 @@ __device__ __forceinline__ void gpow(double c, int nu, double &p, double &dp)
 enum { G_CONTINUE = 0, G_ACCEPTED = 1, G_FAILED = 2 };
 
 // ==== one wavefront per cell ======================================================================
-// The cell's matrix sits in global memory column-major with column stride NP = N rounded up to
-// 64, so that one column of one cell is one coalesced access of its wavefront.  Lane l owns
-// rows (and unknowns) l, l + 64, l + 128, l + 192 (at most RW per lane).  Species vectors
-// and the pivot row are staged in LDS; rows stay in place during the elimination (a row's
-// current position is `pos`, as in the wave layout), so a step reads and writes every
-// trailing element once and reads the pivot row once.
+// The cell's system is padded to NQ = N rounded up to 8 unknowns with identity rows and
+// columns, which leave the first N unknowns' solution unchanged and let elimination panels
+// and column batches divide the system exactly.  The matrix sits in global memory
+// column-major with column stride NP = NQ + 1 rounded up to 64, so that one column of one
+// cell is one coalesced access of its wavefront.  Lane l owns rows (and unknowns) l, l + 64,
+// l + 128, l + 192 (at most RW per lane).  Row NP - 1 is a spare row: a lane with nothing to
+// load or store in a column addresses it instead of branching around the access, which keeps
+// every access unconditional so that loads issued ahead of their use are not waited on early.
+// Rows stay in place during the elimination (a row's current position is `pos`, as in the
+// wave layout).
 
-__device__ __forceinline__ int gnp(int N) { return (N + 63) & ~63; }
+constexpr int kGC = 4;                                   // columns per batch
+
+__host__ __device__ inline int gnq(int N) { return (N + 7) & ~7; }
+__host__ __device__ inline int gnp(int N) { return (gnq(N) + 1 + 63) & ~63; }
 
 // element (row i, column j) of the slot's matrix
 __device__ __forceinline__ double *gm(double *M, int NP, int i, int j) { return M + (size_t)j * NP + i; }
@@ -74,24 +83,28 @@ __device__ __forceinline__ T pick(const T (&v)[RW], int m)
 }
 
 struct GLds {
-    double *c, *g, *hh, *W, *Mc, *prow;
+    double *c, *g, *hh, *W, *Mc, *tq, *cb;
 };
 
-// LDS doubles per wavefront: c, g, hh (ns each), W and the pivot row (N each), the [M] slots
+// LDS doubles per wavefront: c, g, hh (ns each), W (N), the [M] slots (ntb), and per column
+// of a batch the third-body slot terms (ntb) and row sums (N)
 __host__ __device__ inline size_t glds_doubles(int ns, int ntb)
 {
-    return 3 * (size_t)ns + 2 * ((size_t)ns + 1) + (size_t)(ntb > 0 ? ntb : 1);
+    const size_t N = (size_t)ns + 1, nb = (size_t)(ntb > 0 ? ntb : 1);
+    return 3 * (size_t)ns + N + nb + kGC * (nb + N);
 }
 
 __device__ __forceinline__ GLds glds_map(double *p, int ns, int ntb)
 {
+    const int nb = ntb > 0 ? ntb : 1;
     GLds L;
     L.c = p; p += ns;
     L.g = p; p += ns;
     L.hh = p; p += ns;
     L.W = p; p += ns + 1;
-    L.prow = p; p += ns + 1;
-    L.Mc = p;
+    L.Mc = p; p += nb;
+    L.tq = p; p += kGC * nb;
+    L.cb = p;
     return L;
 }
 
@@ -145,12 +158,15 @@ __device__ bool gw_invert_T(const WaveTables &t, int lane, const double (&x)[RW]
     return true;
 }
 
-// f (lane l: f of unknowns l + 64 m, into f[]) and the Jacobian into the slot's matrix, at xk.
+// The Newton system at xk for a sub-step of size h: f (lane l: f of unknowns l + 64 m, into
+// f[]) and the matrix I - hJ of the padded system into the slot's matrix.  rs[] returns the
+// reciprocal row maxima of the lane's rows (1 for padding rows); chk accumulates v - v over
+// the matrix entries (non-zero when one is not finite).
 template <int RW>
-__device__ void gw_eval(const WaveTables &t, const GLds &L, double *Mx, int lane, double rho,
-                        const double (&xk)[RW], double (&f)[RW])
+__device__ void gw_system(const WaveTables &t, const GLds &L, double *Mx, int lane, double rho, double h,
+                          const double (&xk)[RW], double (&f)[RW], double (&rs)[RW], double &chk)
 {
-    const int ns = t.ns, N = ns + 1, NP = gnp(N);
+    const int ns = t.ns, N = ns + 1, NQ = gnq(N), NP = gnp(N);
     const double T = rdlane(pick<RW>(xk, ns >> 6), ns & 63);
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
@@ -172,15 +188,24 @@ __device__ void gw_eval(const WaveTables &t, const GLds &L, double *Mx, int lane
         }
         if (s < N) L.W[s] = 0.0;
     }
+    // the Jacobian's columns are cleared for every row a lane owns
     for (int j = 0; j < N; ++j)
 #pragma unroll
-        for (int m = 0; m < RW; ++m)
-            if (lane + 64 * m < N) *gm(Mx, NP, lane + 64 * m, j) = 0.0;
+        for (int m = 0; m < RW; ++m) *gm(Mx, NP, lane + 64 * m, j) = 0.0;
+    for (int q = lane; q < kGC * N; q += 64) L.cb[q] = 0.0;
     wave_sync();
+    // [M] of each third-body slot; four independent partial sums keep loads in flight
     for (int q = lane; q < t.ntb; q += 64) {
-        double acc = 0.0;
-        for (int s = 0; s < ns; ++s) acc = fma(t.effT[(size_t)s * t.ntb + q], L.c[s], acc);
-        L.Mc[q] = acc;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        int s = 0;
+        for (; s + 4 <= ns; s += 4) {
+            acc0 = fma(t.effT[(size_t)s * t.ntb + q], L.c[s], acc0);
+            acc1 = fma(t.effT[(size_t)(s + 1) * t.ntb + q], L.c[s + 1], acc1);
+            acc2 = fma(t.effT[(size_t)(s + 2) * t.ntb + q], L.c[s + 2], acc2);
+            acc3 = fma(t.effT[(size_t)(s + 3) * t.ntb + q], L.c[s + 3], acc3);
+        }
+        for (; s < ns; ++s) acc0 = fma(t.effT[(size_t)s * t.ntb + q], L.c[s], acc0);
+        L.Mc[q] = (acc0 + acc1) + (acc2 + acc3);
     }
     // the zeroing stores complete before the atomic adds
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -245,44 +270,16 @@ __device__ void gw_eval(const WaveTables &t, const GLds &L, double *Mx, int lane
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     wave_sync();
-    // dense third-body terms, entries sorted by row: lane k sums a row's entries for its
-    // columns in registers and adds each sum once
-    {
-        int cur = t.ntbe > 0 ? (t.tbe[0] >> 16) : 0;
-        double acc[RW];
-#pragma unroll
-        for (int m = 0; m < RW; ++m) acc[m] = 0.0;
-        for (int e = 0; e < t.ntbe; ++e) {
-            const int ent = t.tbe[e];
-            const int row = ent >> 16;
-            if (row != cur) {
-#pragma unroll
-                for (int m = 0; m < RW; ++m)
-                    if (lane + 64 * m < ns) { *gm(Mx, NP, cur, lane + 64 * m) += acc[m]; acc[m] = 0.0; }
-                cur = row;
-            }
-            const double D = L.Mc[ent & 0xffff];
-            const double *er = t.effR + (size_t)e * ns;
-#pragma unroll
-            for (int m = 0; m < RW; ++m)
-                if (lane + 64 * m < ns) acc[m] = fma(D, er[lane + 64 * m], acc[m]);
-        }
-        if (t.ntbe > 0)
-#pragma unroll
-            for (int m = 0; m < RW; ++m)
-                if (lane + 64 * m < ns) *gm(Mx, NP, cur, lane + 64 * m) += acc[m];
-    }
-    // species rows of f and the temperature column; e_s and c_v,s replace g and h
-    double de = 0.0, cv = 0.0, dcv = 0.0;
+    // species rows of f; c_v,s replaces h in LDS for the energy row
+    double de = 0.0, cv = 0.0, dcv = 0.0, msr[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) {
         const int s = lane + 64 * m;
         f[m] = 0.0;
+        msr[m] = 0.0;
         if (s < ns) {
-            const double ms = t.M[s] * irc;
-            f[m] = L.W[s] * ms;
-            *gm(Mx, NP, s, ns) *= ms;
-            L.g[s] = ek[m];
+            msr[m] = t.M[s] * irc;
+            f[m] = L.W[s] * msr[m];
             L.hh[s] = cvk[m];
             de = fma(ek[m], f[m], de);
             cv = fma(xk[m], cvk[m], cv);
@@ -293,108 +290,274 @@ __device__ void gw_eval(const WaveTables &t, const GLds &L, double *Mx, int lane
     dcv = gw_sum(dcv);
     de = gw_sum(de);
     const double fT = -de / cv, icv = 1.0 / cv;
-    wave_sync();
-    // energy row: J[ns][k] = -(sum_s e_s J[s][k] + f_T c_v,k) / c_v, one column per step
-    for (int k = 0; k <= ns; ++k) {
-        double part = 0.0;
-#pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int s = lane + 64 * m;
-            if (s < ns) {
-                part = fma(L.g[s], *gm(Mx, NP, s, k), part);
-                if (k == ns) part = fma(L.hh[s], f[m], part);
-            }
-        }
-        const double acc = gw_sum(part);
-        const double v = (k < ns) ? -fma(fT, L.hh[k], acc) * icv : -fma(fT, dcv, acc) * icv;
-        if (lane == 0) *gm(Mx, NP, ns, k) = v;
-    }
     if ((ns & 63) == lane) f[ns >> 6] = fT;
     wave_sync();
+    // One pass over the columns, kGC at a time: the dense third-body terms (slot terms of the
+    // batch's columns into LDS, then one lane per entry adds into its row's LDS sum), the
+    // temperature column's M_s / rho' factor, the energy row
+    //   J[ns][k] = -(sum_s e_s J[s][k] + f_T c_v,k) / c_v,
+    // and the Newton matrix I - hJ, padding rows and columns set to the identity.
+    double rmax[RW];
+#pragma unroll
+    for (int m = 0; m < RW; ++m) rmax[m] = 0.0;
+    for (int j = 0; j < NQ; j += kGC) {
+        double a[kGC][RW];
+#pragma unroll
+        for (int q = 0; q < kGC; ++q)
+#pragma unroll
+            for (int m = 0; m < RW; ++m) a[q][m] = *gm(Mx, NP, lane + 64 * m, min(j + q, N - 1));
+        if (t.ntb > 0 && j < ns) {
+#pragma unroll
+            for (int q = 0; q < kGC; ++q) {
+                const int col = min(j + q, ns - 1);
+                const double sc = (j + q < ns) ? 1.0 / t.M[col] : 0.0;
+                for (int p = lane; p < t.ntb; p += 64)
+                    L.tq[q * t.ntb + p] = L.Mc[p] * t.effT[(size_t)col * t.ntb + p] * sc;
+            }
+            wave_sync();
+            for (int e = lane; e < t.ntbe; e += 64) {
+                const int ent = t.tgs[e];
+                const int slot = ent & 0xffff, row = ent >> 16;
+                const double fr = t.tgf[e];
+#pragma unroll
+                for (int q = 0; q < kGC; ++q)
+                    __hip_atomic_fetch_add(L.cb + q * N + row, fr * L.tq[q * t.ntb + slot], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < kGC; ++q)
+#pragma unroll
+                for (int m = 0; m < RW; ++m) {
+                    const int i = lane + 64 * m;
+                    if (i < ns) {
+                        a[q][m] += L.cb[q * N + i];
+                        L.cb[q * N + i] = 0.0;
+                    }
+                }
+            wave_sync();
+        }
+        double ve[kGC];
+#pragma unroll
+        for (int q = 0; q < kGC; ++q) {
+            const int col = j + q;
+            double part = 0.0;
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int s = lane + 64 * m;
+                if (s < ns) {
+                    if (col == ns) a[q][m] *= msr[m];
+                    part = fma(ek[m], a[q][m], part);
+                    if (col == ns) part = fma(cvk[m], f[m], part);
+                }
+            }
+            const double acc = gw_sum(part);
+            const double cvc = (col < ns) ? L.hh[min(col, ns - 1)] : dcv;
+            ve[q] = -fma(fT, cvc, acc) * icv;
+        }
+#pragma unroll
+        for (int q = 0; q < kGC; ++q) {
+            const int col = j + q;
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int i = lane + 64 * m;
+                double v;
+                if (i < N && col < N) {
+                    const double jv = (i == ns) ? ve[q] : a[q][m];
+                    v = (i == col ? 1.0 : 0.0) - h * jv;
+                    chk += v - v;
+                    rmax[m] = fmax(rmax[m], fabs(v));
+                } else {
+                    v = (i == col && i < NQ) ? 1.0 : 0.0;
+                }
+                *gm(Mx, NP, i, col) = v;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < RW; ++m) rs[m] = (lane + 64 * m < N) ? 1.0 / rmax[m] : 1.0;
 }
 
-// Gaussian elimination with partial pivoting over the slot's matrix, rows in place; b[] holds
-// the right-hand side of the lane's rows and returns the update of its unknowns.
+// Load of an element as the factorisation's type, scaled by the row factor sc (FP32 form,
+// first panel only).
+template <bool F32>
+__device__ __forceinline__ typename std::conditional<F32, float, double>::type gld(const double *e, double sc)
+{
+    if constexpr (F32) return (float)(*e * sc);
+    else return *e;
+}
+
+// Gaussian elimination with partial pivoting over the padded system in the slot's matrix,
+// rows in place; b[] holds the right-hand side of the lane's rows (already scaled by rs[]
+// in the FP32 form, whose matrix rows are scaled by rs[] as the first panel reads them) and
+// returns the update of its unknowns.
+//
+// Blocked right-looking form: a panel of GB columns is loaded into registers and factored
+// there (pivot search, multipliers, updates of the panel's later columns), and the columns
+// to the right of the panel then receive the panel's GB updates in one pass, each column
+// read and written once per panel instead of once per pivot step.  Within such a column the
+// GB updates are applied in pivot order, the pivot row's current entry broadcast by readlane
+// before each, which is the same arithmetic as the unblocked order.  Columns move in batches
+// of kGC with the next batch's loads issued before the current batch is computed.  Rows
+// already pivoted take no part: their lanes address the spare row.
 template <bool F32, int RW>
-__device__ bool gw_solve(const GLds &L, double *Mx, int lane, int N, double (&b)[RW])
+__device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], double (&b)[RW])
 {
     using R = typename std::conditional<F32, float, double>::type;
-    const int NP = gnp(N);
+    constexpr int GB = RW <= 2 ? 8 : 4;                  // panel width (divides NQ)
+    constexpr int GC = kGC;
+    const int NQ = gnq(N), NP = gnp(N), SP = NP - 1;
     int pos[RW];
     double dg[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) { pos[m] = lane + 64 * m; dg[m] = 1.0; }
     bool ok = true;
-    for (int k = 0; k < N; ++k) {
-        // the lane's best candidate row in column k: largest |a|, ties to the lowest position
-        double v[RW];
-        R best = R(-1);
-        int bpos = 0x7fffffff, bm = 0;
+    for (int k0 = 0; k0 < NQ; k0 += GB) {
+        // rows not yet pivoted: the only rows this panel changes
+        bool act[RW];
+        int ri[RW];
+        double sc[RW];
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int i = lane + 64 * m;
-            v[m] = 0.0;
-            if (i < N) {
-                v[m] = *gm(Mx, NP, i, k);
-                const R a = (R)fabs((R)v[m]);
-                if (pos[m] >= k && (a > best || (a == best && pos[m] < bpos))) { best = a; bpos = pos[m]; bm = m; }
-            }
+            act[m] = i < NQ && pos[m] >= k0;
+            ri[m] = act[m] ? i : SP;
+            sc[m] = (k0 == 0) ? rs[m] : 1.0;
         }
-        const bool cand = bpos != 0x7fffffff;
-        const int w = pivot_lane<R>(cand ? best : R(0), cand, cand ? bpos : 0x7fffffff);
-        const int mw = rdlane(bm, w);
-        const int p = w + 64 * mw;                       // physical pivot row
-        const int pos_p = rdlane(pick<RW>(pos, mw), w);
-        const double piv_d = rdlane(pick<RW>(v, mw), w);
-        const R piv = (R)piv_d;
-        if (piv == R(0)) ok = false;
-        const double yk = rdlane(pick<RW>(b, mw), w);
+        R P[GB][RW];
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int i = lane + 64 * m;
-            const bool isp = i == p;
-            dg[m] = isp ? piv_d : dg[m];
-            pos[m] = isp ? k : (pos[m] == k ? pos_p : pos[m]);
-        }
-        // the pivot row's trailing part into LDS
-        for (int j = k + 1 + lane; j < N; j += 64) L.prow[j] = *gm(Mx, NP, p, j);
-        wave_sync();
-        R l[RW];
+        for (int c = 0; c < GB; ++c)
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            l[m] = (lane + 64 * m < N && pos[m] > k) ? (R)v[m] / piv : R(0);
-            b[m] = (double)fma(-l[m], (R)yk, (R)b[m]);
-        }
-        for (int j = k + 1; j < N; ++j) {
-            const R pj = (R)L.prow[j];
+            for (int m = 0; m < RW; ++m) P[c][m] = gld<F32>(gm(Mx, NP, ri[m], k0 + c), sc[m]);
+        R Lp[GB][RW];
+        int wv[GB], mwv[GB];
+#pragma unroll
+        for (int c = 0; c < GB; ++c) {
+            const int k = k0 + c;
+            // the lane's best candidate row in column k: largest |a|, ties to the lowest position
+            R best = R(-1);
+            int bpos = 0x7fffffff, bm = 0;
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
-                if (l[m] != R(0)) {
-                    double *e = gm(Mx, NP, lane + 64 * m, j);
-                    *e = (double)fma(-l[m], pj, (R)*e);
+                const R av = (R)fabs(P[c][m]);
+                if (act[m] && pos[m] >= k && (av > best || (av == best && pos[m] < bpos))) {
+                    best = av; bpos = pos[m]; bm = m;
                 }
             }
+            const bool cand = bpos != 0x7fffffff;
+            const int w = pivot_lane<R>(cand ? best : R(0), cand, cand ? bpos : 0x7fffffff);
+            const int mw = rdlane(bm, w);
+            const int p = w + 64 * mw;                   // physical pivot row
+            const int pos_p = rdlane(pick<RW>(pos, mw), w);
+            const R piv = rdlane(pick<RW>(P[c], mw), w);
+            if (piv == R(0)) ok = false;
+            const double yk = rdlane(pick<RW>(b, mw), w);
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int i = lane + 64 * m;
+                const bool isp = i == p;
+                dg[m] = isp ? (double)piv : dg[m];
+                pos[m] = isp ? k : (pos[m] == k ? pos_p : pos[m]);
+            }
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                Lp[c][m] = (act[m] && pos[m] > k) ? P[c][m] / piv : R(0);
+                b[m] = (double)fma(-Lp[c][m], (R)yk, (R)b[m]);
+            }
+#pragma unroll
+            for (int c2 = c + 1; c2 < GB; ++c2) {
+                const R u = rdlane(pick<RW>(P[c2], mw), w);
+#pragma unroll
+                for (int m = 0; m < RW; ++m) P[c2][m] = fma(-Lp[c][m], u, P[c2][m]);
+            }
+            wv[c] = w;
+            mwv[c] = mw;
         }
-        wave_sync();
+        // the panel back: the rows pivoted here keep their U entries for back substitution
+#pragma unroll
+        for (int c = 0; c < GB; ++c)
+#pragma unroll
+            for (int m = 0; m < RW; ++m) *gm(Mx, NP, ri[m], k0 + c) = (double)P[c][m];
+        // columns right of the panel: the panel's GB updates per column
+        const int j0 = k0 + GB;
+        R nx[GC][RW];
+#pragma unroll
+        for (int q = 0; q < GC; ++q)
+#pragma unroll
+            for (int m = 0; m < RW; ++m) nx[q][m] = gld<F32>(gm(Mx, NP, ri[m], min(j0 + q, NQ - 1)), sc[m]);
+        for (int j = j0; j < NQ; j += GC) {
+            R cu[GC][RW];
+#pragma unroll
+            for (int q = 0; q < GC; ++q)
+#pragma unroll
+                for (int m = 0; m < RW; ++m) cu[q][m] = nx[q][m];
+#pragma unroll
+            for (int q = 0; q < GC; ++q)
+#pragma unroll
+                for (int m = 0; m < RW; ++m)
+                    nx[q][m] = gld<F32>(gm(Mx, NP, ri[m], min(j + GC + q, NQ - 1)), sc[m]);
+#pragma unroll
+            for (int c = 0; c < GB; ++c)
+#pragma unroll
+                for (int q = 0; q < GC; ++q) {
+                    const R u = rdlane(pick<RW>(cu[q], mwv[c]), wv[c]);
+#pragma unroll
+                    for (int m = 0; m < RW; ++m) cu[q][m] = fma(-Lp[c][m], u, cu[q][m]);
+                }
+#pragma unroll
+            for (int q = 0; q < GC; ++q)
+#pragma unroll
+                for (int m = 0; m < RW; ++m) *gm(Mx, NP, ri[m], j + q) = (double)cu[q][m];
+        }
     }
-    // back substitution by columns: the row at position k gives x_k, which every row above
-    // it removes from its right-hand side
+    // back substitution by columns over the first N positions (the padding unknowns are
+    // zero): the row at position k gives x_k, which every row above it removes from its
+    // right-hand side; a batch's column entries are loaded one batch ahead
     double xl[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) xl[m] = 0.0;
-    for (int k = N - 1; k >= 0; --k) {
-        int o = -1, om = 0;
+    R ux[GC][RW];
+#pragma unroll
+    for (int q = 0; q < GC; ++q)
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
-            const unsigned long long bal = __ballot(lane + 64 * m < N && pos[m] == k);
-            if (bal) { o = __builtin_ctzll(bal); om = m; }
+            const int k = N - 1 - q, i = lane + 64 * m;
+            const bool need = k >= 0 && i < N && pos[m] < k;
+            const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
+            ux[q][m] = need ? v : R(0);
         }
-        const double xk = (double)((R)rdlane(pick<RW>(b, om), o) / (R)rdlane(pick<RW>(dg, om), o));
+    for (int kt = N - 1; kt >= 0; kt -= GC) {
+        R uc[GC][RW];
 #pragma unroll
-        for (int m = 0; m < RW; ++m) {
-            const int i = lane + 64 * m;
-            if (i == k) xl[m] = xk;
-            if (i < N && pos[m] < k) b[m] = (double)fma(-(R)*gm(Mx, NP, i, k), (R)xk, (R)b[m]);
+        for (int q = 0; q < GC; ++q)
+#pragma unroll
+            for (int m = 0; m < RW; ++m) uc[q][m] = ux[q][m];
+#pragma unroll
+        for (int q = 0; q < GC; ++q)
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int k = kt - GC - q, i = lane + 64 * m;
+                const bool need = k >= 0 && i < N && pos[m] < k;
+                const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
+                ux[q][m] = need ? v : R(0);
+            }
+#pragma unroll
+        for (int q = 0; q < GC; ++q) {
+            const int k = kt - q;
+            if (k < 0) continue;
+            int o = -1, om = 0;
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const unsigned long long bal = __ballot(lane + 64 * m < N && pos[m] == k);
+                if (bal) { o = __builtin_ctzll(bal); om = m; }
+            }
+            const double xk = (double)((R)rdlane(pick<RW>(b, om), o) / (R)rdlane(pick<RW>(dg, om), o));
+#pragma unroll
+            for (int m = 0; m < RW; ++m) {
+                const int i = lane + 64 * m;
+                if (i == k) xl[m] = xk;
+                if (i < N && pos[m] < k) b[m] = (double)fma(-uc[q][m], (R)xk, (R)b[m]);
+            }
         }
     }
 #pragma unroll
@@ -410,7 +573,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
     if (slot >= S) return;
     const int lane = threadIdx.x;
     const int ns = t.ns, N = ns + 1, NP = gnp(N);
-    double *Mx = wsbase + (size_t)slot * NP * N;
+    double *Mx = wsbase + (size_t)slot * NP * gnq(N);
     const GLds L = glds_map(gsmem, ns, t.ntb);
     const bool adapt = a.L_forced < 0;
     const int Lc = adapt ? a.L_max : a.L_forced;
@@ -462,8 +625,8 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
             // one Newton iteration
             int outcome = G_CONTINUE;
             double f[RW], bv[RW];
-            gw_eval<RW>(t, L, Mx, lane, rho, xk, f);
-            double chk = 0.0;
+            double chk = 0.0, rs[RW];
+            gw_system<RW>(t, L, Mx, lane, rho, h, xk, f, rs, chk);
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
                 const int i = lane + 64 * m;
@@ -471,36 +634,12 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
                 if (i < N) {
                     bv[m] = -((xk[m] - x[m]) - h * f[m]);
                     chk += bv[m] - bv[m];
+                    if (F32) bv[m] *= rs[m];   // row equilibration of the FP32 factorisation
                 }
-            }
-            double rmax[RW];
-#pragma unroll
-            for (int m = 0; m < RW; ++m) rmax[m] = 0.0;
-            for (int jc = 0; jc < N; ++jc)
-#pragma unroll
-                for (int m = 0; m < RW; ++m) {
-                    const int i = lane + 64 * m;
-                    if (i < N) {
-                        double *e = gm(Mx, NP, i, jc);
-                        const double v = (i == jc ? 1.0 : 0.0) - h * *e;
-                        *e = v;
-                        chk += v - v;
-                        rmax[m] = fmax(rmax[m], fabs(v));
-                    }
-                }
-            if (F32) {  // row equilibration before the FP32 factorisation
-#pragma unroll
-                for (int m = 0; m < RW; ++m) rmax[m] = (lane + 64 * m < N) ? 1.0 / rmax[m] : 1.0;
-                for (int jc = 0; jc < N; ++jc)
-#pragma unroll
-                    for (int m = 0; m < RW; ++m)
-                        if (lane + 64 * m < N) *gm(Mx, NP, lane + 64 * m, jc) *= rmax[m];
-#pragma unroll
-                for (int m = 0; m < RW; ++m) bv[m] *= rmax[m];
             }
             if (__any(!(chk == 0.0))) {
                 outcome = G_FAILED;
-            } else if (!gw_solve<F32, RW>(L, Mx, lane, N, bv)) {
+            } else if (!gw_solve<F32, RW>(Mx, lane, N, rs, bv)) {
                 outcome = G_FAILED;
             } else {
                 bool conv = true, finx = true;
@@ -586,8 +725,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
 size_t global_work_doubles_per_slot(int ns, int ntb)
 {
     (void)ntb;
-    const size_t N = (size_t)ns + 1, NP = (N + 63) & ~(size_t)63;
-    return NP * N;
+    return (size_t)gnp(ns + 1) * (size_t)gnq(ns + 1);
 }
 
 hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool f32, double *work, long long slots,
@@ -604,7 +742,7 @@ hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool f32, do
         else                                                                                         \
             hipLaunchKernelGGL((gwave_kernel<false, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots); \
         break;
-    switch ((t.ns + 1 + 63) / 64) {
+    switch ((gnq(t.ns + 1) + 63) / 64) {
         KIN_GW(1)
         KIN_GW(2)
         KIN_GW(3)

@@ -109,6 +109,8 @@ struct WaveTables {
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
     const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
     const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
+    const int *tgs;         // [ntbe] the same entries ordered by slot: slot | row << 16
+    const double *tgf;      // [ntbe] row factor nu_rs M_s of each tgs entry
     const int *chunk_rp;    // [nchunk] largest reactant count | largest product count << 8, per
                             // pass of 64 reactions
 };

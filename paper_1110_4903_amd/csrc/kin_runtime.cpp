@@ -360,6 +360,22 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     const int ntbe = (int)tbe.size();
     if (tbe.empty()) tbe.push_back(0);
     if (effR.empty()) effR.push_back(0.0);
+    // the same entries ordered by slot, with their row factors (global-memory layout: one
+    // pass of lanes over entries adds into distinct rows)
+    std::vector<int> tgs;
+    std::vector<double> tgf;
+    for (int r = 0; r < nr; ++r) {
+        const int q = slot[r];
+        if (q < 0) continue;
+        const Rxn &x = h.rx[r];
+        for (int s = 0; s < ns; ++s)
+            for (int j = 0; j < x.npart; ++j) {
+                if (!x.part[j].nu || x.part[j].sp != s) continue;
+                tgs.push_back(q | (s << 16));
+                tgf.push_back((double)x.part[j].nu * h.M[s]);
+            }
+    }
+    if (tgs.empty()) { tgs.push_back(0); tgf.push_back(0.0); }
     // one allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pc = {
@@ -368,7 +384,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
         {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0},
-        {ef.data(), sizeof(double) * ns, 0}};
+        {ef.data(), sizeof(double) * ns, 0}, {tgs.data(), sizeof(int) * tgs.size(), 0},
+        {tgf.data(), sizeof(double) * tgf.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -391,6 +408,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
     t.chunk_rp = reinterpret_cast<const int *>(b + pc[9].off);
     t.ef = reinterpret_cast<const double *>(b + pc[10].off);
+    t.tgs = reinterpret_cast<const int *>(b + pc[11].off);
+    t.tgf = reinterpret_cast<const double *>(b + pc[12].off);
     return KIN_OK;
 }
 

@@ -65,29 +65,30 @@ def global_tier_bytes(mech) -> dict:
     """Algorithmic memory traffic (bytes) of one Newton iteration of one cell when the cell's
     (Ns+1)^2 matrix lives in global memory (the paper's first kinetics kernel, Sec. 4.2), by
     phase.  Every element the method touches is counted once per pass that touches it: the
-    Jacobian is cleared (write), assembled by read-modify-write of each nonzero contribution,
-    closed by the energy row (reads of the species block), turned into I - hJ (read and
-    write), and eliminated: at pivot step k the search reads column k below the diagonal and
-    every trailing element is read and written once (the pivot row's reuse across rows is
-    not counted again).  The back substitution reads the upper triangle."""
+    Jacobian is cleared (write), assembled by read-modify-write of each nonzero reaction
+    contribution, completed in one pass over its columns (read and write: the dense
+    third-body terms and the energy row are formed on chip, the matrix becomes I - hJ), and
+    eliminated in panels of `panel` columns (8 up to 128 unknowns, else 4): a panel's columns
+    are read for the rows not yet pivoted and written back for the rows it pivots, and every
+    column right of the panel is read and written once per panel for the rows not yet
+    pivoted.  The back substitution reads the upper triangle.  Padding of the stored system
+    is not counted."""
     ns = mech.ns
     N = ns + 1
+    panel = 8 if N <= 128 else 4
     clear = 8 * N * N
     scatter = 0
     for r in range(mech.nr):
         parts = _parts(mech, r)
         n = sum(1 for v in parts.values() if v != 0)
         scatter += 16 * (n * n + 2 * n)            # J block, T column and production sums
-    tb = int((mech.tb >= 0).sum()) if hasattr(mech.tb, "__len__") else 0
-    dense_tb = 0
-    for r in range(mech.nr):
-        if mech.tb[r] >= 0:
-            dense_tb += 16 * ns * sum(1 for v in _parts(mech, r).values() if v != 0)
-    energy_row = 8 * ns * ns + 8 * N
-    newton = 16 * N * N
-    lu = sum(8 * (N - k) + 16 * (N - k - 1) ** 2 for k in range(N))
+    columns = 16 * N * N
+    lu = 0
+    for k0 in range(0, N, panel):
+        kb = min(panel, N - k0)
+        rows = N - k0
+        lu += 8 * kb * rows + 8 * kb * kb + 16 * (N - k0 - kb) * rows
     back = 8 * N * (N - 1) // 2 + 16 * N
-    out = dict(clear=clear, scatter=scatter, third_body=dense_tb + 8 * tb * ns, energy_row=energy_row,
-               newton_matrix=newton, elimination=lu, back_substitution=back)
+    out = dict(clear=clear, scatter=scatter, column_pass=columns, elimination=lu, back_substitution=back)
     out["total"] = sum(out.values())
     return out
