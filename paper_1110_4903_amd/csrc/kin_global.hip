@@ -83,20 +83,22 @@ __device__ __forceinline__ T pick(const T (&v)[RW], int m)
 }
 
 struct GLds {
-    double *c, *g, *hh, *W, *Mc, *tq, *cb;
+    double *c, *g, *hh, *W, *Mc, *tq, *cb, *tgf;
+    int *tgs;
 };
 
-// LDS doubles per wavefront: c, g, hh (ns each), W (N), the [M] slots (ntb), and per column
-// of a batch the third-body slot terms (ntb) and row sums (N)
-__host__ __device__ inline size_t glds_doubles(int ns, int ntb)
+// LDS doubles per wavefront: c, g, hh (ns each), W (N), the [M] slots (ntb), per column of a
+// batch the third-body slot terms (ntb) and row sums (N), and, when `staged` entries are
+// given (ntbe > 0), a copy of the slot-ordered third-body entries (factor and slot | row)
+__host__ __device__ inline size_t glds_doubles(int ns, int ntb, int staged)
 {
-    const size_t N = (size_t)ns + 1, nb = (size_t)(ntb > 0 ? ntb : 1);
-    return 3 * (size_t)ns + N + nb + kGC * (nb + N);
+    const size_t N = (size_t)ns + 1, nb = (size_t)(ntb > 0 ? ntb : 1), ne = (size_t)(staged > 0 ? staged : 0);
+    return 3 * (size_t)ns + N + nb + kGC * (nb + N) + ne + (ne + 1) / 2;
 }
 
-__device__ __forceinline__ GLds glds_map(double *p, int ns, int ntb)
+__device__ __forceinline__ GLds glds_map(double *p, int ns, int ntb, int ntbe)
 {
-    const int nb = ntb > 0 ? ntb : 1;
+    const int nb = ntb > 0 ? ntb : 1, ne = ntbe > 0 ? ntbe : 1;
     GLds L;
     L.c = p; p += ns;
     L.g = p; p += ns;
@@ -104,7 +106,9 @@ __device__ __forceinline__ GLds glds_map(double *p, int ns, int ntb)
     L.W = p; p += ns + 1;
     L.Mc = p; p += nb;
     L.tq = p; p += kGC * nb;
-    L.cb = p;
+    L.cb = p; p += kGC * (ns + 1);
+    L.tgf = p; p += ne;
+    L.tgs = reinterpret_cast<int *>(p);
     return L;
 }
 
@@ -163,8 +167,8 @@ __device__ bool gw_invert_T(const WaveTables &t, int lane, const double (&x)[RW]
 // reciprocal row maxima of the lane's rows (1 for padding rows); chk accumulates v - v over
 // the matrix entries (non-zero when one is not finite).
 template <int RW>
-__device__ void gw_system(const WaveTables &t, const GLds &L, double *Mx, int lane, double rho, double h,
-                          const double (&xk)[RW], double (&f)[RW], double (&rs)[RW], double &chk)
+__device__ void gw_system(const WaveTables &t, const GLds &L, bool staged, double *Mx, int lane, double rho,
+                          double h, const double (&xk)[RW], double (&f)[RW], double (&rs)[RW], double &chk)
 {
     const int ns = t.ns, N = ns + 1, NQ = gnq(N), NP = gnp(N);
     const double T = rdlane(pick<RW>(xk, ns >> 6), ns & 63);
@@ -307,23 +311,40 @@ __device__ void gw_system(const WaveTables &t, const GLds &L, double *Mx, int la
 #pragma unroll
             for (int m = 0; m < RW; ++m) a[q][m] = *gm(Mx, NP, lane + 64 * m, min(j + q, N - 1));
         if (t.ntb > 0 && j < ns) {
+            // slot terms D_q eff_q,k / M_k of the batch's columns (zero past the species); a
+            // batch's table loads are all issued before any is used
+            for (int p0 = 0; p0 < t.ntb; p0 += 128) {
+                const int pa = min(p0 + lane, t.ntb - 1), pb = min(p0 + 64 + lane, t.ntb - 1);
+                double ea[kGC], eb[kGC];
 #pragma unroll
-            for (int q = 0; q < kGC; ++q) {
-                const int col = min(j + q, ns - 1);
-                const double sc = (j + q < ns) ? 1.0 / t.M[col] : 0.0;
-                for (int p = lane; p < t.ntb; p += 64)
-                    L.tq[q * t.ntb + p] = L.Mc[p] * t.effT[(size_t)col * t.ntb + p] * sc;
+                for (int q = 0; q < kGC; ++q) {
+                    const size_t row0 = (size_t)min(j + q, ns - 1) * t.ntb;
+                    ea[q] = t.effTM[row0 + pa];
+                    eb[q] = t.effTM[row0 + pb];
+                }
+                const double da = L.Mc[pa], db = L.Mc[pb];
+#pragma unroll
+                for (int q = 0; q < kGC; ++q) {
+                    const bool sp = j + q < ns;
+                    if (p0 + lane < t.ntb) L.tq[q * t.ntb + pa] = sp ? da * ea[q] : 0.0;
+                    if (p0 + 64 + lane < t.ntb) L.tq[q * t.ntb + pb] = sp ? db * eb[q] : 0.0;
+                }
             }
             wave_sync();
-            for (int e = lane; e < t.ntbe; e += 64) {
-                const int ent = t.tgs[e];
-                const int slot = ent & 0xffff, row = ent >> 16;
-                const double fr = t.tgf[e];
+            // one lane per entry adds its row's terms (entries of one slot have distinct rows)
+            auto entries = [&](const int *tgs, const double *tgf) {
+                for (int e = lane; e < t.ntbe; e += 64) {
+                    const int ent = tgs[e];
+                    const int slot = ent & 0xffff, row = ent >> 16;
+                    const double fr = tgf[e];
 #pragma unroll
-                for (int q = 0; q < kGC; ++q)
-                    __hip_atomic_fetch_add(L.cb + q * N + row, fr * L.tq[q * t.ntb + slot], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
-            }
+                    for (int q = 0; q < kGC; ++q)
+                        __hip_atomic_fetch_add(L.cb + q * N + row, fr * L.tq[q * t.ntb + slot], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            };
+            if (staged) entries(L.tgs, L.tgf);
+            else entries(t.tgs, t.tgf);
             wave_sync();
 #pragma unroll
             for (int q = 0; q < kGC; ++q)
@@ -566,7 +587,8 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 }
 
 template <bool F32, int RW>
-__global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, double *wsbase, long long S)
+__global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, double *wsbase, long long S,
+                                                   int staged)
 {
     extern __shared__ double gsmem[];
     const long long slot = blockIdx.x;
@@ -574,7 +596,15 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
     const int lane = threadIdx.x;
     const int ns = t.ns, N = ns + 1, NP = gnp(N);
     double *Mx = wsbase + (size_t)slot * NP * gnq(N);
-    const GLds L = glds_map(gsmem, ns, t.ntb);
+    const GLds L = glds_map(gsmem, ns, t.ntb, staged ? t.ntbe : 0);
+    // the slot-ordered third-body entries, read once per column batch, stay in LDS when they fit
+    if (staged) {
+        for (int e = lane; e < t.ntbe; e += 64) {
+            L.tgs[e] = t.tgs[e];
+            L.tgf[e] = t.tgf[e];
+        }
+    }
+    wave_sync();
     const bool adapt = a.L_forced < 0;
     const int Lc = adapt ? a.L_max : a.L_forced;
     const unsigned long long end = 1ull << Lc;
@@ -626,7 +656,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
             int outcome = G_CONTINUE;
             double f[RW], bv[RW];
             double chk = 0.0, rs[RW];
-            gw_system<RW>(t, L, Mx, lane, rho, h, xk, f, rs, chk);
+            gw_system<RW>(t, L, staged != 0, Mx, lane, rho, h, xk, f, rs, chk);
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
                 const int i = lane + 64 * m;
@@ -733,14 +763,20 @@ hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool f32, do
 {
     if (slots <= 0) return hipSuccess;
     if (slots > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * glds_doubles(t.ns, t.ntb);
+    // the third-body entries are staged in LDS when they fit in the 64 KiB of a workgroup
+    int staged = t.ntbe;
+    size_t lds = sizeof(double) * glds_doubles(t.ns, t.ntb, staged);
+    if (lds > 65536) {
+        staged = 0;
+        lds = sizeof(double) * glds_doubles(t.ns, t.ntb, 0);
+    }
     if (lds > 65536) return hipErrorInvalidConfiguration;
 #define KIN_GW(RWV)                                                                                  \
     case RWV:                                                                                        \
         if (f32)                                                                                     \
-            hipLaunchKernelGGL((gwave_kernel<true, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots); \
+            hipLaunchKernelGGL((gwave_kernel<true, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots, staged); \
         else                                                                                         \
-            hipLaunchKernelGGL((gwave_kernel<false, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots); \
+            hipLaunchKernelGGL((gwave_kernel<false, RWV>), dim3((unsigned)slots), dim3(64), lds, s, t, a, work, slots, staged); \
         break;
     switch ((gnq(t.ns + 1) + 63) / 64) {
         KIN_GW(1)

@@ -111,6 +111,7 @@ struct WaveTables {
     const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
     const int *tgs;         // [ntbe] the same entries ordered by slot: slot | row << 16
     const double *tgf;      // [ntbe] row factor nu_rs M_s of each tgs entry
+    const double *effTM;    // [ns][ntb] effT[k][q] / M_k
     const int *chunk_rp;    // [nchunk] largest reactant count | largest product count << 8, per
                             // pass of 64 reactions
 };

@@ -357,6 +357,9 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         if (q < 0) continue;
         for (int k = 0; k < ns; ++k) effT[(size_t)k * ntb + q] = h.eff[(size_t)slot_row[q] * ns + k];
     }
+    std::vector<double> effTM(effT);
+    for (int k = 0; k < ns; ++k)
+        for (int q = 0; q < ntb; ++q) effTM[(size_t)k * ntb + q] /= h.M[k];
     const int ntbe = (int)tbe.size();
     if (tbe.empty()) tbe.push_back(0);
     if (effR.empty()) effR.push_back(0.0);
@@ -385,7 +388,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
         {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0},
         {ef.data(), sizeof(double) * ns, 0}, {tgs.data(), sizeof(int) * tgs.size(), 0},
-        {tgf.data(), sizeof(double) * tgf.size(), 0}};
+        {tgf.data(), sizeof(double) * tgf.size(), 0}, {effTM.data(), sizeof(double) * effTM.size(), 0}};
     size_t total = 0;
     for (Piece &p : pc) { p.off = total; total = align256(total + p.bytes); }
     std::vector<char> host(total, 0);
@@ -410,6 +413,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.ef = reinterpret_cast<const double *>(b + pc[10].off);
     t.tgs = reinterpret_cast<const int *>(b + pc[11].off);
     t.tgf = reinterpret_cast<const double *>(b + pc[12].off);
+    t.effTM = reinterpret_cast<const double *>(b + pc[13].off);
     return KIN_OK;
 }
 
