@@ -615,7 +615,12 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
         if (gi >= (unsigned long long)a.total) break;
         int j = 0;
         while (j + 1 < a.nspan && (unsigned long long)a.span[j + 1].start <= gi) ++j;
-        const long long cell = (long long)gi - a.span[j].start;
+        const long long pos = (long long)gi - a.span[j].start;
+        long long cell = pos;
+        if (a.span[j].order) {
+            const long long c = a.span[j].order[pos];
+            if ((unsigned long long)c < (unsigned long long)a.span[j].n) cell = c;
+        }
         const double dt = a.span[j].dt;
         const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
         const long long ld = a.span[j].n;

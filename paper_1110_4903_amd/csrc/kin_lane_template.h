@@ -12,11 +12,13 @@
 // backward Euler; the dense solve is Gaussian elimination with partial pivoting (Sec. 4.2).
 
 // One instance's share of the launch: global cells [start, start + n) live in the arena at
-// base (layout below), advanced by dt.
+// base (layout below), advanced by dt; order (when not null) maps a position of the span to
+// the cell taken there (cells expected to need more iterations first).
 struct KinSpan {
     long long start, n;
     double dt;
     char *base;
+    const int *order;
 };
 #define KIN_MAX_SPANS 64
 
@@ -309,6 +311,10 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                     nspan_cells = a.span[j].n;
                     dt = a.span[j].dt;
                     i = (long long)gi - a.span[j].start;
+                    if (a.span[j].order) {
+                        const long long c = a.span[j].order[i];
+                        if ((unsigned long long)c < (unsigned long long)nspan_cells) i = c;
+                    }
                     need = false;
                     const double *Yin = kin_Y(base, nspan_cells);
                     rho = kin_rho(base, nspan_cells)[i];

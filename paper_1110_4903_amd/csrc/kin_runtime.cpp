@@ -46,7 +46,11 @@ struct Inst {
     int *status = nullptr, *level = nullptr, *iters = nullptr;
     unsigned long long *counter = nullptr;  // work counter of the advance kernels
     unsigned long long *sched = nullptr;    // per-cell sub-step schedule hash
+    bool iters_current = false;  // iters[] holds the counts of an advance of the current state
 };
+
+// Instances at least this large take their cells in cost order once iters[] is current.
+constexpr long long kOrderMinCells = 32768;
 
 // Code objects already compiled in this process, keyed by their source.
 static std::mutex g_jit_mu;
@@ -738,6 +742,7 @@ kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double
     Inst &in = *it->second;
     const Mech &m = *ctx->mechs[in.mech];
     hipStream_t st = static_cast<hipStream_t>(stream);
+    in.iters_current = false;
     if ((s = fill_conserved(ctx, in, m, rho_s, E_sens, T_guess, where, st)) != KIN_OK) return s;
     if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
     return KIN_OK;
@@ -783,6 +788,7 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
     if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
     Inst &in = *it->second;
     const Mech &m = *ctx->mechs[in.mech];
+    in.iters_current = false;
     return fill_state(ctx, in, m, rho, T, Y, e0, where, static_cast<hipStream_t>(stream));
 }
 
@@ -1033,7 +1039,12 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
             if (inst_ids[q] == inst_ids[k]) return err(KIN_EINVAL, "an instance appears twice in one advance");
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (n > 1) return advance_batch(ctx, inst_ids, dts, n, prec, o, st);
+    if (n > 1) {
+        s = advance_batch(ctx, inst_ids, dts, n, prec, o, st);
+        if (s == KIN_OK)
+            for (int k = 0; k < n; ++k) ctx->insts[inst_ids[k]]->iters_current = true;
+        return s;
+    }
     Inst &in = *ctx->insts[inst_ids[0]];
     Mech &m = *ctx->mechs[in.mech];
     int layout, block;
@@ -1049,7 +1060,15 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     a.total = in.n;
     a.counter = in.counter;
     KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
-    return launch_spans(ctx, m, a, prec, layout, block, st);
+    // cost order: cells that needed many iterations in the previous advance are taken first
+    if (in.iters_current && in.n >= kOrderMinCells && in.n <= 0x7fffffffLL) {
+        const Arena ar = arena_at(static_cast<char *>(in.buf), in.n, m.h.ns);
+        KIN_HIP(ctx, launch_cost_order(in.iters, in.n, ar.order, ar.ocount, st));
+        a.span[0].order = ar.order;
+    }
+    s = launch_spans(ctx, m, a, prec, layout, block, st);
+    if (s == KIN_OK) in.iters_current = true;
+    return s;
 }
 
 kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,
@@ -1221,6 +1240,7 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
         cand.push_back({KIN_LAYOUT_GLOBAL, 64});
     }
     void *save = nullptr;
+    const bool iters_was_current = in.iters_current;  // the saved arena's counts, restored with it
     KIN_HIP(ctx, hipMalloc(&save, in.bytes));
     KIN_HIP(ctx, hipMemcpy(save, in.buf, in.bytes, hipMemcpyDeviceToDevice));
     hipEvent_t e0, e1;
@@ -1234,9 +1254,12 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     for (const auto &c : cand) {
         if ((s = kin_set_layout(ctx, mech_id, c.first, c.second)) != KIN_OK) break;
         KIN_HIP(ctx, hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice));
-        // one untimed launch loads the module and warms the caches
+        // one untimed launch loads the module and warms the caches; candidates are timed in
+        // index order
+        in.iters_current = false;
         if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, &o, nullptr)) != KIN_OK) break;
         KIN_HIP(ctx, hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice));
+        in.iters_current = false;
         KIN_HIP(ctx, hipEventRecord(e0, nullptr));
         if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, &o, nullptr)) != KIN_OK) break;
         KIN_HIP(ctx, hipEventRecord(e1, nullptr));
@@ -1246,6 +1269,7 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
         if (ms < best) { best = ms; win = c; }
     }
     hipMemcpy(in.buf, save, in.bytes, hipMemcpyDeviceToDevice);
+    in.iters_current = iters_was_current;
     hipFree(save);
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -520,7 +520,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
     if (gcell >= a.total) return;
     int j = 0;
     while (j + 1 < a.nspan && a.span[j + 1].start <= gcell) ++j;
-    const long long cell = gcell - a.span[j].start;
+    const long long pos = gcell - a.span[j].start;
+    long long cell = pos;
+    if (a.span[j].order) {
+        const long long c = a.span[j].order[pos];
+        if ((unsigned long long)c < (unsigned long long)a.span[j].n) cell = c;
+    }
     const double dt = a.span[j].dt;
     const Arena ar = arena_at(a.span[j].base, a.span[j].n, ns);
     const long long ld = a.span[j].n;

@@ -228,6 +228,40 @@ def test_e0_given_and_resume(ctx):
     ctx.mech_release(mid)
 
 
+@pytest.mark.parametrize("case", ["mech9-lane", "mech36-wave", "mech9-global"])
+def test_cost_order_is_bitwise_neutral(ctx, case):
+    """A single instance of >= 32768 cells whose iteration counts are current takes its cells
+    in cost order; its second step equals, bitwise (state, status, level, iterations,
+    schedule), the same step taken in index order by a fresh instance holding the first
+    step's result.  A cell left out of, or repeated in, the order would show as a difference."""
+    from paper_1110_4903_amd import kin
+    name, layout = case.split("-")
+    m = synth.mechanism(name)
+    n = 40000 if name == "mech9" else 33000
+    st = synth.uniform_cells(71, n, m.ns, 1.0 if name == "mech9" else 0.5)
+    dt = 1e-6
+    mid = ctx.mech_upload(m)
+    if layout == "global":
+        ctx.set_layout(mid, kin.LAYOUT_GLOBAL, 64)
+    a = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    ctx.advance([a], [dt])
+    T1, Y1, _, _, it1 = ctx.download(a)[:5]
+    bounds = [5, 10, 20, 40, 80, 160, 320]
+    assert np.unique(np.digitize(it1, bounds)).size > 1, "the first step should give more than one cost class"
+    e0 = ctx.download_e0(a)
+    b = ctx.state_upload(mid, st.rho, T1, Y1, e0=e0)
+    ctx.advance([a], [dt])      # cost order (a's counts are current)
+    ctx.advance([b], [dt])      # index order (fresh instance)
+    ra = ctx.download(a) + (ctx.download_schedule(a),)
+    rb = ctx.download(b) + (ctx.download_schedule(b),)
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y, equal_nan=True)
+    report(f"cost order {case}", dict(cells=n, classes=np.bincount(np.digitize(it1, bounds), minlength=8).tolist()))
+    for i in (a, b):
+        ctx.instance_release(i)
+    ctx.mech_release(mid)
+
+
 def _batch_setup(ctx, insts):
     mids = {}
     ids, states = [], []
