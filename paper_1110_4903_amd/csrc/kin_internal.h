@@ -119,13 +119,14 @@ struct WaveTables {
 // Device layout of one instance's arena (n cells, ns species), from its base address:
 //   rho[n] e0[n] T[n] Y[ns][n] sched[n] (8-byte entries, each array 256-byte aligned)
 //   status[n] level[n] iters[n] (4-byte entries), one 64-bit work counter, the cell order
-//   order[n] of a cost-ordered advance and its per-tile class counts ocount[8 * tiles].
+//   order[n] of a cost-ordered advance, its per-tile class counts ocount[8 * tiles] and the
+//   cost classes okey[n] of a first advance (no iteration counts yet).
 struct Arena {
     double *rho, *e0, *T, *Y;
     unsigned long long *sched;
     int *status, *level, *iters;
     unsigned long long *counter;
-    int *order, *ocount;
+    int *order, *ocount, *okey;
 };
 
 // Cost-ordered advance: cells are classed by their Newton iterations in the previous advance
@@ -153,13 +154,14 @@ __host__ __device__ inline Arena arena_at(char *base, long long n, int ns)
     a.counter = reinterpret_cast<unsigned long long *>(ib + 3 * i);
     a.order = reinterpret_cast<int *>(ib + 3 * i + 256);
     a.ocount = reinterpret_cast<int *>(ib + 4 * i + 256);
+    a.okey = reinterpret_cast<int *>(ib + 4 * i + 256 + arena_align(sizeof(int) * kOrderClasses * (size_t)order_tiles(n)));
     return a;
 }
 
 __host__ __device__ inline size_t arena_bytes(long long n, int ns)
 {
     return arena_align(sizeof(double) * (size_t)n) * (4 + (size_t)ns) +
-           4 * arena_align(sizeof(int) * (size_t)n) + 256 +
+           5 * arena_align(sizeof(int) * (size_t)n) + 256 +
            arena_align(sizeof(int) * kOrderClasses * (size_t)order_tiles(n));
 }
 
@@ -197,9 +199,10 @@ hipError_t launch_conserved_out(const WaveTables &t, long long n, long long ld, 
 // Global-memory layout (kin_global.hip): workspace doubles per slot, and the launch over
 // `slots` threads with a workspace of slots * global_work_doubles_per_slot doubles.
 size_t global_work_doubles_per_slot(int ns, int ntb);
-// Cost order of an instance's n cells from the iterations of its previous advance
-// (kin_order.hip): order[n], per-tile scratch ocount[kOrderClasses * order_tiles(n)].
-hipError_t launch_cost_order(const int *iters, long long n, int *order, int *ocount, hipStream_t s);
+// Cost order of an instance's n cells (kin_order.hip): order[n], per-tile scratch
+// ocount[kOrderClasses * order_tiles(n)].  key: the iterations of the previous advance, or
+// with direct, cost classes 0..kOrderClasses-1 already.
+hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount, hipStream_t s);
 hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, double *work,
                          long long slots, hipStream_t stream);
 hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,

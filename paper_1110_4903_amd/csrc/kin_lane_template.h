@@ -406,6 +406,37 @@ extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f64(KinLaneArgs
     kin_lane_run<false>(a);
 }
 
+// Cost class of each cell of span 0 for a first advance (no iteration counts yet): the octave
+// of the relative temperature change that the source term predicts over dt, |dT/dt| dt / T,
+// clamped to 0..7 (7: a change of T itself or more; 0: below T / 128).  Cells whose
+// temperature moves fastest take the most sub-steps.  The class only orders the cells.
+extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_cost(KinLaneArgs a, int *key)
+{
+    const long long i = (long long)blockIdx.x * KIN_BLOCK + threadIdx.x;
+    const long long n = a.span[0].n;
+    if (i >= n) return;
+    char *base = a.span[0].base;
+    const double *Yin = kin_Y(base, n);
+    double x[KIN_N];
+#pragma unroll
+    for (int s = 0; s < KIN_NS; ++s) x[s] = Yin[s * n + i];
+    x[KIN_NS] = kin_T(base, n)[i];
+    const double rho = kin_rho(base, n)[i];
+    const double dt = a.span[0].dt;
+    bool ok = rho > 0.0 && x[KIN_NS] >= KIN_T_MIN && x[KIN_NS] <= KIN_T_MAX;
+#pragma unroll
+    for (int s = 0; s < KIN_N; ++s) ok = ok && __builtin_isfinite(x[s]);
+    int c = 0;
+    if (ok) {
+        double f[KIN_N], J[KIN_N][KIN_N];
+        kin_eval(kin_launder(a.K), rho, x, f, J);
+        const double p = fabs(f[KIN_NS]) * dt / x[KIN_NS];
+        if (!(p < 1.0)) c = 7;
+        else if (p > 0.0) c = max((int)floor(log2(p)) + 7, 0);
+    }
+    key[i] = c;
+}
+
 extern "C" __global__ void __launch_bounds__(KIN_BLOCK) kin_lane_f32lu(KinLaneArgs a)
 {
     kin_lane_run<true>(a);

@@ -5,7 +5,7 @@
 // leave the rest of the device idle.  The iterations a cell needed in the previous advance of
 // the same instance predict its cost well, so the next advance takes the cells in kOrderClasses
 // geometric classes, most expensive first: >= 320, 160-319, ..., 10-19, 5-9 and < 5
-// iterations.  Within a class cells keep their index order, which keeps the state accesses of
+// iterations.  A first advance (no counts yet) may pass classes computed otherwise (direct).  Within a class cells keep their index order, which keeps the state accesses of
 // neighbouring lanes coalesced.  Which cell a lane takes does not change that cell's
 // arithmetic: results are bitwise the same in any order.
 //
@@ -24,9 +24,11 @@ constexpr int kOrderThreads = 256;
 constexpr int kOrderRounds = kOrderTile / kOrderThreads;
 constexpr int kScanThreads = 1024;
 
-// class of a cell that needed `it` iterations: 0 below 5, then one class per doubling
-__device__ __forceinline__ int cost_class(int it)
+// class of a cell that needed `it` iterations: 0 below 5, then one class per doubling; with
+// direct, the key is the class
+__device__ __forceinline__ int cost_class(int it, int direct)
 {
+    if (direct) return it < 0 ? 0 : (it >= kC ? kC - 1 : it);
     int k = 0;
 #pragma unroll
     for (int b = 5; b <= (5 << (kC - 2)); b <<= 1) k += it >= b;
@@ -34,7 +36,8 @@ __device__ __forceinline__ int cost_class(int it)
 }
 
 // ocount[kC t + c] = cells of class c in tile t
-__global__ void __launch_bounds__(kOrderThreads) order_count_kernel(const int *iters, long long n, int *ocount)
+__global__ void __launch_bounds__(kOrderThreads) order_count_kernel(const int *iters, long long n, int direct,
+                                                                    int *ocount)
 {
     __shared__ int cnt[kC];
     if (threadIdx.x < kC) cnt[threadIdx.x] = 0;
@@ -42,7 +45,7 @@ __global__ void __launch_bounds__(kOrderThreads) order_count_kernel(const int *i
     const long long t0 = (long long)blockIdx.x * kOrderTile;
     for (int r = 0; r < kOrderRounds; ++r) {
         const long long i = t0 + (long long)r * kOrderThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[cost_class(iters[i])], 1);
+        if (i < n) atomicAdd(&cnt[cost_class(iters[i], direct)], 1);
     }
     __syncthreads();
     if (threadIdx.x < kC) ocount[(size_t)blockIdx.x * kC + threadIdx.x] = cnt[threadIdx.x];
@@ -96,8 +99,8 @@ __global__ void __launch_bounds__(kScanThreads) order_scan_kernel(int *ocount, l
 }
 
 // order[position] = cell, stable within each class
-__global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(const int *iters, long long n, const int *ocount,
-                                                                      int *order)
+__global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(const int *iters, long long n, int direct,
+                                                                      const int *ocount, int *order)
 {
     constexpr int kWaves = kOrderThreads / 64;
     __shared__ int run[kC];
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(const int 
     for (int r = 0; r < kOrderRounds; ++r) {
         const long long i = t0 + (long long)r * kOrderThreads + threadIdx.x;
         const bool valid = i < n;
-        const int k = valid ? cost_class(iters[i]) : -1;
+        const int k = valid ? cost_class(iters[i], direct) : -1;
         unsigned long long mine = 0;
 #pragma unroll
         for (int c = 0; c < kC; ++c) {
@@ -137,14 +140,15 @@ __global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(const int 
 
 }  // namespace
 
-hipError_t launch_cost_order(const int *iters, long long n, int *order, int *ocount, hipStream_t s)
+hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (n > 0x7fffffffLL) return hipErrorInvalidValue;
     const long long tiles = order_tiles(n);
-    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, iters, n, ocount);
+    const int d = direct ? 1 : 0;
+    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, key, n, d, ocount);
     hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, ocount, tiles);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, iters, n, ocount,
+    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, key, n, d, ocount,
                        order);
     return hipGetLastError();
 }

@@ -30,7 +30,7 @@ struct Mech {
     int layout = KIN_LAYOUT_WAVE;
     int block = 64;          // lane layout: threads per block; wave layout: waves per block
     hipModule_t mod = nullptr;
-    hipFunction_t lane_f64 = nullptr, lane_f32 = nullptr;
+    hipFunction_t lane_f64 = nullptr, lane_f32 = nullptr, lane_cost = nullptr;
     double *kconst = nullptr;  // constant table of the lane kernels
     int lane_block = 0;      // block size the module was compiled for
     double jit_seconds = 0.0;
@@ -266,6 +266,7 @@ static kin_status build_lane(kin_ctx *ctx, Mech &m, int block)
     KIN_HIP(ctx, hipModuleLoadData(&m.mod, code.data()));
     KIN_HIP(ctx, hipModuleGetFunction(&m.lane_f64, m.mod, "kin_lane_f64"));
     KIN_HIP(ctx, hipModuleGetFunction(&m.lane_f32, m.mod, "kin_lane_f32lu"));
+    KIN_HIP(ctx, hipModuleGetFunction(&m.lane_cost, m.mod, "kin_lane_cost"));
     m.lane_block = block;
     m.jit_seconds += secs;
     return KIN_OK;
@@ -1060,11 +1061,23 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     a.total = in.n;
     a.counter = in.counter;
     KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
-    // cost order: cells that needed many iterations in the previous advance are taken first
-    if (in.iters_current && in.n >= kOrderMinCells && in.n <= 0x7fffffffLL) {
+    // cost order: cells that needed many iterations in the previous advance are taken first;
+    // in the lane layout a first advance orders by the source term's temperature change
+    if (!o.point_implicit && in.n >= kOrderMinCells && in.n <= 0x7fffffffLL) {
         const Arena ar = arena_at(static_cast<char *>(in.buf), in.n, m.h.ns);
-        KIN_HIP(ctx, launch_cost_order(in.iters, in.n, ar.order, ar.ocount, st));
-        a.span[0].order = ar.order;
+        if (in.iters_current) {
+            KIN_HIP(ctx, launch_cost_order(in.iters, in.n, false, ar.order, ar.ocount, st));
+            a.span[0].order = ar.order;
+        } else if (layout == KIN_LAYOUT_LANE && m.h.ns <= kLaneNsMax) {
+            if ((s = build_lane(ctx, m, block)) != KIN_OK) return s;
+            a.K = m.kconst;
+            int *key = ar.okey;
+            void *params[] = {&a, &key};
+            const long long grid = (in.n + block - 1) / block;
+            KIN_HIP(ctx, hipModuleLaunchKernel(m.lane_cost, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
+            KIN_HIP(ctx, launch_cost_order(ar.okey, in.n, true, ar.order, ar.ocount, st));
+            a.span[0].order = ar.order;
+        }
     }
     s = launch_spans(ctx, m, a, prec, layout, block, st);
     if (s == KIN_OK) in.iters_current = true;

@@ -230,34 +230,49 @@ def test_e0_given_and_resume(ctx):
 
 @pytest.mark.parametrize("case", ["mech9-lane", "mech36-wave", "mech9-global"])
 def test_cost_order_is_bitwise_neutral(ctx, case):
-    """A single instance of >= 32768 cells whose iteration counts are current takes its cells
-    in cost order; its second step equals, bitwise (state, status, level, iterations,
-    schedule), the same step taken in index order by a fresh instance holding the first
-    step's result.  A cell left out of, or repeated in, the order would show as a difference."""
+    """A single instance of >= 32768 cells takes its cells in cost order: by the previous
+    advance's iteration counts when they are current, and in the lane layout by the source
+    term's temperature change on a first advance.  Both equal, bitwise (state, status, level,
+    iterations, schedule), the same step in index order, taken through a batched launch (which
+    never reorders).  A cell left out of, or repeated in, an order would show as a difference."""
     from paper_1110_4903_amd import kin
     name, layout = case.split("-")
     m = synth.mechanism(name)
     n = 40000 if name == "mech9" else 33000
     st = synth.uniform_cells(71, n, m.ns, 1.0 if name == "mech9" else 0.5)
+    tiny = synth.uniform_cells(72, 64, m.ns, 0.5)
     dt = 1e-6
     mid = ctx.mech_upload(m)
     if layout == "global":
         ctx.set_layout(mid, kin.LAYOUT_GLOBAL, 64)
+
+    def full(i):
+        return ctx.download(i) + (ctx.download_schedule(i),)
+
+    def same(x, y):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v, equal_nan=True)
+
+    # first step: a alone (first-advance order in the lane layout) against index order
     a = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    c = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    d = ctx.state_upload(mid, tiny.rho, tiny.T, tiny.Y)
     ctx.advance([a], [dt])
+    ctx.advance([c, d], [dt, dt])
+    same(full(a), full(c))
     T1, Y1, _, _, it1 = ctx.download(a)[:5]
     bounds = [5, 10, 20, 40, 80, 160, 320]
     assert np.unique(np.digitize(it1, bounds)).size > 1, "the first step should give more than one cost class"
+    # second step: a in the order of its counts; b (fresh, same state) and c (batched, index order)
     e0 = ctx.download_e0(a)
     b = ctx.state_upload(mid, st.rho, T1, Y1, e0=e0)
-    ctx.advance([a], [dt])      # cost order (a's counts are current)
-    ctx.advance([b], [dt])      # index order (fresh instance)
-    ra = ctx.download(a) + (ctx.download_schedule(a),)
-    rb = ctx.download(b) + (ctx.download_schedule(b),)
-    for x, y in zip(ra, rb):
-        assert np.array_equal(x, y, equal_nan=True)
+    ctx.advance([a], [dt])
+    ctx.advance([b], [dt])
+    ctx.advance([c, d], [dt, dt])
+    same(full(a), full(b))
+    same(full(a), full(c))
     report(f"cost order {case}", dict(cells=n, classes=np.bincount(np.digitize(it1, bounds), minlength=8).tolist()))
-    for i in (a, b):
+    for i in (a, b, c, d):
         ctx.instance_release(i)
     ctx.mech_release(mid)
 
