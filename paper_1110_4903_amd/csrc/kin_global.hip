@@ -408,19 +408,35 @@ __device__ __forceinline__ typename std::conditional<F32, float, double>::type g
     else return *e;
 }
 
-// Gaussian elimination with partial pivoting over the padded system in the slot's matrix,
-// rows in place; b[] holds the right-hand side of the lane's rows (already scaled by rs[]
-// in the FP32 form, whose matrix rows are scaled by rs[] as the first panel reads them) and
-// returns the update of its unknowns.
+// Exchange rows k and p (physical rows of the lane-distributed vector v: lane r & 63,
+// register r >> 6); wave-uniform k and p.
+template <int RW, typename T>
+__device__ __forceinline__ void gswap(T (&v)[RW], int lane, int k, int p)
+{
+    const T vk = rdlane(pick<RW>(v, k >> 6), k & 63);
+    const T vp = rdlane(pick<RW>(v, p >> 6), p & 63);
+#pragma unroll
+    for (int m = 0; m < RW; ++m) {
+        const int i = lane + 64 * m;
+        v[m] = i == k ? vp : (i == p ? vk : v[m]);
+    }
+}
+
+// Gaussian elimination with partial pivoting over the padded system in the slot's matrix;
+// b[] holds the right-hand side of the lane's rows (already scaled by rs[] in the FP32 form,
+// whose matrix rows are scaled by rs[] as the first panel reads them) and returns the update
+// of its unknowns.
 //
-// Blocked right-looking form: a panel of GB columns is loaded into registers and factored
-// there (pivot search, multipliers, updates of the panel's later columns), and the columns
-// to the right of the panel then receive the panel's GB updates in one pass, each column
-// read and written once per panel instead of once per pivot step.  Within such a column the
-// GB updates are applied in pivot order, the pivot row's current entry broadcast by readlane
-// before each, which is the same arithmetic as the unblocked order.  Columns move in batches
-// of kGC with the next batch's loads issued before the current batch is computed.  Rows
-// already pivoted take no part: their lanes address the spare row.
+// Blocked right-looking form with physical row exchanges: a panel of GB columns is loaded
+// into registers and factored there (pivot search over the rows not yet pivoted, exchange of
+// the pivot row into place, multipliers, updates of the panel's later columns by readlane
+// broadcasts of the pivot row), its multipliers kept in the final row order as later
+// exchanges happen.  The columns right of the panel then receive the panel's exchanges and
+// its GB updates in one pass, each column read and written once per panel instead of once per
+// pivot step; this is the arithmetic of the unblocked order.  Rows not yet pivoted stay
+// contiguous (rows k0 and up), so a panel touches whole lines of them only; lanes with
+// nothing to load or store address the spare row.  Columns move in batches of kGC with the
+// next batch's loads issued before the current batch is computed.
 template <bool F32, int RW>
 __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], double (&b)[RW])
 {
@@ -428,21 +444,19 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
     constexpr int GB = RW <= 2 ? 8 : 4;                  // panel width (divides NQ)
     constexpr int GC = kGC;
     const int NQ = gnq(N), NP = gnp(N), SP = NP - 1;
-    int pos[RW];
     double dg[RW];
 #pragma unroll
-    for (int m = 0; m < RW; ++m) { pos[m] = lane + 64 * m; dg[m] = 1.0; }
+    for (int m = 0; m < RW; ++m) dg[m] = 1.0;
     bool ok = true;
     for (int k0 = 0; k0 < NQ; k0 += GB) {
-        // rows not yet pivoted: the only rows this panel changes
-        bool act[RW];
-        int ri[RW];
+        // rows k0.. are not yet pivoted: the only rows this panel changes
+        int ri[RW], rp[RW];
         double sc[RW];
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int i = lane + 64 * m;
-            act[m] = i < NQ && pos[m] >= k0;
-            ri[m] = act[m] ? i : SP;
+            ri[m] = (i >= k0 && i < NQ) ? i : SP;
+            rp[m] = (i >= k0 && i < k0 + GB) ? i : SP;  // the panel's own rows
             sc[m] = (k0 == 0) ? rs[m] : 1.0;
         }
         R P[GB][RW];
@@ -451,55 +465,53 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 #pragma unroll
             for (int m = 0; m < RW; ++m) P[c][m] = gld<F32>(gm(Mx, NP, ri[m], k0 + c), sc[m]);
         R Lp[GB][RW];
-        int wv[GB], mwv[GB];
+        int pv[GB];
 #pragma unroll
         for (int c = 0; c < GB; ++c) {
             const int k = k0 + c;
-            // the lane's best candidate row in column k: largest |a|, ties to the lowest position
+            // the lane's best candidate row in column k: largest |a|, ties to the lowest row
             R best = R(-1);
-            int bpos = 0x7fffffff, bm = 0;
-#pragma unroll
-            for (int m = 0; m < RW; ++m) {
-                const R av = (R)fabs(P[c][m]);
-                if (act[m] && pos[m] >= k && (av > best || (av == best && pos[m] < bpos))) {
-                    best = av; bpos = pos[m]; bm = m;
-                }
-            }
-            const bool cand = bpos != 0x7fffffff;
-            const int w = pivot_lane<R>(cand ? best : R(0), cand, cand ? bpos : 0x7fffffff);
-            const int mw = rdlane(bm, w);
-            const int p = w + 64 * mw;                   // physical pivot row
-            const int pos_p = rdlane(pick<RW>(pos, mw), w);
-            const R piv = rdlane(pick<RW>(P[c], mw), w);
-            if (piv == R(0)) ok = false;
-            const double yk = rdlane(pick<RW>(b, mw), w);
+            int bpos = 0x7fffffff;
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
                 const int i = lane + 64 * m;
-                const bool isp = i == p;
-                dg[m] = isp ? (double)piv : dg[m];
-                pos[m] = isp ? k : (pos[m] == k ? pos_p : pos[m]);
+                const R av = (R)fabs(P[c][m]);
+                if (i >= k && i < NQ && (av > best || (av == best && i < bpos))) { best = av; bpos = i; }
             }
+            const bool cand = bpos != 0x7fffffff;
+            const int w = pivot_lane<R>(cand ? best : R(0), cand, cand ? bpos : 0x7fffffff);
+            const int p = rdlane(bpos, w);               // physical pivot row, >= k
+            pv[c] = p;
+            if (p != k) {                                // exchange rows k and p
+#pragma unroll
+                for (int c2 = c; c2 < GB; ++c2) gswap<RW>(P[c2], lane, k, p);
+#pragma unroll
+                for (int c1 = 0; c1 < c; ++c1) gswap<RW>(Lp[c1], lane, k, p);
+                gswap<RW>(b, lane, k, p);
+            }
+            const R piv = rdlane(pick<RW>(P[c], k >> 6), k & 63);
+            if (piv == R(0)) ok = false;
+            const double yk = rdlane(pick<RW>(b, k >> 6), k & 63);
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
-                Lp[c][m] = (act[m] && pos[m] > k) ? P[c][m] / piv : R(0);
+                const int i = lane + 64 * m;
+                dg[m] = i == k ? (double)piv : dg[m];
+                Lp[c][m] = (i > k && i < NQ) ? P[c][m] / piv : R(0);
                 b[m] = (double)fma(-Lp[c][m], (R)yk, (R)b[m]);
             }
 #pragma unroll
             for (int c2 = c + 1; c2 < GB; ++c2) {
-                const R u = rdlane(pick<RW>(P[c2], mw), w);
+                const R u = rdlane(pick<RW>(P[c2], k >> 6), k & 63);
 #pragma unroll
                 for (int m = 0; m < RW; ++m) P[c2][m] = fma(-Lp[c][m], u, P[c2][m]);
             }
-            wv[c] = w;
-            mwv[c] = mw;
         }
-        // the panel back: the rows pivoted here keep their U entries for back substitution
+        // the panel's rows back (their U entries); the multipliers are not stored
 #pragma unroll
         for (int c = 0; c < GB; ++c)
 #pragma unroll
-            for (int m = 0; m < RW; ++m) *gm(Mx, NP, ri[m], k0 + c) = (double)P[c][m];
-        // columns right of the panel: the panel's GB updates per column
+            for (int m = 0; m < RW; ++m) *gm(Mx, NP, rp[m], k0 + c) = (double)P[c][m];
+        // columns right of the panel: the panel's exchanges, then its GB updates per column
         const int j0 = k0 + GB;
         R nx[GC][RW];
 #pragma unroll
@@ -519,21 +531,28 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
                     nx[q][m] = gld<F32>(gm(Mx, NP, ri[m], min(j + GC + q, NQ - 1)), sc[m]);
 #pragma unroll
             for (int c = 0; c < GB; ++c)
+                if (pv[c] != k0 + c)
+#pragma unroll
+                    for (int q = 0; q < GC; ++q) gswap<RW>(cu[q], lane, k0 + c, pv[c]);
+#pragma unroll
+            for (int c = 0; c < GB; ++c) {
+                const int k = k0 + c;
 #pragma unroll
                 for (int q = 0; q < GC; ++q) {
-                    const R u = rdlane(pick<RW>(cu[q], mwv[c]), wv[c]);
+                    const R u = rdlane(pick<RW>(cu[q], k >> 6), k & 63);
 #pragma unroll
                     for (int m = 0; m < RW; ++m) cu[q][m] = fma(-Lp[c][m], u, cu[q][m]);
                 }
+            }
 #pragma unroll
             for (int q = 0; q < GC; ++q)
 #pragma unroll
                 for (int m = 0; m < RW; ++m) *gm(Mx, NP, ri[m], j + q) = (double)cu[q][m];
         }
     }
-    // back substitution by columns over the first N positions (the padding unknowns are
-    // zero): the row at position k gives x_k, which every row above it removes from its
-    // right-hand side; a batch's column entries are loaded one batch ahead
+    // back substitution by columns over the first N rows (the padding unknowns are zero):
+    // row k gives x_k, which every row above it removes from its right-hand side; a batch's
+    // column entries (rows above the diagonal) are loaded one batch ahead
     double xl[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) xl[m] = 0.0;
@@ -543,7 +562,7 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int k = N - 1 - q, i = lane + 64 * m;
-            const bool need = k >= 0 && i < N && pos[m] < k;
+            const bool need = i < k;
             const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
             ux[q][m] = need ? v : R(0);
         }
@@ -558,7 +577,7 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
                 const int k = kt - GC - q, i = lane + 64 * m;
-                const bool need = k >= 0 && i < N && pos[m] < k;
+                const bool need = i < k;
                 const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
                 ux[q][m] = need ? v : R(0);
             }
@@ -566,18 +585,12 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
         for (int q = 0; q < GC; ++q) {
             const int k = kt - q;
             if (k < 0) continue;
-            int o = -1, om = 0;
-#pragma unroll
-            for (int m = 0; m < RW; ++m) {
-                const unsigned long long bal = __ballot(lane + 64 * m < N && pos[m] == k);
-                if (bal) { o = __builtin_ctzll(bal); om = m; }
-            }
-            const double xk = (double)((R)rdlane(pick<RW>(b, om), o) / (R)rdlane(pick<RW>(dg, om), o));
+            const double xk = (double)((R)rdlane(pick<RW>(b, k >> 6), k & 63) / (R)rdlane(pick<RW>(dg, k >> 6), k & 63));
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
                 const int i = lane + 64 * m;
                 if (i == k) xl[m] = xk;
-                if (i < N && pos[m] < k) b[m] = (double)fma(-uc[q][m], (R)xk, (R)b[m]);
+                if (i < k) b[m] = (double)fma(-uc[q][m], (R)xk, (R)b[m]);
             }
         }
     }
