@@ -399,13 +399,35 @@ __device__ void gw_system(const WaveTables &t, const GLds &L, bool staged, doubl
     for (int m = 0; m < RW; ++m) rs[m] = (lane + 64 * m < N) ? 1.0 / rmax[m] : 1.0;
 }
 
+// The elimination addresses the slot's matrix through a buffer resource: one scalar base,
+// a scalar column offset and a 32-bit lane (row) offset per access, so a batch of column
+// accesses shares one address register.  A lane with nothing to access gives an offset past
+// the slot (kNoRow): the hardware's range check drops its store and returns zero to its load.
+typedef unsigned int gu2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kNoRow = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gslot_rsrc(double *Mx, int NP, int NQ)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(Mx, (short)0, NP * NQ * (int)sizeof(double), 0x00020000);
+}
+
+__device__ __forceinline__ double gbld(__amdgpu_buffer_rsrc_t r, unsigned row_off, int col_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, row_off, col_off, 0));
+}
+
+__device__ __forceinline__ void gbst(__amdgpu_buffer_rsrc_t r, unsigned row_off, int col_off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gu2, v), r, row_off, col_off, 0);
+}
+
 // Load of an element as the factorisation's type, scaled by the row factor sc (FP32 form,
 // first panel only).
 template <bool F32>
-__device__ __forceinline__ typename std::conditional<F32, float, double>::type gld(const double *e, double sc)
+__device__ __forceinline__ typename std::conditional<F32, float, double>::type gld(double v, double sc)
 {
-    if constexpr (F32) return (float)(*e * sc);
-    else return *e;
+    if constexpr (F32) return (float)(v * sc);
+    else return v;
 }
 
 // Exchange rows k and p (physical rows of the lane-distributed vector v: lane r & 63,
@@ -442,28 +464,31 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 {
     using R = typename std::conditional<F32, float, double>::type;
     constexpr int GB = RW <= 2 ? 8 : 4;                  // panel width (divides NQ)
-    constexpr int GC = kGC;
-    const int NQ = gnq(N), NP = gnp(N), SP = NP - 1;
+    constexpr int GC = GB;                               // trailing columns per batch
+    constexpr int GK = kGC;                              // back-substitution columns per batch
+    const int NQ = gnq(N), NP = gnp(N), CB = NP * (int)sizeof(double);
+    const __amdgpu_buffer_rsrc_t mr = gslot_rsrc(Mx, NP, NQ);
+    __asm__ volatile("" ::: "memory");                   // the column pass's stores come first
     double dg[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) dg[m] = 1.0;
     bool ok = true;
     for (int k0 = 0; k0 < NQ; k0 += GB) {
         // rows k0.. are not yet pivoted: the only rows this panel changes
-        int ri[RW], rp[RW];
+        unsigned ri[RW], rp[RW];
         double sc[RW];
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int i = lane + 64 * m;
-            ri[m] = (i >= k0 && i < NQ) ? i : SP;
-            rp[m] = (i >= k0 && i < k0 + GB) ? i : SP;  // the panel's own rows
+            ri[m] = (i >= k0 && i < NQ) ? (unsigned)i * 8u : kNoRow;
+            rp[m] = (i >= k0 && i < k0 + GB) ? (unsigned)i * 8u : kNoRow;  // the panel's own rows
             sc[m] = (k0 == 0) ? rs[m] : 1.0;
         }
         R P[GB][RW];
 #pragma unroll
         for (int c = 0; c < GB; ++c)
 #pragma unroll
-            for (int m = 0; m < RW; ++m) P[c][m] = gld<F32>(gm(Mx, NP, ri[m], k0 + c), sc[m]);
+            for (int m = 0; m < RW; ++m) P[c][m] = gld<F32>(gbld(mr, ri[m], (k0 + c) * CB), sc[m]);
         R Lp[GB][RW];
         int pv[GB];
 #pragma unroll
@@ -510,14 +535,14 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 #pragma unroll
         for (int c = 0; c < GB; ++c)
 #pragma unroll
-            for (int m = 0; m < RW; ++m) *gm(Mx, NP, rp[m], k0 + c) = (double)P[c][m];
+            for (int m = 0; m < RW; ++m) gbst(mr, rp[m], (k0 + c) * CB, (double)P[c][m]);
         // columns right of the panel: the panel's exchanges, then its GB updates per column
         const int j0 = k0 + GB;
         R nx[GC][RW];
 #pragma unroll
         for (int q = 0; q < GC; ++q)
 #pragma unroll
-            for (int m = 0; m < RW; ++m) nx[q][m] = gld<F32>(gm(Mx, NP, ri[m], min(j0 + q, NQ - 1)), sc[m]);
+            for (int m = 0; m < RW; ++m) nx[q][m] = gld<F32>(gbld(mr, ri[m], min(j0 + q, NQ - 1) * CB), sc[m]);
         for (int j = j0; j < NQ; j += GC) {
             R cu[GC][RW];
 #pragma unroll
@@ -528,7 +553,7 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
             for (int q = 0; q < GC; ++q)
 #pragma unroll
                 for (int m = 0; m < RW; ++m)
-                    nx[q][m] = gld<F32>(gm(Mx, NP, ri[m], min(j + GC + q, NQ - 1)), sc[m]);
+                    nx[q][m] = gld<F32>(gbld(mr, ri[m], min(j + GC + q, NQ - 1) * CB), sc[m]);
 #pragma unroll
             for (int c = 0; c < GB; ++c)
                 if (pv[c] != k0 + c)
@@ -547,7 +572,7 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
 #pragma unroll
             for (int q = 0; q < GC; ++q)
 #pragma unroll
-                for (int m = 0; m < RW; ++m) *gm(Mx, NP, ri[m], j + q) = (double)cu[q][m];
+                for (int m = 0; m < RW; ++m) gbst(mr, ri[m], (j + q) * CB, (double)cu[q][m]);
         }
     }
     // back substitution by columns over the first N rows (the padding unknowns are zero):
@@ -556,33 +581,31 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
     double xl[RW];
 #pragma unroll
     for (int m = 0; m < RW; ++m) xl[m] = 0.0;
-    R ux[GC][RW];
+    R ux[GK][RW];
 #pragma unroll
-    for (int q = 0; q < GC; ++q)
+    for (int q = 0; q < GK; ++q)
 #pragma unroll
         for (int m = 0; m < RW; ++m) {
             const int k = N - 1 - q, i = lane + 64 * m;
             const bool need = i < k;
-            const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
-            ux[q][m] = need ? v : R(0);
+            ux[q][m] = (R)gbld(mr, need ? (unsigned)i * 8u : kNoRow, max(k, 0) * CB);
         }
-    for (int kt = N - 1; kt >= 0; kt -= GC) {
-        R uc[GC][RW];
+    for (int kt = N - 1; kt >= 0; kt -= GK) {
+        R uc[GK][RW];
 #pragma unroll
-        for (int q = 0; q < GC; ++q)
+        for (int q = 0; q < GK; ++q)
 #pragma unroll
             for (int m = 0; m < RW; ++m) uc[q][m] = ux[q][m];
 #pragma unroll
-        for (int q = 0; q < GC; ++q)
+        for (int q = 0; q < GK; ++q)
 #pragma unroll
             for (int m = 0; m < RW; ++m) {
-                const int k = kt - GC - q, i = lane + 64 * m;
+                const int k = kt - GK - q, i = lane + 64 * m;
                 const bool need = i < k;
-                const R v = (R)*gm(Mx, NP, need ? i : SP, max(k, 0));
-                ux[q][m] = need ? v : R(0);
+                ux[q][m] = (R)gbld(mr, need ? (unsigned)i * 8u : kNoRow, max(k, 0) * CB);
             }
 #pragma unroll
-        for (int q = 0; q < GC; ++q) {
+        for (int q = 0; q < GK; ++q) {
             const int k = kt - q;
             if (k < 0) continue;
             const double xk = (double)((R)rdlane(pick<RW>(b, k >> 6), k & 63) / (R)rdlane(pick<RW>(dg, k >> 6), k & 63));
@@ -596,6 +619,7 @@ __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], do
     }
 #pragma unroll
     for (int m = 0; m < RW; ++m) b[m] = xl[m];
+    __asm__ volatile("" ::: "memory");                   // before the next evaluation's stores
     return ok;
 }
 
