@@ -55,18 +55,16 @@ enum { G_CONTINUE = 0, G_ACCEPTED = 1, G_FAILED = 2 };
 // The cell's system is padded to NQ = N rounded up to 8 unknowns with identity rows and
 // columns, which leave the first N unknowns' solution unchanged and let elimination panels
 // and column batches divide the system exactly.  The matrix sits in global memory
-// column-major with column stride NP = NQ + 1 rounded up to 64, so that one column of one
-// cell is one coalesced access of its wavefront.  Lane l owns rows (and unknowns) l, l + 64,
-// l + 128, l + 192 (at most RW per lane).  Row NP - 1 is a spare row: a lane with nothing to
-// load or store in a column addresses it instead of branching around the access, which keeps
-// every access unconditional so that loads issued ahead of their use are not waited on early.
-// Rows stay in place during the elimination (a row's current position is `pos`, as in the
-// wave layout).
+// column-major with column stride NP = NQ rounded up to 64, so that one column of one cell is
+// one coalesced access of its wavefront.  Lane l owns rows (and unknowns) l, l + 64, l + 128,
+// l + 192 (at most RW per lane).  Every access is unconditional (a lane with nothing to access
+// in the elimination passes an out-of-range offset, see gbld), so that loads issued ahead of
+// their use are not waited on early.
 
 constexpr int kGC = 4;                                   // columns per batch
 
 __host__ __device__ inline int gnq(int N) { return (N + 7) & ~7; }
-__host__ __device__ inline int gnp(int N) { return (gnq(N) + 1 + 63) & ~63; }
+__host__ __device__ inline int gnp(int N) { return (gnq(N) + 63) & ~63; }
 
 // element (row i, column j) of the slot's matrix
 __device__ __forceinline__ double *gm(double *M, int NP, int i, int j) { return M + (size_t)j * NP + i; }
@@ -457,8 +455,9 @@ __device__ __forceinline__ void gswap(T (&v)[RW], int lane, int k, int p)
 // its GB updates in one pass, each column read and written once per panel instead of once per
 // pivot step; this is the arithmetic of the unblocked order.  Rows not yet pivoted stay
 // contiguous (rows k0 and up), so a panel touches whole lines of them only; lanes with
-// nothing to load or store address the spare row.  Columns move in batches of kGC with the
-// next batch's loads issued before the current batch is computed.
+// nothing to load or store pass an out-of-range offset.  Columns move in batches (eight when
+// a lane holds at most two rows, else four) with the next batch's loads issued before the
+// current batch is computed.
 template <bool F32, int RW>
 __device__ bool gw_solve(double *Mx, int lane, int N, const double (&rs)[RW], double (&b)[RW])
 {
