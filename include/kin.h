@@ -170,12 +170,15 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
  * are replaced by the step's result (a failed cell keeps its state) and its status, level
  * (deepest halving level) and iters (Newton iterations including failed tries) are written.
  * s may be NULL for the defaults.  With n > 1 all instances go out in one graph launch.
- * A single instance of at least 32768 cells whose iters come from an advance of its current
- * state (no kin_state_reset or conserved reset since) takes its cells in cost order, in
- * classes by the iterations they needed: 320 or more first, then 160-319, 80-159, 40-79,
- * 20-39, 10-19, 5-9 and the rest, each class in index order.  This shortens the launch's tail; every cell's result is bitwise the same in any
- * order.  Advances of one instance must be ordered on one stream (or synchronised), as the
- * order is computed on `stream` from the previous advance's iters. */
+ * A single instance of at least 262144 cells in the lane layout, or 32768 in the others
+ * (about four times the cells a layout keeps in flight), takes its cells in cost order.  When
+ * its iters come from an advance of its current state (no kin_state_reset or conserved
+ * reset since), the classes are the iterations each cell needed: 320 or more first, then
+ * 160-319, 80-159, 40-79, 20-39, 10-19, 5-9 and the rest.  Otherwise, in the lane layout,
+ * they are the octave of the temperature change the source term predicts over dt.  Each class
+ * keeps index order.  This shortens the launch's tail; every cell's result is bitwise the
+ * same in any order.  Advances of one instance must be ordered on one stream (or
+ * synchronised), as the order is computed on `stream` from the previous advance's iters. */
 kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
                        kin_precision prec, const kin_solver_opts *s, void *stream);
 

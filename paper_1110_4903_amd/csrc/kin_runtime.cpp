@@ -49,8 +49,11 @@ struct Inst {
     bool iters_current = false;  // iters[] holds the counts of an advance of the current state
 };
 
-// Instances at least this large take their cells in cost order once iters[] is current.
+// Instances at least this large take their cells in cost order: about four times the cells
+// the layout keeps in flight (65536 lanes in the lane layout, a few thousand wavefronts in
+// the others); below that every cell starts almost at once and the order only costs.
 constexpr long long kOrderMinCells = 32768;
+constexpr long long kOrderMinLaneCells = 262144;
 
 // Code objects already compiled in this process, keyed by their source.
 static std::mutex g_jit_mu;
@@ -1063,7 +1066,8 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
     // cost order: cells that needed many iterations in the previous advance are taken first;
     // in the lane layout a first advance orders by the source term's temperature change
-    if (!o.point_implicit && in.n >= kOrderMinCells && in.n <= 0x7fffffffLL) {
+    const long long order_min = layout == KIN_LAYOUT_LANE ? kOrderMinLaneCells : kOrderMinCells;
+    if (!o.point_implicit && in.n >= order_min && in.n <= 0x7fffffffLL) {
         const Arena ar = arena_at(static_cast<char *>(in.buf), in.n, m.h.ns);
         if (in.iters_current) {
             KIN_HIP(ctx, launch_cost_order(in.iters, in.n, false, ar.order, ar.ocount, st));

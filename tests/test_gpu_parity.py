@@ -230,7 +230,8 @@ def test_e0_given_and_resume(ctx):
 
 @pytest.mark.parametrize("case", ["mech9-lane", "mech36-wave", "mech9-global"])
 def test_cost_order_is_bitwise_neutral(ctx, case):
-    """A single instance of >= 32768 cells takes its cells in cost order: by the previous
+    """A single instance large enough (262144 cells in the lane layout, 32768 in the others)
+    takes its cells in cost order: by the previous
     advance's iteration counts when they are current, and in the lane layout by the source
     term's temperature change on a first advance.  Both equal, bitwise (state, status, level,
     iterations, schedule), the same step in index order, taken through a batched launch (which
@@ -238,7 +239,7 @@ def test_cost_order_is_bitwise_neutral(ctx, case):
     from paper_1110_4903_amd import kin
     name, layout = case.split("-")
     m = synth.mechanism(name)
-    n = 40000 if name == "mech9" else 33000
+    n = {"lane": 270000, "wave": 33000, "global": 40000}[layout]
     st = synth.uniform_cells(71, n, m.ns, 1.0 if name == "mech9" else 0.5)
     tiny = synth.uniform_cells(72, 64, m.ns, 0.5)
     dt = 1e-6
