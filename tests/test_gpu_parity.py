@@ -228,7 +228,7 @@ def test_e0_given_and_resume(ctx):
     ctx.mech_release(mid)
 
 
-@pytest.mark.parametrize("case", ["mech9-lane", "mech36-wave", "mech9-global"])
+@pytest.mark.parametrize("case", ["mech9-lane", "mech9-lane-fp32lu", "mech36-wave", "mech9-global"])
 def test_cost_order_is_bitwise_neutral(ctx, case):
     """A single instance large enough (262144 cells in the lane layout, 32768 in the others)
     takes its cells in cost order: by the previous
@@ -237,7 +237,8 @@ def test_cost_order_is_bitwise_neutral(ctx, case):
     iterations, schedule), the same step in index order, taken through a batched launch (which
     never reorders).  A cell left out of, or repeated in, an order would show as a difference."""
     from paper_1110_4903_amd import kin
-    name, layout = case.split("-")
+    name, layout = case.split("-")[:2]
+    prec = 1 if case.endswith("fp32lu") else 0
     m = synth.mechanism(name)
     n = {"lane": 270000, "wave": 33000, "global": 40000}[layout]
     st = synth.uniform_cells(71, n, m.ns, 1.0 if name == "mech9" else 0.5)
@@ -258,8 +259,8 @@ def test_cost_order_is_bitwise_neutral(ctx, case):
     a = ctx.state_upload(mid, st.rho, st.T, st.Y)
     c = ctx.state_upload(mid, st.rho, st.T, st.Y)
     d = ctx.state_upload(mid, tiny.rho, tiny.T, tiny.Y)
-    ctx.advance([a], [dt])
-    ctx.advance([c, d], [dt, dt])
+    ctx.advance([a], [dt], prec=prec)
+    ctx.advance([c, d], [dt, dt], prec=prec)
     same(full(a), full(c))
     T1, Y1, _, _, it1 = ctx.download(a)[:5]
     bounds = [5, 10, 20, 40, 80, 160, 320]
@@ -267,9 +268,9 @@ def test_cost_order_is_bitwise_neutral(ctx, case):
     # second step: a in the order of its counts; b (fresh, same state) and c (batched, index order)
     e0 = ctx.download_e0(a)
     b = ctx.state_upload(mid, st.rho, T1, Y1, e0=e0)
-    ctx.advance([a], [dt])
-    ctx.advance([b], [dt])
-    ctx.advance([c, d], [dt, dt])
+    ctx.advance([a], [dt], prec=prec)
+    ctx.advance([b], [dt], prec=prec)
+    ctx.advance([c, d], [dt, dt], prec=prec)
     same(full(a), full(b))
     same(full(a), full(c))
     report(f"cost order {case}", dict(cells=n, classes=np.bincount(np.digitize(it1, bounds), minlength=8).tolist()))
