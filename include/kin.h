@@ -131,37 +131,51 @@ typedef struct {
                              * times the previous iteration's (Newton diverging); 0 disables */
 } kin_solver_opts;
 
+/* Fill s with the defaults above.
+ * Paper: Sec. 3.2, Eq. "kinetics" (the implicit system these controls iterate); the
+ * constants themselves are this library's readings, the paper gives none. */
 void kin_default_solver_opts(kin_solver_opts *s);
 
-/* Message of the calling thread's last non-OK status ("" if none). */
+/* Message of the calling thread's last non-OK status ("" if none).
+ * Paper: no passage (error reporting of this library). */
 const char *kin_last_error(void);
 
-/* Create a context on a device.  o may be NULL (device 0, no budget, no tune cache). */
+/* Create a context on a device.  o may be NULL (device 0, no budget, no tune cache).
+ * Paper: Sec. 5.2, the device memory that bounds how many cells' Jacobians are held at once,
+ * which the optional budget caps. */
 kin_status kin_create(kin_ctx **out, const kin_ctx_opts *o);
 
-/* Free every device allocation and compiled module of the context.  Safe on NULL. */
+/* Free every device allocation and compiled module of the context.  Safe on NULL.
+ * Paper: no passage (resource release). */
 void kin_destroy(kin_ctx *ctx);
 
 /* Validate and copy a mechanism to the device; returns its id.  Validation: counts in
  * range, indices in range, coefficients 1..3, every reaction element-balanced, A > 0,
  * finite parameters, cp > 0 over [200, 6000] K, efficiencies >= 0.  Species count decides
  * the default layout (lane layout when ns <= 15); a mechanism that will run the lane
- * layout gets its kernels compiled here (hipRTC, gfx950). */
+ * layout gets its kernels compiled here (hipRTC, gfx950).
+ * Paper: Sec. 3.2, where species data and elementary reactions are read from data files
+ * separate from the solver; the reaction form, Arrhenius law, equilibrium constant and
+ * third-body sum that the tables parameterise are the equations of Sec. 3.2. */
 kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_id);
 
-/* KIN_EBUSY while instances still use the mechanism. */
+/* Release a mechanism's device tables and kernels.  KIN_EBUSY while instances still use it.
+ * Paper: Sec. 3.2 (the mechanism data uploaded by kin_mech_upload). */
 kin_status kin_mech_release(kin_ctx *ctx, int32_t mech_id);
 
 /* Copy n_cells cell states into a new device-resident instance of a mechanism.  rho, T,
  * Y (and e0) live in host or device memory as `where` says; device copies are enqueued on
  * `stream` (a hipStream_t, NULL = the null stream), host copies complete before return.
  * e0_or_null: per-cell internal energy e0 (J/kg) the step conserves; NULL computes
- * e0 = e(Y, T) on the device.  KIN_ENOMEM if the context budget would be exceeded. */
+ * e0 = e(Y, T) on the device.  KIN_ENOMEM if the context budget would be exceeded.
+ * Paper: Sec. 4.2, each cell's kinetics is independent of every other cell's, so cells are
+ * stored as independent structure-of-arrays records; Sec. 2, Eq. energy, for e0. */
 kin_status kin_state_upload(kin_ctx *ctx, int32_t mech_id, int64_t n_cells, const double *rho,
                             const double *T, const double *Y, const double *e0_or_null,
                             kin_mem where, void *stream, int32_t *inst_id);
 
-/* Overwrite an existing instance's state (same cell count) without allocating. */
+/* Overwrite an existing instance's state (same cell count) without allocating.
+ * Paper: Sec. 4.2 (independent cells), as kin_state_upload. */
 kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, const double *T,
                            const double *Y, const double *e0_or_null, kin_mem where,
                            void *stream);
@@ -178,14 +192,17 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
  * they are the octave of the temperature change the source term predicts over dt.  Each class
  * keeps index order.  This shortens the launch's tail; every cell's result is bitwise the
  * same in any order.  Advances of one instance must be ordered on one stream (or
- * synchronised), as the order is computed on `stream` from the previous advance's iters. */
+ * synchronised), as the order is computed on `stream` from the previous advance's iters.
+ * Paper: Sec. 3.2, Eq. "kinetics", solved by Gaussian elimination per cell; Sec. 4.2, one
+ * independent system per cell; iteration and halving are this library's additions. */
 kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
                        kin_precision prec, const kin_solver_opts *s, void *stream);
 
 /* Copy an instance's state (T[n], Y[Ns][n]), the conserved internal energy e0[n] and the
  * per-cell diagnostics of the last advance into caller buffers; any pointer may be NULL.
  * Re-uploading T, Y with this e0 resumes the run bitwise (checkpoint / restart).
- * Host destinations: synchronous.  Device destinations: enqueued on `stream`. */
+ * Host destinations: synchronous.  Device destinations: enqueued on `stream`.
+ * Paper: Sec. 4.2 (independent per-cell results of the system of Sec. 3.2, Eq. "kinetics"). */
 kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,
                         int32_t *status, int32_t *level, int32_t *iters, kin_mem where,
                         void *stream);
@@ -193,7 +210,9 @@ kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, dou
 /* Per-cell sub-step schedule of the last advance: a 64-bit FNV-1a hash of the sequence of
  * sub-step attempts, starting from 0xcbf29ce484222325 and folding in, per attempt at level l,
  * h = (h ^ (2 l + accepted)) * 0x100000001b3.  Two runs whose hashes agree took the same
- * sub-steps, so their results differ only by arithmetic, not by the step sizes taken. */
+ * sub-steps, so their results differ only by arithmetic, not by the step sizes taken.
+ * Paper: Sec. 3.2, Eq. "kinetics" (the sub-steps over which it is solved; halving itself is
+ * this library's addition). */
 kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched, kin_mem where,
                                  void *stream);
 
@@ -211,13 +230,15 @@ kin_status kin_download_schedule(kin_ctx *ctx, int32_t inst_id, uint64_t *sched,
  * (NULL: 1500 K) with a bisection fallback; a cell without a root gets T = NaN, which the next
  * kin_advance reports as bad input.  All three arrays live where `where` says (host copies
  * complete before return); the conversion runs on the device on `stream`.  Errors as
- * kin_state_upload. */
+ * kin_state_upload.
+ * Paper: Sec. 2, Eq. energy (formation energies left out of E) and Eq. operator_splitting. */
 kin_status kin_state_upload_conserved(kin_ctx *ctx, int32_t mech_id, int64_t n_cells,
                                       const double *rho_s, const double *E_sens,
                                       const double *T_guess, kin_mem where, void *stream,
                                       int32_t *inst_id);
 
-/* The same conversion into an existing instance of the same cell count, without allocating. */
+/* The same conversion into an existing instance of the same cell count, without allocating.
+ * Paper: Sec. 2, Eq. energy and Eq. operator_splitting, as kin_state_upload_conserved. */
 kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double *rho_s,
                                      const double *E_sens, const double *T_guess, kin_mem where,
                                      void *stream);
@@ -227,27 +248,35 @@ kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double
  * E_sens after a step differs from E_sens before it by minus the change of formation energy,
  * sum_s (rho_s,before - rho_s,after) e_s(T_ref): the source term of the energy equation.
  * Device destinations: computed in place on `stream`.  Host or pinned destinations: through a
- * stream-ordered device staging buffer; host copies complete before return. */
+ * stream-ordered device staging buffer; host copies complete before return.
+ * Paper: Sec. 2, Eq. energy (the source term carries the change of formation energy) and
+ * Eq. operator_splitting. */
 kin_status kin_download_conserved(kin_ctx *ctx, int32_t inst_id, double *rho_s, double *E_sens,
                                   kin_mem where, void *stream);
 
-/* Wait for `stream` (NULL = the null stream). */
+/* Wait for `stream` (NULL = the null stream).
+ * Paper: no passage (stream synchronisation). */
 kin_status kin_sync(kin_ctx *ctx, void *stream);
 
 /* A stream (default priority) whose kernels run only on compute units [cu_begin, cu_end) of
  * the context's device, for a serving loop that keeps some units free of long launches so
- * that short requests do not queue behind them (Sec. 4.3 processes the domain in segments to
- * bound resources; this bounds compute units instead).  *stream receives a hipStream_t the
+ * that short requests do not queue behind them.  *stream receives a hipStream_t the
  * caller passes to kin_advance etc. and releases with kin_stream_destroy.  KIN_EINVAL unless
- * 0 <= cu_begin < cu_end <= number of compute units. */
+ * 0 <= cu_begin < cu_end <= number of compute units.
+ * Paper: Sec. 5.2, which processes the domain in segments large enough to fill the device;
+ * this bounds the compute units a launch may occupy instead of its cells. */
 kin_status kin_stream_create(kin_ctx *ctx, int32_t cu_begin, int32_t cu_end, void **stream);
+/* Destroy a stream made by kin_stream_create.  Paper: Sec. 5.2, as kin_stream_create. */
 kin_status kin_stream_destroy(kin_ctx *ctx, void *stream);
 
 /* Free an instance.  Work already enqueued on it must have completed (with a budget pool the
- * memory goes straight back to the pool, without a device synchronisation). */
+ * memory goes straight back to the pool, without a device synchronisation).
+ * Paper: Sec. 5.2 (segments of the domain held one after another within the device memory). */
 kin_status kin_instance_release(kin_ctx *ctx, int32_t inst_id);
 
-/* Device bytes an instance of n_cells cells of a mechanism occupies. */
+/* Device bytes an instance of n_cells cells of a mechanism occupies (admission by footprint).
+ * Paper: Sec. 5.2, where the per-cell memory limits the cells processed at once and the domain
+ * is split into segments that fit. */
 kin_status kin_footprint(const kin_ctx *ctx, int32_t mech_id, int64_t n_cells,
                          kin_precision prec, uint64_t *bytes);
 
@@ -261,10 +290,14 @@ typedef enum {
     KIN_Q_LARGEST_FREE = 6    /* out: uint64 largest free block of the budget pool (0 without one) */
 } kin_query_what;
 
+/* Report what kin_query_what names.  Paper: Sec. 5.2 (memory in use against the device's), and
+ * Sec. 4.2 (the kernel layout chosen for a mechanism). */
 kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
 
 /* Set a mechanism's layout and block size (what the autotuner decides): lane 64/128/256
- * threads, wave 1..4 wavefronts, global 64 threads per block. */
+ * threads, wave 1..4 wavefronts, global 64 threads per block.
+ * Paper: Sec. 4.1, block size as a tuning parameter; Sec. 4.2, the choice between keeping the
+ * Jacobian in global memory or in on-chip memory. */
 kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
 
 /* Autotuner: time one advance of an existing instance with every admissible kernel layout
@@ -272,12 +305,15 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
  * ns <= 15; wave layout with 1, 2 or 4 wavefronts per block), keep the fastest for the
  * mechanism and record it in the context's tune cache file (JSON, keyed by a hash of the
  * mechanism, the precision and the device), from which kin_mech_upload applies it later.
- * The instance's state is restored afterwards.  Outputs may be NULL. */
+ * The instance's state is restored afterwards.  Outputs may be NULL.
+ * Paper: Sec. 4.1 (block size tuned by measurement) and Sec. 4.2 (global versus on-chip
+ * memory for the Jacobian, chosen by measurement). */
 kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double dt,
                         kin_precision prec, int32_t *layout, int32_t *block, double *best_ms);
 
 /* Generate the lane-layout source for a mechanism and compile it for gfx950 with hipRTC,
- * without a device.  log (may be NULL) receives up to log_len bytes of compiler output. */
+ * without a device.  log (may be NULL) receives up to log_len bytes of compiler output.
+ * Paper: Sec. 3.2 (the mechanism from data files, here validated and compiled). */
 kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len);
 
 #ifdef __cplusplus

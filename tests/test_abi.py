@@ -73,3 +73,39 @@ def test_c_program_compiles_against_header(tmp_path):
     r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), src,
                         "-L", libdir, "-lkin", "-lm", "-o", str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+# Sections of the paper (Le & Cambier, arXiv:1110.4903): 1 Introduction, 2 Governing
+# Equations, 3 Numerical Formulation (3.1 Fluid Dynamics, 3.2 Chemical Kinetics), 4 GPU
+# Implementation (4.1 Computational Fluid Dynamics, 4.2 Chemical Kinetics), 5 Results (5.1 Solver
+# Results, 5.2 Performance Results), 6 Conclusion, Appendix A.
+PAPER_SECTIONS = {"1", "2", "3", "3.1", "3.2", "4", "4.1", "4.2", "5", "5.1", "5.2", "6"}
+# Calls that serve no passage of the paper (library plumbing) say so explicitly.
+PLUMBING = {"kin_last_error", "kin_destroy", "kin_sync"}
+
+
+def export_comments():
+    """The comment block directly above each declared export (its contract)."""
+    src = open(os.path.join(ROOT, "include", "kin.h")).read()
+    out = {}
+    for m in re.finditer(r"/\*((?:(?!\*/).)*)\*/\s*(?:kin_status|void|const char \*)\s*(kin_\w+)\s*\(", src, re.S):
+        out[m.group(2)] = m.group(1)
+    return out
+
+
+def test_every_export_cites_the_paper():
+    """Each exported call's comment has a 'Paper:' line; every call that is not plumbing names
+    at least one section, and every section cited anywhere in the header exists in the paper."""
+    comments = export_comments()
+    names = declared_functions()
+    assert set(comments) == set(names), set(names) ^ set(comments)
+    src = open(os.path.join(ROOT, "include", "kin.h")).read()
+    for sec in re.findall(r"Sec\. (\d+(?:\.\d+)?)", src):
+        assert sec in PAPER_SECTIONS, sec
+    for n, c in comments.items():
+        assert "Paper:" in c, n
+        cite = c[c.index("Paper:"):]
+        if n in PLUMBING:
+            assert "no passage" in cite, n
+        else:
+            assert re.search(r"Sec\. \d", cite), n
