@@ -198,6 +198,20 @@ kin_status kin_state_reset(kin_ctx *ctx, int32_t inst_id, const double *rho, con
 kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
                        kin_precision prec, const kin_solver_opts *s, void *stream);
 
+/* kin_advance of one instance that also records every cell's sub-step schedule, for checking
+ * a result against a reference that follows the same sub-steps.  trace: device memory of
+ * n_cells * words uint64 (caller-owned, words 2..4096); cell i's record is trace[i * words ..]:
+ * word 0 the number of sub-step attempts, words 1.. their outcomes, attempt j accepted iff bit
+ * j % 64 of word 1 + j / 64 is set (the first 64 (words - 1) attempts are recorded; the count
+ * is always complete).  The sub-step sizes follow from the outcomes: a rejection retries the
+ * same start at the next level, an acceptance at level l advances by dt 2^-l and drops a level
+ * when the elapsed time is aligned to the coarser grid.  The cells' arithmetic, results and
+ * diagnostics are those of kin_advance (cells taken in index order); the lane layout runs a
+ * separately compiled build of its kernels with the recorder.  Enqueued on `stream`.
+ * Paper: Sec. 3.2, Eq. "kinetics" (the sub-steps over which it is solved). */
+kin_status kin_advance_trace(kin_ctx *ctx, int32_t inst_id, double dt, kin_precision prec,
+                             const kin_solver_opts *s, int32_t words, uint64_t *trace, void *stream);
+
 /* Copy an instance's state (T[n], Y[Ns][n]), the conserved internal energy e0[n] and the
  * per-cell diagnostics of the last advance into caller buffers; any pointer may be NULL.
  * Re-uploading T, Y with this e0 resumes the run bitwise (checkpoint / restart).
@@ -287,32 +301,41 @@ typedef enum {
     KIN_Q_NUM_CU = 3,         /* out: int32 */
     KIN_Q_DEVICE_PTRS = 4,    /* arg: instance id; out: 7 x uint64 rho, e0, T, Y, status, level, iters */
     KIN_Q_JIT_SECONDS = 5,    /* arg: mech id; out: double compile time of its lane kernels */
-    KIN_Q_LARGEST_FREE = 6    /* out: uint64 largest free block of the budget pool (0 without one) */
+    KIN_Q_LARGEST_FREE = 6,   /* out: uint64 largest free block of the budget pool (0 without one) */
+    KIN_Q_TUNED = 7           /* arg: mech id; out: int32[20], (layout, block) autotuned for
+                               * precision p and size class c at [2 (5 p + c)], -1 where none */
 } kin_query_what;
 
 /* Report what kin_query_what names.  Paper: Sec. 5.2 (memory in use against the device's), and
  * Sec. 4.2 (the kernel layout chosen for a mechanism). */
 kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
 
-/* Set a mechanism's layout and block size (what the autotuner decides): lane 64/128/256
- * threads, wave 1..4 wavefronts, global 64 threads per block.
+/* Set a mechanism's layout and block size for every launch: lane 64/128/256 threads, wave 1..4
+ * wavefronts, global 64 threads per block.  Drops the autotuner's per-size choices.
  * Paper: Sec. 4.1, block size as a tuning parameter; Sec. 4.2, the choice between keeping the
  * Jacobian in global memory or in on-chip memory. */
 kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
 
 /* Autotuner: time one advance of an existing instance with every admissible kernel layout
  * and block size of its mechanism (lane layout with 64, 128 or 256 threads per block when
- * ns <= 15; wave layout with 1, 2 or 4 wavefronts per block), keep the fastest for the
- * mechanism and record it in the context's tune cache file (JSON, keyed by a hash of the
- * mechanism, the precision and the device), from which kin_mech_upload applies it later.
- * The instance's state is restored afterwards.  Outputs may be NULL.
+ * ns <= 15; wave layout with 1, 2 or 4 wavefronts per block; the global layout above 63
+ * species), and keep the fastest for launches of the instance's size class and this
+ * precision.  Size classes of a launch's cell count (a batched advance counts all instances
+ * of a mechanism together): below 4096, 16384, 65536, 262144, and the rest.  A launch of a
+ * class and precision without a tuned entry uses the mechanism's layout (kin_set_layout, or
+ * the default by species count); kin_set_layout drops the tuned entries.  Each choice is also
+ * recorded in the context's tune cache file (JSON, keyed by a hash of the mechanism, the
+ * precision, the size class and the device), from which kin_mech_upload applies it later.
+ * Tune at the cell count the launches will have.  The instance's state is restored
+ * afterwards.  Outputs may be NULL.
  * Paper: Sec. 4.1 (block size tuned by measurement) and Sec. 4.2 (global versus on-chip
  * memory for the Jacobian, chosen by measurement). */
 kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double dt,
                         kin_precision prec, int32_t *layout, int32_t *block, double *best_ms);
 
 /* Generate the lane-layout source for a mechanism and compile it for gfx950 with hipRTC,
- * without a device.  log (may be NULL) receives up to log_len bytes of compiler output.
+ * without a device, both as kin_advance runs them and with the schedule recorder of
+ * kin_advance_trace.  log (may be NULL) receives up to log_len bytes of compiler output.
  * Paper: Sec. 3.2 (the mechanism from data files, here validated and compiled). */
 kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len);
 

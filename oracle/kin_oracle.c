@@ -447,6 +447,69 @@ int orc_advance_cell(const orc_mech *m, double rho, double e0, double *T, double
     return failed ? ORC_OK_HALVED : ORC_OK;
 }
 
+int orc_follow_cell(const orc_mech *m, double rho, double e0, double *T, double *Y, long stride,
+                    double dt, const orc_opts *o, const unsigned long long *bits, long count,
+                    int *level, int *iters, unsigned long long *sched)
+{
+    int ns = m->ns, N = ns + 1;
+    double xn[ORC_NS_MAX + 1], x[ORC_NS_MAX + 1];
+    *level = 0;
+    *iters = 0;
+    *sched = ORC_SCHED_SEED;
+    for (int s = 0; s < ns; ++s) xn[s] = Y[s * stride];
+    xn[ns] = *T;
+    if (!all_finite(xn, N) || !isfinite(rho) || !(rho > 0) || !isfinite(e0) || !isfinite(dt) ||
+        !(dt >= 0) || xn[ns] < ORC_T_MIN || xn[ns] > ORC_T_MAX)
+        return ORC_BAD_INPUT;
+    /* an accepted attempt is solved to convergence: no divergence test, at least 50 iterations */
+    orc_opts solve = *o;
+    solve.diverge_ratio = 0.0;
+    if (solve.k_max < 50) solve.k_max = 50;
+    memcpy(x, xn, sizeof(double) * N);
+    const long long end = 1LL << o->L_max;
+    long long t = 0;
+    int l = 0, failed = 0;
+    for (long j = 0; j < count && t < end; ++j) {
+        int accepted = (int)((bits[j / 64] >> (j % 64)) & 1ULL);
+        *sched = sched_step(*sched, l, accepted);
+        if (accepted) {
+            if (orc_be_substep(m, rho, e0, x, ldexp(dt, -l), &solve, iters, 0) != 0) return -1;
+            t += 1LL << (o->L_max - l);
+            if (l > 0 && (t & ((1LL << (o->L_max - l + 1)) - 1)) == 0) --l;
+        } else {
+            failed = 1;
+            ++l;
+            if (l > *level) *level = l;
+            if (l > o->L_max) { *level = o->L_max; break; }
+        }
+    }
+    if (t < end) return ORC_FAILED;
+    for (int s = 0; s < ns; ++s) Y[s * stride] = x[s];
+    *T = x[ns];
+    return failed ? ORC_OK_HALVED : ORC_OK;
+}
+
+void orc_follow(const orc_mech *m, long n, const double *rho, const double *e0, double *T, double *Y,
+                double dt, const orc_opts *o, const unsigned long long *trace, int words, int *status,
+                int *level, int *iters, unsigned long long *sched, int nthreads)
+{
+    if (nthreads <= 0) nthreads = orc_num_threads();
+    long i;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (i = 0; i < n; ++i) {
+        const unsigned long long *tr = trace + (size_t)i * words;
+        const long count = (long)tr[0];
+        int lv = 0, it = 0, st;
+        unsigned long long sh = ORC_SCHED_SEED;
+        if (count > 64L * (words - 1)) st = -2;
+        else st = orc_follow_cell(m, rho[i], e0[i], &T[i], &Y[i], n, dt, o, tr + 1, count, &lv, &it, &sh);
+        status[i] = st;
+        level[i] = lv;
+        iters[i] = it;
+        sched[i] = sh;
+    }
+}
+
 void orc_advance(const orc_mech *m, long n, const double *rho, const double *e0, double *T,
                  double *Y, double dt, const orc_opts *o, int L_forced, int *status, int *level,
                  int *iters, unsigned long long *sched, int nthreads)

@@ -120,6 +120,30 @@ void orc_advance(const orc_mech *m, long n, const double *rho, const double *e0,
                  double *T, double *Y, double dt, const orc_opts *o, int L_forced,
                  int *status, int *level, int *iters, unsigned long long *sched, int nthreads);
 
+/* Advance one cell along a given sub-step schedule instead of choosing it: attempt j of the
+ * schedule (bit j % 64 of word j / 64 of bits[]) was accepted (1) or rejected (0) by another
+ * implementation.  The sub-step sizes follow from those bits by the adaptive rule of
+ * orc_advance_cell (a rejection retries the same start at level l + 1, an acceptance at level l
+ * advances by dt 2^-l and drops a level when the elapsed time is aligned to the coarser grid).
+ * A rejected attempt is skipped; an accepted one is the backward-Euler sub-step solved to
+ * convergence from the last accepted state (Newton without the divergence test and with at
+ * least 50 iterations, then the temperature inversion).  So the result is this oracle's
+ * backward-Euler solution over exactly the other side's sub-steps.
+ * Returns ORC_OK or ORC_OK_HALVED when the schedule covers dt, ORC_FAILED (state unchanged)
+ * when it ends before dt (the other side failed the cell), ORC_BAD_INPUT on bad input, and -1
+ * when an attempt the schedule accepts does not converge here (result undefined).
+ * *level, *iters and *sched are as for orc_advance_cell (sched over the given schedule). */
+int orc_follow_cell(const orc_mech *m, double rho, double e0, double *T, double *Y, long stride,
+                    double dt, const orc_opts *o, const unsigned long long *bits, long count,
+                    int *level, int *iters, unsigned long long *sched);
+
+/* Batch form: trace[n][words], word 0 of a cell the number of attempts, words 1.. their bits
+ * (a cell whose count exceeds 64 (words - 1) gets status -2: schedule not recorded in full). */
+void orc_follow(const orc_mech *m, long n, const double *rho, const double *e0, double *T,
+                double *Y, double dt, const orc_opts *o, const unsigned long long *trace,
+                int words, int *status, int *level, int *iters, unsigned long long *sched,
+                int nthreads);
+
 /* Schedule hash: h0 = ORC_SCHED_SEED, then h = (h ^ (2 l + accepted)) * ORC_SCHED_PRIME per
  * sub-step attempt at level l (FNV-1a over the attempt codes). */
 #define ORC_SCHED_SEED 0xcbf29ce484222325ULL

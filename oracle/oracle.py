@@ -69,6 +69,7 @@ def lib():
         L.orc_invert_T.argtypes = [vp, vp, d, d, vp]; L.orc_invert_T.restype = i
         L.orc_be_substep.argtypes = [vp, d, d, vp, d, vp, vp, vp]; L.orc_be_substep.restype = i
         L.orc_advance.argtypes = [vp, l, vp, vp, vp, vp, d, vp, i, vp, vp, vp, vp, i]
+        L.orc_follow.argtypes = [vp, l, vp, vp, vp, vp, d, vp, vp, i, vp, vp, vp, vp, i]
         L.orc_energy_batch.argtypes = [vp, l, vp, vp, vp]
         L.orc_residual_ld.argtypes = [vp, d, vp, vp, d, vp, vp]; L.orc_residual_ld.restype = d
         L.orc_term_scale.argtypes = [vp, d, vp, vp, d, vp]
@@ -246,6 +247,24 @@ class OracleMech:
         if with_sched:
             return T, Y, st, lv, it, sh
         return T, Y, st, lv, it
+
+    def follow(self, rho, T, Y, dt: float, e0, trace, opts: Optional[Opts] = None, nthreads: int = 0):
+        """Advance cells along given sub-step schedules (trace[n][words]: word 0 the attempt
+        count, then the accept bits); returns (T, Y, status, level, iters, sched) as new arrays.
+        status -1: an attempt the schedule accepts does not converge here; -2: schedule
+        truncated."""
+        rho = np.ascontiguousarray(rho, np.float64)
+        n = rho.shape[0]
+        T = np.array(T, dtype=np.float64)
+        Y = np.array(Y, dtype=np.float64).reshape(self.ns, n)
+        e0 = np.ascontiguousarray(e0, np.float64)
+        trace = np.ascontiguousarray(trace, np.uint64)
+        assert trace.ndim == 2 and trace.shape[0] == n
+        st, lv, it = (np.zeros(n, np.int32) for _ in range(3))
+        sh = np.zeros(n, np.uint64)
+        lib().orc_follow(self.ref, n, _p(rho), _p(e0), _p(T), _p(Y), float(dt), C.byref(opts or default_opts()),
+                         _p(trace), int(trace.shape[1]), _p(st), _p(lv), _p(it), _p(sh), int(nthreads))
+        return T, Y, st, lv, it, sh
 
 
 def lu_factor(A):

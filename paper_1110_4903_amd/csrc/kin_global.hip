@@ -673,6 +673,8 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
             fin = fin && __builtin_isfinite(x[m]);
         }
         const double T0 = ar.T[cell];
+        ScheduleTrace tr;
+        tr.start(a.trace, a.trace_words, a.span[j].start + cell);
         const bool bad = __any(!fin) || !__builtin_isfinite(rho) || !(rho > 0.0) || !__builtin_isfinite(e0) ||
                          !__builtin_isfinite(dt) || !(dt >= 0.0) || T0 < gTmin || T0 > gTmax;
         if (bad) {
@@ -682,6 +684,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
                 ar.iters[cell] = 0;
                 ar.sched[cell] = 0xcbf29ce484222325ull;
             }
+            tr.finish(lane);
             continue;
         }
         unsigned long long tt = 0, hsh = 0xcbf29ce484222325ull;
@@ -755,6 +758,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
             if (outcome == G_CONTINUE && ++k >= a.k_max) outcome = G_FAILED;
             if (outcome == G_CONTINUE) continue;
             hsh = (hsh ^ (unsigned long long)(2 * l + (outcome == G_ACCEPTED ? 1 : 0))) * 0x100000001b3ull;
+            tr.add(outcome == G_ACCEPTED, lane);
             k = 0;
             if (outcome == G_ACCEPTED) {
 #pragma unroll
@@ -789,6 +793,7 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
             ar.iters[cell] = iters;
             ar.sched[cell] = hsh;
         }
+        tr.finish(lane);
     }
 }
 }  // namespace

@@ -187,6 +187,12 @@ struct AdvanceArgs {
     double diverge_ratio;            // > 0: fail an attempt whose update norm grows by more
     const double *K;                 // lane layout: the mechanism's constant table
     unsigned long long *counter;     // next unclaimed cell (zero at launch)
+    // diagnostic sub-step schedule of every cell, or null: trace[g * trace_words + w] for the
+    // cell at launch position g (span start + cell): word 0 the number of sub-step attempts,
+    // words 1.. their accept bits (attempt j: bit j % 64 of word 1 + j / 64), recorded up to
+    // 64 (trace_words - 1) attempts
+    unsigned long long *trace;
+    int trace_words;
 };
 
 // Host launchers of the precompiled kernels (kin_wave.hip).

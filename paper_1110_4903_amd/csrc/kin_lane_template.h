@@ -32,6 +32,10 @@ struct KinLaneArgs {
     double diverge_ratio; // > 0: fail an attempt whose update norm grows by more than this
     const double *K;      // the mechanism's constant table (KIN_NCONST values)
     unsigned long long *counter;  // next unclaimed global cell; zero at launch
+    // diagnostic sub-step schedules (recorded only by a module compiled with KIN_TRACE): cell
+    // at launch position g has trace[g * trace_words ...]: the attempt count, then accept bits
+    unsigned long long *trace;
+    int trace_words;
 };
 
 // Arena of an instance of n cells: rho[n] e0[n] T[n] Y[ns][n] sched[n] as 8-byte arrays, then
@@ -287,6 +291,9 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     int l = 0, k = 0, iters = 0, level = 0;
     bool failed = false;
     double r_prev = -1.0;  // weighted norm of the previous update of the current attempt
+#ifdef KIN_TRACE
+    unsigned long long *tr = nullptr;  // this cell's schedule record
+#endif
 
     for (;;) {
         // ---- hand new cells to lanes that need one ----------------------------------------
@@ -315,6 +322,10 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                         const long long c = a.span[j].order[i];
                         if ((unsigned long long)c < (unsigned long long)nspan_cells) i = c;
                     }
+#ifdef KIN_TRACE
+                    tr = a.trace + (size_t)(a.span[j].start + i) * a.trace_words;
+                    tr[0] = 0;
+#endif
                     need = false;
                     const double *Yin = kin_Y(base, nspan_cells);
                     rho = kin_rho(base, nspan_cells)[i];
@@ -364,6 +375,16 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
             }
             if (outcome != KIN_CONTINUE)
                 hsh = (hsh ^ (unsigned long long)(2 * l + (outcome == KIN_ACCEPTED))) * KIN_SCHED_PRIME;
+#ifdef KIN_TRACE
+            if (outcome != KIN_CONTINUE) {
+                const unsigned long long na = tr[0];
+                if (na < 64ull * (unsigned long long)(a.trace_words - 1)) {
+                    const unsigned long long bit = (unsigned long long)(outcome == KIN_ACCEPTED) << (na & 63);
+                    tr[1 + (na >> 6)] = ((na & 63) ? tr[1 + (na >> 6)] : 0ull) | bit;
+                }
+                tr[0] = na + 1;
+            }
+#endif
             if (outcome == KIN_ACCEPTED) {
 #pragma unroll
                 for (int s = 0; s < KIN_N; ++s) x[s] = xk[s];

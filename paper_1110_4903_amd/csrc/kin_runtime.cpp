@@ -31,8 +31,15 @@ struct Mech {
     int block = 64;          // lane layout: threads per block; wave layout: waves per block
     hipModule_t mod = nullptr;
     hipFunction_t lane_f64 = nullptr, lane_f32 = nullptr, lane_cost = nullptr;
+    // the same lane kernels compiled with the schedule recorder (kin_advance_trace only)
+    hipModule_t mod_tr = nullptr;
+    hipFunction_t lane_f64_tr = nullptr, lane_f32_tr = nullptr;
+    int lane_block_tr = 0;
     double *kconst = nullptr;  // constant table of the lane kernels
     int lane_block = 0;      // block size the module was compiled for
+    // autotuned (layout, block) per (precision, size class of the launch's cell count); a launch
+    // of a class without an entry uses (layout, block) above
+    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
     double jit_seconds = 0.0;
     int refs = 0;
 };
@@ -230,6 +237,7 @@ void kin_destroy(kin_ctx *ctx)
             for (auto &kv : ctx->insts) hipFree(kv.second->buf);
         for (auto &kv : ctx->mechs) {
             if (kv.second->mod) hipModuleUnload(kv.second->mod);
+            if (kv.second->mod_tr) hipModuleUnload(kv.second->mod_tr);
             hipFree(kv.second->dbuf);
             hipFree(kv.second->kconst);
         }
@@ -272,6 +280,38 @@ static kin_status build_lane(kin_ctx *ctx, Mech &m, int block)
     KIN_HIP(ctx, hipModuleGetFunction(&m.lane_cost, m.mod, "kin_lane_cost"));
     m.lane_block = block;
     m.jit_seconds += secs;
+    return KIN_OK;
+}
+
+// Lane-layout kernels with the schedule recorder (KIN_TRACE), compiled on first use.
+static kin_status build_lane_trace(kin_ctx *ctx, Mech &m, int block)
+{
+    if (m.mod_tr && m.lane_block_tr == block) return KIN_OK;
+    kin_status s = build_lane(ctx, m, block);  // the constant table
+    if (s != KIN_OK) return s;
+    std::vector<double> consts;
+    const std::string src = "#define KIN_TRACE 1\n" + lane_source(m.h, block, consts);
+    std::vector<char> code;
+    {
+        std::lock_guard<std::mutex> lk(g_jit_mu);
+        auto it = g_jit_cache.find(src);
+        if (it != g_jit_cache.end()) {
+            code = it->second.first;
+        } else {
+            std::string msg;
+            double secs = 0.0;
+            if ((s = rtc_compile(src, "kin_lane_trace.hip", code, msg, &secs)) != KIN_OK) return err(s, msg);
+            g_jit_cache.emplace(src, std::make_pair(code, secs));
+        }
+    }
+    if (m.mod_tr) {
+        hipModuleUnload(m.mod_tr);
+        m.mod_tr = nullptr;
+    }
+    KIN_HIP(ctx, hipModuleLoadData(&m.mod_tr, code.data()));
+    KIN_HIP(ctx, hipModuleGetFunction(&m.lane_f64_tr, m.mod_tr, "kin_lane_f64"));
+    KIN_HIP(ctx, hipModuleGetFunction(&m.lane_f32_tr, m.mod_tr, "kin_lane_f32lu"));
+    m.lane_block_tr = block;
     return KIN_OK;
 }
 
@@ -528,8 +568,19 @@ kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_i
         m->layout = KIN_LAYOUT_GLOBAL;
         m->block = 64;
     }
-    {   // a tuned choice (FP64 entry) from the cache file, if any
+    {   // tuned choices from the cache file, if any: per (precision, size class) ...
         const auto cache = tune_read(ctx->tune_cache);
+        for (int prec : {(int)KIN_FP64, (int)KIN_FP32_LU})
+            for (int c = 0; c <= 4; ++c) {
+                auto it = cache.find(tune_key(ctx, *m, prec) + "-c" + std::to_string(c));
+                if (it == cache.end() || it->second.size() < 2) continue;
+                const int lay = (int)it->second[0], blk = (int)it->second[1];
+                const bool ok = (lay == KIN_LAYOUT_WAVE && blk >= 1 && blk <= 4 && m->h.ns <= kWaveNsMax) ||
+                                (lay == KIN_LAYOUT_LANE && m->h.ns <= kLaneNsMax && (blk == 64 || blk == 128 || blk == 256)) ||
+                                (lay == KIN_LAYOUT_GLOBAL && blk == 64);
+                if (ok) m->tuned[{prec, c}] = {lay, blk};
+            }
+        // ... and a mechanism-wide FP64 entry of an earlier cache format
         auto it = cache.find(tune_key(ctx, *m, KIN_FP64));
         if (it != cache.end() && it->second.size() >= 2) {
             const int lay = (int)it->second[0], blk = (int)it->second[1];
@@ -559,6 +610,7 @@ kin_status kin_mech_release(kin_ctx *ctx, int32_t mech_id)
     if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
     if (it->second->refs > 0) return err(KIN_EBUSY, "mechanism still used by instances");
     if (it->second->mod) hipModuleUnload(it->second->mod);
+    if (it->second->mod_tr) hipModuleUnload(it->second->mod_tr);
     KIN_HIP(ctx, hipFree(it->second->dbuf));
     KIN_HIP(ctx, hipFree(it->second->kconst));
     ctx->mechs.erase(it);
@@ -589,6 +641,7 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
     }
     m.layout = layout;
     m.block = block;
+    m.tuned.clear();  // an explicit choice replaces the autotuned ones
     return KIN_OK;
 }
 
@@ -808,9 +861,27 @@ static void fill_opts(AdvanceArgs &a, const kin_solver_opts &o)
     }
 }
 
-// Effective (layout, block) of a mechanism for these options.
-static void layout_of(const Mech &m, const kin_solver_opts &o, int &layout, int &block)
+// Size class of a launch's cell count for the autotuner: below 4096, 16384, 65536, 262144, and
+// the rest.  A lane-layout launch fills the device's 65536 lanes only from the top class on,
+// so small launches can prefer another layout.
+static int size_class(long long cells)
 {
+    return cells < 4096 ? 0 : cells < 16384 ? 1 : cells < 65536 ? 2 : cells < 262144 ? 3 : 4;
+}
+
+// Effective (layout, block) of a mechanism for these options and a launch of `cells` cells:
+// an explicit layout in the options, else the autotuned choice for the launch's size class and
+// precision, else the mechanism's layout.
+static void layout_of(const Mech &m, const kin_solver_opts &o, int prec, long long cells, int &layout, int &block)
+{
+    if (o.layout == KIN_LAYOUT_AUTO) {
+        auto it = m.tuned.find({prec, size_class(cells)});
+        if (it != m.tuned.end()) {
+            layout = it->second.first;
+            block = it->second.second;
+            return;
+        }
+    }
     layout = o.layout == KIN_LAYOUT_AUTO ? m.layout : o.layout;
     if (layout == KIN_LAYOUT_LANE) block = (m.layout == KIN_LAYOUT_LANE) ? m.block : 64;
     else if (layout == KIN_LAYOUT_WAVE) block = (m.layout == KIN_LAYOUT_WAVE) ? m.block : 1;
@@ -845,9 +916,10 @@ static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precis
     a.ns = m.h.ns;
     if (layout == KIN_LAYOUT_LANE) {
         if (m.h.ns > kLaneNsMax) return err(KIN_EINVAL, "lane layout needs ns <= 15");
-        kin_status s = build_lane(ctx, m, block);
+        // a launch with a schedule trace runs the recorder build of the same kernels
+        kin_status s = a.trace ? build_lane_trace(ctx, m, block) : build_lane(ctx, m, block);
         if (s != KIN_OK) return s;
-        hipFunction_t fn = f32 ? m.lane_f32 : m.lane_f64;
+        hipFunction_t fn = a.trace ? (f32 ? m.lane_f32_tr : m.lane_f64_tr) : (f32 ? m.lane_f32 : m.lane_f64);
         int per_cu = 0;
         KIN_HIP(ctx, hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0));
         if (per_cu < 1) per_cu = 1;
@@ -882,30 +954,29 @@ static bool opts_ok(const kin_solver_opts &o)
            o.layout >= KIN_LAYOUT_AUTO && o.layout <= KIN_LAYOUT_GLOBAL && o.diverge_ratio >= 0;
 }
 
-// Batched advance: instances grouped by (mechanism, layout), at most kMaxSpans per launch, each
-// launch preceded by a kernel that zeroes its work counter, launches of different groups on
-// parallel branches; captured once into a graph and replayed while the description is unchanged.
-static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *dts, int n, kin_precision prec,
-                                const kin_solver_opts &o, hipStream_t user)
+// One kernel launch of a multi-instance advance: instances of one mechanism and layout, at most
+// kMaxSpans of them.
+struct Launch {
+    Mech *m;
+    int layout, block;
+    AdvanceArgs a;
+};
+
+// Group instances by (mechanism, layout), at most kMaxSpans per launch, in a fixed order.
+static void plan_launches(kin_ctx *ctx, const int32_t *ids, const double *dts, int n, const kin_solver_opts &o,
+                          int prec, std::vector<Launch> &launches)
 {
-    struct Launch {
-        Mech *m;
-        int layout, block;
-        AdvanceArgs a;
-    };
-    std::map<std::pair<int, int>, std::vector<int>> groups;  // (mech, layout) -> positions
+    std::map<int, std::vector<int>> groups;  // mechanism -> positions
+    std::map<int, long long> cells;          // mechanism -> cells over its instances
     for (int k = 0; k < n; ++k) {
         Inst &in = *ctx->insts[ids[k]];
-        Mech &m = *ctx->mechs[in.mech];
-        int layout, block;
-        layout_of(m, o, layout, block);
-        groups[{in.mech, layout}].push_back(k);
+        groups[in.mech].push_back(k);
+        cells[in.mech] += in.n;
     }
-    std::vector<Launch> launches;
     for (auto &g : groups) {
-        Mech &m = *ctx->mechs[g.first.first];
+        Mech &m = *ctx->mechs[g.first];
         int layout, block;
-        layout_of(m, o, layout, block);
+        layout_of(m, o, prec, cells[g.first], layout, block);
         for (size_t off = 0; off < g.second.size(); off += kMaxSpans) {
             Launch L;
             L.m = &m; L.layout = layout; L.block = block;
@@ -927,6 +998,16 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
             launches.push_back(L);
         }
     }
+}
+
+// Batched advance: instances grouped by (mechanism, layout), at most kMaxSpans per launch, each
+// launch preceded by a kernel that zeroes its work counter, launches of different groups on
+// parallel branches; captured once into a graph and replayed while the description is unchanged.
+static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *dts, int n, kin_precision prec,
+                                const kin_solver_opts &o, hipStream_t user)
+{
+    std::vector<Launch> launches;
+    plan_launches(ctx, ids, dts, n, o, prec, launches);
     const int nl = (int)launches.size();
     // key: everything the captured kernels depend on
     std::string key(reinterpret_cast<const char *>(&prec), sizeof prec);
@@ -1021,20 +1102,17 @@ static kin_status advance_batch(kin_ctx *ctx, const int32_t *ids, const double *
     return KIN_OK;
 }
 
-kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
-                       kin_precision prec, const kin_solver_opts *sopt, void *stream)
+// Arguments of an advance (either entry point); ctx->mu must be held for the instance checks.
+static kin_status check_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
+                                kin_precision prec, const kin_solver_opts *sopt, kin_solver_opts &o)
 {
-    kin_status s = enter(ctx);
-    if (s != KIN_OK) return s;
     if (n < 1 || !inst_ids || !dts) return err(KIN_EINVAL, "bad instance list");
     if (prec != KIN_FP64 && prec != KIN_FP32_LU) return err(KIN_EINVAL, "bad precision");
-    kin_solver_opts o;
     kin_default_solver_opts(&o);
     if (sopt) o = *sopt;
     if (!opts_ok(o)) return err(KIN_EINVAL, "bad solver options");
     if (o.point_implicit && prec != KIN_FP64)
         return err(KIN_EINVAL, "the point-implicit step has no Newton refinement and runs in FP64 only");
-    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     for (int k = 0; k < n; ++k) {
         auto it = ctx->insts.find(inst_ids[k]);
         if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
@@ -1042,6 +1120,17 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
         for (int q = 0; q < k; ++q)
             if (inst_ids[q] == inst_ids[k]) return err(KIN_EINVAL, "an instance appears twice in one advance");
     }
+    return KIN_OK;
+}
+
+kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
+                       kin_precision prec, const kin_solver_opts *sopt, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    kin_solver_opts o;
+    if ((s = check_advance(ctx, inst_ids, dts, n, prec, sopt, o)) != KIN_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (n > 1) {
         s = advance_batch(ctx, inst_ids, dts, n, prec, o, st);
@@ -1052,7 +1141,7 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     Inst &in = *ctx->insts[inst_ids[0]];
     Mech &m = *ctx->mechs[in.mech];
     int layout, block;
-    layout_of(m, o, layout, block);
+    layout_of(m, o, prec, in.n, layout, block);
     AdvanceArgs a;
     std::memset(&a, 0, sizeof a);
     fill_opts(a, o);
@@ -1083,6 +1172,37 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
             a.span[0].order = ar.order;
         }
     }
+    s = launch_spans(ctx, m, a, prec, layout, block, st);
+    if (s == KIN_OK) in.iters_current = true;
+    return s;
+}
+
+kin_status kin_advance_trace(kin_ctx *ctx, int32_t inst_id, double dt, kin_precision prec,
+                             const kin_solver_opts *sopt, int32_t words, uint64_t *trace, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    kin_solver_opts o;
+    if ((s = check_advance(ctx, &inst_id, &dt, 1, prec, sopt, o)) != KIN_OK) return s;
+    if (!trace || words < 2 || words > 4096) return err(KIN_EINVAL, "trace needs a buffer of 2..4096 words per cell");
+    Inst &in = *ctx->insts[inst_id];
+    Mech &m = *ctx->mechs[in.mech];
+    int layout, block;
+    layout_of(m, o, prec, in.n, layout, block);
+    AdvanceArgs a;
+    std::memset(&a, 0, sizeof a);
+    fill_opts(a, o);
+    a.span[0].n = in.n;
+    a.span[0].dt = dt;
+    a.span[0].base = static_cast<char *>(in.buf);
+    a.nspan = 1;
+    a.total = in.n;
+    a.counter = in.counter;
+    a.trace = reinterpret_cast<unsigned long long *>(trace);
+    a.trace_words = words;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
     s = launch_spans(ctx, m, a, prec, layout, block, st);
     if (s == KIN_OK) in.iters_current = true;
     return s;
@@ -1218,6 +1338,18 @@ kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out)
         else *static_cast<double *>(out) = it->second->jit_seconds;
         return KIN_OK;
     }
+    case KIN_Q_TUNED: {
+        auto it = ctx->mechs.find((int)arg);
+        if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
+        int32_t *p = static_cast<int32_t *>(out);
+        for (int prec = 0; prec < 2; ++prec)
+            for (int c = 0; c < 5; ++c) {
+                auto t = it->second->tuned.find({prec, c});
+                p[2 * (5 * prec + c)] = t == it->second->tuned.end() ? -1 : t->second.first;
+                p[2 * (5 * prec + c) + 1] = t == it->second->tuned.end() ? -1 : t->second.second;
+            }
+        return KIN_OK;
+    }
     case KIN_Q_DEVICE_PTRS: {
         auto it = ctx->insts.find((int)arg);
         if (it == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
@@ -1264,6 +1396,7 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     KIN_HIP(ctx, hipEventCreate(&e0));
     KIN_HIP(ctx, hipEventCreate(&e1));
     const int old_layout = m.layout, old_block = m.block;
+    const auto old_tuned = m.tuned;
     double best = 1e300;
     std::pair<int, int> win = {old_layout, old_block};
     kin_solver_opts o;
@@ -1290,13 +1423,14 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     hipFree(save);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (s != KIN_OK) {
-        kin_set_layout(ctx, mech_id, old_layout, old_block);
-        return s;
-    }
-    if ((s = kin_set_layout(ctx, mech_id, win.first, win.second)) != KIN_OK) return s;
+    // the mechanism keeps its default layout; the choice applies to launches of this size class
+    kin_set_layout(ctx, mech_id, old_layout, old_block);
+    m.tuned = old_tuned;
+    if (s != KIN_OK) return s;
+    const int cls = size_class(in.n);
+    m.tuned[{(int)prec, cls}] = win;
     auto cache = tune_read(ctx->tune_cache);
-    cache[tune_key(ctx, m, prec)] = {(double)win.first, (double)win.second, best};
+    cache[tune_key(ctx, m, prec) + "-c" + std::to_string(cls)] = {(double)win.first, (double)win.second, best};
     tune_write(ctx->tune_cache, cache);
     if (layout_out) *layout_out = win.first;
     if (block_out) *block_out = win.second;
@@ -1317,8 +1451,17 @@ kin_status kin_jit_check(const kin_mech_desc *d, char *log, size_t log_len)
             std::vector<char> code;
             std::vector<double> consts;
             double secs = 0.0;
-            s = rtc_compile(lane_source(h, 64, consts), "kin_lane.hip", code, msg, &secs);
-            if (s == KIN_OK) msg = "compiled " + std::to_string(code.size()) + " bytes in " + std::to_string(secs) + " s\n" + msg;
+            const std::string src = lane_source(h, 64, consts);
+            s = rtc_compile(src, "kin_lane.hip", code, msg, &secs);
+            if (s == KIN_OK) {
+                // and the build with the schedule recorder (kin_advance_trace)
+                std::vector<char> code_tr;
+                double secs_tr = 0.0;
+                s = rtc_compile("#define KIN_TRACE 1\n" + src, "kin_lane_trace.hip", code_tr, msg, &secs_tr);
+                if (s == KIN_OK)
+                    msg = "compiled " + std::to_string(code.size()) + " bytes in " + std::to_string(secs) +
+                          " s, with the schedule recorder " + std::to_string(code_tr.size()) + " bytes\n" + msg;
+            }
         }
     }
     if (log && log_len) {

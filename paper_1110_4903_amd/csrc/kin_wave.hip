@@ -547,11 +547,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
     int iters = 0, level = bad_in ? 0 : l, st = bad_in ? 3 : 0;
     bool failed = false;
     unsigned long long hsh = 0xcbf29ce484222325ull;  // FNV-1a of the sub-step attempts
+    ScheduleTrace tr;
+    tr.start(a.trace, a.trace_words, a.span[j].start + cell);
     while (tt < end) {
         if (iters >= a.max_iters) { st = 2; break; }
         const double h = ldexp(dt, -l);
         const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters, Ms, invMs);
         hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
+        tr.add(ok, lane);
         if (ok) {
             tt += 1ull << (Lc - l);
             if (adapt && l > 0 && (tt & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
@@ -574,6 +577,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
         ar.iters[cell] = iters;
         ar.sched[cell] = hsh;
     }
+    tr.finish(lane);
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n)

@@ -22,6 +22,41 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *uniform_ta
     return (const __attribute__((address_space(4))) T *)p;
 }
 
+// Diagnostic record of one cell's sub-step schedule (AdvanceArgs::trace), kept wave-uniform:
+// the attempts' accept bits fill a 64-bit word that lane 0 stores when it is full, and the
+// attempt count goes to word 0 at the end.  Inactive (p null) unless a trace was asked for.
+struct ScheduleTrace {
+    unsigned long long *p = nullptr;
+    long long cap = 0, n = 0;
+    unsigned long long w = 0;
+    __device__ void start(unsigned long long *base, int words, long long g)
+    {
+        p = base ? base + (size_t)g * words : nullptr;
+        cap = 64LL * (words - 1);
+        n = 0;
+        w = 0;
+    }
+    __device__ void add(bool accepted, int lane)
+    {
+        if (!p) return;
+        if (n < cap) {
+            w |= (unsigned long long)(accepted ? 1 : 0) << (n & 63);
+            if ((n & 63) == 63) {
+                if (lane == 0) p[1 + (n >> 6)] = w;
+                w = 0;
+            }
+        }
+        ++n;
+    }
+    __device__ void finish(int lane)
+    {
+        if (!p || lane != 0) return;
+        const long long rec = n < cap ? n : cap;
+        if (rec & 63) p[1 + (rec >> 6)] = w;
+        p[0] = (unsigned long long)n;
+    }
+};
+
 // ---- cross-lane helpers (all lanes of the wavefront must be active) ------------------------
 template <int CTRL>
 __device__ __forceinline__ int dpp(int v)

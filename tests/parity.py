@@ -79,3 +79,65 @@ def point_implicit_floor(om, rho, Y0, T0, Y1, T1, dt, eps):
         es = np.array([om.energy(unit[s], T1[c]) for s in range(ns)])
         ft[c] = np.abs(es) @ fy[:, c] / om.cv(Y1[:, c], T1[c])
     return fy, ft
+
+
+def gpu_traces(ctx, mech_id, st, dt, prec, opts=None, steps=1, words=64):
+    """Advance cells on the GPU with the schedule recorder, step by step: per step the schedule
+    record [n][words] and the GPU's (T, Y, status, level, iters, schedule hash) after it."""
+    iid = ctx.state_upload(mech_id, st.rho, st.T, st.Y)
+    traces, outs = [], []
+    for _ in range(steps):
+        traces.append(ctx.advance_trace(iid, dt, prec=prec, opts=opts, words=words))
+        outs.append(ctx.download(iid) + (ctx.download_schedule(iid),))
+    ctx.instance_release(iid)
+    return traces, outs
+
+
+def oracle_follow(om, st, dt, traces, opts=None, e0=None):
+    """The oracle advanced along the GPU's own sub-step schedules, step after step, from the same
+    inputs (its own e0 unless given): its backward-Euler solution over exactly the GPU's
+    sub-steps.  Returns (T, Y, status, level, iters, schedule hash) of the last step."""
+    e0 = om.energy_batch(st.T, st.Y) if e0 is None else e0
+    T, Y = st.T.copy(), st.Y.copy()
+    out = None
+    for tr in traces:
+        out = om.follow(st.rho, T, Y, dt, e0, tr, opts=opts)
+        T, Y = out[0], out[1]
+    return out
+
+
+def check_every_cell(ctx, orc, mech, mech_id, st, dt, prec, gpu, ref, rtol, opts=None, orc_opts=None,
+                     extra=None):
+    """Every cell of a single step, against the oracle.  Cells whose sub-step schedule matches the
+    oracle's own (status, level and schedule hash equal) are compared with the oracle's adaptive
+    result; the others are advanced again on the GPU with the schedule recorder, and compared with
+    the oracle following the GPU's schedule.  Returns the statistics of both comparisons and
+    their union; 'unchecked' counts cells of neither kind (it should be zero), 'follow_fail'
+    cells whose recorded schedule the oracle could not follow or whose recorded schedule's hash
+    differs from the first run's, and 'ok_vs_failed' cells that one side finished and the other
+    failed."""
+    om = orc.OracleMech(mech)
+    s = compare(gpu, ref, st.rho, st.Y, dt, om, rtol, extra=extra)
+    sg, sr = gpu[2], ref[2]
+    same = (sg == sr) & (gpu[3] == ref[3]) & (gpu[5] == ref[5])
+    mis = np.flatnonzero(~same)
+    out = dict(s)
+    out.update(followed=0, follow_fail=0, fail_Y_followed=0, fail_T_followed=0, max_rel_Y_followed=0.0,
+               max_rel_T_followed=0.0, ok_vs_failed=int(((sg < 2) != (sr < 2)).sum()))
+    if mis.size:
+        sub = st.subset(mis)
+        traces, g2 = gpu_traces(ctx, mech_id, sub, dt, prec, opts)
+        gsub = tuple(a[..., mis] for a in gpu)
+        rerun_same = all(np.array_equal(x, y, equal_nan=True) for x, y in zip(g2[-1], gsub))
+        fol = oracle_follow(om, sub, dt, traces, opts=orc_opts)
+        bad = (fol[2] < 0) | (fol[5] != gsub[5]) | (fol[2] != gsub[2])
+        ex = None if extra is None else (extra[0][:, mis], extra[1][mis])
+        s2 = compare(gsub, fol, sub.rho, sub.Y, dt, om, rtol, extra=ex)
+        out.update(followed=int(s2["compared"]), follow_fail=int(bad.sum()) + (0 if rerun_same else mis.size),
+                   fail_Y_followed=s2["fail_Y"], fail_T_followed=s2["fail_T"],
+                   max_rel_Y_followed=s2["max_rel_Y"], max_rel_T_followed=s2["max_rel_T"])
+    n_valid = int((sr < 3).sum())
+    out["checked"] = out["compared"] + out["followed"]
+    out["unchecked"] = n_valid - out["checked"] - int((sg == 2).sum())
+    out["failed_gpu"] = int((sg == 2).sum())
+    return out

@@ -1,7 +1,12 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle on the same
-seeded inputs.  Gate: 1e-10 relative per mass fraction and temperature for the FP64 form (with
-the term-scale floor of tests/parity.py), identical per-cell status, halving level and Newton
-iteration count."""
+seeded inputs.  Gate per mass fraction and temperature: 1e-10 relative for the FP64 form, 1e-6
+for the FP32-LU form (with the term-scale floor of tests/parity.py).  Every cell is compared:
+a cell whose sub-step schedule (status, halving level, schedule hash) matches the oracle's own
+is compared with the oracle's adaptive result, any other cell with the oracle following the
+GPU's recorded schedule (tests/parity.check_every_cell).  Schedule mismatches are counted and
+bounded; Newton iteration counts are reported, not compared (the FP32-LU form converges
+linearly, and the FP64 form's last iteration can differ by one where an update sits at the
+tolerance)."""
 import numpy as np
 import pytest
 
@@ -40,6 +45,25 @@ def report(name, s):
     print(f"\n[{name}] " + " ".join(f"{k}={v}" for k, v in s.items()), flush=True)
 
 
+def every_cell(ctx, orc, m, st, dt, prec, rtol, opts=None, mech_id=None, orc_kw=None, max_mismatch=2):
+    """Run the GPU and the oracle on the same cells and compare every cell (see check_every_cell);
+    asserts the gate on every cell, no cell finished on one side and failed on the other, and at
+    most max_mismatch schedule mismatches (a count, or a fraction of the cells when below 1)."""
+    from tests.parity import check_every_cell
+    mid = mech_id if mech_id is not None else ctx.mech_upload(m)
+    gpu = run_gpu(ctx, m, st, dt, prec=prec, opts=opts, mech_id=mid)
+    om, ref = run_oracle(orc, m, st, dt, **(orc_kw or {}))
+    s = check_every_cell(ctx, orc, m, mid, st, dt, prec, gpu, ref, rtol, opts=opts,
+                         orc_opts=orc.make_opts(**orc_kw) if orc_kw else None)
+    if mech_id is None:
+        ctx.mech_release(mid)
+    bound = max_mismatch if max_mismatch >= 1 else max_mismatch * st.n
+    assert s["unchecked"] == 0 and s["follow_fail"] == 0 and s["ok_vs_failed"] == 0, s
+    assert s["fail_Y"] == 0 and s["fail_T"] == 0 and s["fail_Y_followed"] == 0 and s["fail_T_followed"] == 0, s
+    assert s["status_mismatch"] + s["schedule_mismatch"] <= bound, s
+    return s, gpu, ref
+
+
 def test_isomer_closed_form_gpu(ctx):
     """A <=> B through the lane layout: the exact backward-Euler step."""
     from tests.test_oracle_pins import isomer_mech
@@ -58,112 +82,161 @@ def test_isomer_closed_form_gpu(ctx):
 
 def test_mech9_small_fp64_lane(ctx, orc):
     """9 species / 38 reactions, 4096 cells, one step of 1e-6 s, FP64, lane layout."""
-    from tests.parity import compare
     m, st, dt = synth.workload_small_mech9()
-    gpu = run_gpu(ctx, m, st, dt)
-    om, ref = run_oracle(orc, m, st, dt)
-    s = compare(gpu, ref, st.rho, st.Y, dt, om, 1e-10)
+    s, gpu, ref = every_cell(ctx, orc, m, st, dt, 0, 1e-10)
     report("mech9 4096 fp64", s)
-    assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
-    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+    assert s["checked"] == st.n
 
 
 def test_mech36_sample_fp64_wave(ctx, orc):
     """36 species / 308 reactions, 512 cells of the 2^18-cell input, FP64, wave layout."""
-    from tests.parity import compare
     m, st, dt = synth.workload_mech36(1 << 18)
     sub = st.subset(np.arange(0, 1 << 18, 512))
-    gpu = run_gpu(ctx, m, sub, dt)
-    om, ref = run_oracle(orc, m, sub, dt)
-    s = compare(gpu, ref, sub.rho, sub.Y, dt, om, 1e-10)
+    s, gpu, ref = every_cell(ctx, orc, m, sub, dt, 0, 1e-10)
     report("mech36 512 fp64", s)
-    assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
-    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+    assert s["checked"] == sub.n
 
 
 def test_mech9_small_fp32lu(ctx, orc):
-    """FP32-LU form against the FP64 oracle: gate 1e-6 per result on cells whose sub-step
-    schedule (status, level) matches; schedule mismatches are counted and bounded."""
-    from tests.parity import compare
+    """FP32-LU form against the FP64 oracle at 1e-6 per result, every one of the 4096 cells:
+    FP32 Newton converges linearly, so some cells take another sub-step schedule than the
+    oracle's own; those are compared with the oracle following the GPU's schedule."""
     from paper_1110_4903_amd import kin
     m, st, dt = synth.workload_small_mech9()
-    gpu = run_gpu(ctx, m, st, dt, prec=kin.FP32_LU)
-    om, ref = run_oracle(orc, m, st, dt)
-    s = compare(gpu, ref, st.rho, st.Y, dt, om, 1e-6)
+    s, gpu, ref = every_cell(ctx, orc, m, st, dt, kin.FP32_LU, 1e-6, max_mismatch=0.1)
     report("mech9 4096 fp32lu", s)
-    # FP32 Newton converges linearly, so some cells take a different sub-step schedule; those
-    # differ by the backward-Euler truncation error and are counted, not gated
-    assert s["schedule_mismatch"] <= 0.1 * s["n"]
-    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+    assert s["checked"] == st.n and s["compared"] >= 0.9 * st.n
 
 
 def test_mech36_sample_fp32lu(ctx, orc):
-    from tests.parity import compare
+    """FP32-LU form of the 36-species mechanism, 256 cells of the 2^18-cell input, wave layout,
+    every cell against the oracle at 1e-6."""
     from paper_1110_4903_amd import kin
     m, st, dt = synth.workload_mech36(1 << 18)
     sub = st.subset(np.arange(7, 1 << 18, 1024))
-    gpu = run_gpu(ctx, m, sub, dt, prec=kin.FP32_LU)
-    om, ref = run_oracle(orc, m, sub, dt)
-    s = compare(gpu, ref, sub.rho, sub.Y, dt, om, 1e-6)
+    s, gpu, ref = every_cell(ctx, orc, m, sub, dt, kin.FP32_LU, 1e-6, max_mismatch=0.1)
     report("mech36 256 fp32lu", s)
-    assert s["schedule_mismatch"] <= 0.25 * s["n"]
-    assert s["fail_Y"] == 0 and s["fail_T"] == 0
+    assert s["checked"] == sub.n and s["compared"] >= 0.9 * sub.n
 
 
-def test_grid_multistep_sampled(ctx, orc):
-    """The 1024x1024 band grid, three steps of 1e-6 s on the GPU (all cells), compared on a
-    strided sample of cells the oracle advances through the same three steps."""
-    from tests.parity import compare
+@pytest.mark.parametrize("prec,rtol", [(0, 1e-10), (1, 1e-6)])
+def test_grid_multistep_sampled(ctx, orc, prec, rtol):
+    """The 1024x1024 band grid (the headline input), three steps of 1e-6 s on the GPU over all
+    cells in the benchmark's launch configuration (cost-ordered), in the FP64 and the FP32-LU
+    form.  A strided sample of 1052 cells is checked two ways: against the oracle's own three
+    adaptive steps (FP64: every sampled cell must take the oracle's schedules; FP32-LU: the
+    agreement is reported), and, every sampled cell, against the oracle following the GPU's
+    recorded schedules of the same three steps.  The recorded re-run of the sample reproduces the
+    full-grid result bitwise."""
+    from tests.parity import compare, gpu_traces, oracle_follow
     m, grid, dt = synth.workload_grid_mech9()
     mid = ctx.mech_upload(m)
     iid = ctx.state_upload(mid, grid.rho, grid.T, grid.Y)
     for _ in range(3):
-        ctx.advance([iid], [dt])
-    gpu = ctx.download(iid)
+        ctx.advance([iid], [dt], prec=prec)
+    gpu = ctx.download(iid) + (ctx.download_schedule(iid),)
     ctx.instance_release(iid)
-    ctx.mech_release(mid)
     sample = np.arange(0, grid.n, 997)
     sub = grid.subset(sample)
+    g = tuple(a[..., sample] for a in gpu)
+    traces, reruns = gpu_traces(ctx, mid, sub, dt, prec, steps=3)
+    ctx.mech_release(mid)
+    for x, y in zip(reruns[-1], g):
+        assert np.array_equal(x, y, equal_nan=True)
     om = orc.OracleMech(m)
     e0 = om.energy_batch(sub.T, sub.Y)
     T, Y = sub.T.copy(), sub.Y.copy()
     for _ in range(3):
-        T, Y, s_, l_, i_ = om.advance(sub.rho, T, Y, dt, e0=e0)
-    g = (gpu[0][sample], gpu[1][:, sample], gpu[2][sample], gpu[3][sample], gpu[4][sample])
-    # status/level/iters of the last step only are comparable
-    s = compare(g, (T, Y, s_, l_, i_), sub.rho, sub.Y, 3 * dt, om, 1e-10)
-    report("grid 3 steps sampled", s)
-    assert s["fail_Y"] == 0 and s["fail_T"] == 0 and s["status_mismatch"] == 0
+        T, Y, s_, l_, i_, h_ = om.advance(sub.rho, T, Y, dt, e0=e0, with_sched=True)
+    own = compare(g, (T, Y, s_, l_, i_, h_), sub.rho, sub.Y, 3 * dt, om, rtol)
+    fol = oracle_follow(om, sub, dt, traces, e0=e0)
+    assert np.array_equal(fol[5], g[5]) and np.array_equal(fol[2], g[2])
+    s = compare(g, fol, sub.rho, sub.Y, 3 * dt, om, rtol)
+    report(f"grid 3 steps sampled prec {prec} (own schedule)", own)
+    report(f"grid 3 steps sampled prec {prec} (GPU schedule)", s)
+    assert s["compared"] == sub.n and s["fail_Y"] == 0 and s["fail_T"] == 0
+    if prec == 0:
+        assert own["status_mismatch"] == 0 and own["fail_Y"] == 0 and own["fail_T"] == 0
 
 
-def test_mech36_full_size_sampled(ctx, orc):
+def full_size_invariants(orc, m, st, T1, Y1, e0, status):
+    """Properties every finished cell of a backward-Euler step at constant (rho, e) has, at any
+    size: element amounts and the sum of mass fractions unchanged, and e(Y, T) = e0 (the
+    temperature inversion), checked with the oracle's energy function on every cell."""
+    om = orc.OracleMech(m)
+    ok = status < 2
+    comp = np.asarray(m.comp, dtype=float).T
+    el0 = comp @ (st.Y[:, ok] / m.M[:, None])
+    el1 = comp @ (Y1[:, ok] / m.M[:, None])
+    scale = comp @ (np.abs(st.Y[:, ok]) / m.M[:, None])
+    assert np.all(np.abs(el1 - el0) <= 1e-12 * scale + 1e-300)
+    assert np.all(np.abs(Y1[:, ok].sum(0) - st.Y[:, ok].sum(0)) <= 1e-12)
+    e1 = om.energy_batch(T1[ok], Y1[:, ok])
+    assert np.all(np.abs(e1 - e0[ok]) <= 1e-12 * np.abs(e0[ok]) + 1e-6)
+    return int(ok.sum())
+
+
+@pytest.mark.parametrize("prec,rtol", [(0, 1e-10), (1, 1e-6)])
+def test_mech36_full_size_sampled(ctx, orc, prec, rtol):
     """All 2^18 cells of the 36-species input on the GPU in the launch configuration the
-    benchmark times; 64 strided cells checked against the oracle."""
-    from tests.parity import compare
+    benchmark times: every cell keeps its element amounts, sum of mass fractions and energy;
+    1024 strided cells checked against the oracle (each through its own schedule, or the GPU's
+    where they differ)."""
+    from tests.parity import check_every_cell
+    from paper_1110_4903_amd import kin
     m, st, dt = synth.workload_mech36(1 << 18)
-    gpu = run_gpu(ctx, m, st, dt)
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload(mid, st.rho, st.T, st.Y)
+    ctx.advance([iid], [dt], prec=prec)
+    gpu = ctx.download(iid) + (ctx.download_schedule(iid),)
+    e0 = ctx.download_e0(iid)
+    ctx.instance_release(iid)
     assert np.all(gpu[2] < 2)
-    sample = np.arange(3, 1 << 18, 4096)
+    n_inv = full_size_invariants(orc, m, st, gpu[0], gpu[1], e0, gpu[2])
+    sample = np.arange(3, 1 << 18, 256)
     sub = st.subset(sample)
     om, ref = run_oracle(orc, m, sub, dt)
     g = tuple(a[..., sample] for a in gpu)
-    s = compare(g, ref, sub.rho, sub.Y, dt, om, 1e-10)
-    report("mech36 2^18 sampled", s)
-    assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0
+    s = check_every_cell(ctx, orc, m, mid, sub, dt, prec, g, ref, rtol)
+    ctx.mech_release(mid)
+    s["invariant_cells"] = n_inv
+    report(f"mech36 2^18 prec {prec}", s)
+    assert s["checked"] == sub.n and s["follow_fail"] == 0 and s["ok_vs_failed"] == 0
+    assert s["fail_Y"] == 0 and s["fail_T"] == 0 and s["fail_Y_followed"] == 0 and s["fail_T_followed"] == 0
+    assert s["status_mismatch"] + s["schedule_mismatch"] <= (2 if prec == kin.FP64 else 0.1 * sub.n)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid_ten_steps_invariants(ctx, orc, prec):
+    """The headline run itself: all 2^20 cells of the band grid through the ten steps the
+    benchmark times (cost-ordered after the first), in either form; every cell finishes every
+    step and keeps its element amounts, sum of mass fractions and energy."""
+    m, grid, dt = synth.workload_grid_mech9()
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload(mid, grid.rho, grid.T, grid.Y)
+    for _ in range(10):
+        ctx.advance([iid], [dt], prec=prec)
+        assert np.all(ctx.download(iid)[2] < 2)
+    T1, Y1, st1 = ctx.download(iid)[:3]
+    e0 = ctx.download_e0(iid)
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    n_inv = full_size_invariants(orc, m, grid, T1, Y1, e0, st1)
+    report(f"grid 10 steps prec {prec}", dict(invariant_cells=n_inv))
+    assert n_inv == grid.n
 
 
 @pytest.mark.parametrize("n", [1, 63, 65, 1000])
 def test_ragged_sizes_both_layouts(ctx, orc, n):
-    """Cell counts that are not multiples of the wavefront, through both layouts."""
-    from tests.parity import compare
+    """Cell counts that are not multiples of the wavefront, through both layouts, every cell."""
     from paper_1110_4903_amd import kin
     m = synth.mechanism("mech9")
     st = synth.uniform_cells(100 + n, n, m.ns, 1.0)
-    om, ref = run_oracle(orc, m, st, 1e-6)
+    mid = ctx.mech_upload(m)
     for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
-        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout))
-        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
-        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, (layout, s)
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, 0, 1e-10, opts=kin.solver_opts(layout=layout), mech_id=mid)
+        assert s["checked"] == st.n, (layout, s)
+    ctx.mech_release(mid)
 
 
 def test_bad_inputs_and_forced_failure(ctx, orc):
@@ -359,7 +432,31 @@ def test_autotune_restores_state_and_persists(ctx, tmp_path):
         print(f"\n[autotune mech9 8192] layout={lay} block={blk} {ms:.3f} ms", flush=True)
     with kin.Context(0, tune_cache=cache) as c2:
         mid = c2.mech_upload(m)
-        assert c2.query_int(kin.Q_LAYOUT, mid) == lay and c2.query_int(kin.Q_BLOCK, mid) == blk
+        assert c2.tuned(mid) == {(kin.FP64, kin.size_class(8192)): (lay, blk)}
+        # the mechanism's own layout (other size classes) is unchanged
+        assert c2.query_int(kin.Q_LAYOUT, mid) == kin.LAYOUT_LANE
+
+
+def test_autotune_is_per_size_class(ctx, orc, tmp_path):
+    """The autotuner's choice applies to launches of the size class it was tuned at.  Tuned at
+    1024 cells the 9-species mechanism picks some layout for that class, and launches of 2^18
+    cells still run the lane layout; the tuned small launch still matches the oracle."""
+    from paper_1110_4903_amd import kin
+    from tests.parity import compare
+    m = synth.mechanism("mech9")
+    small = synth.uniform_cells(81, 1024, m.ns, 1.0)
+    with kin.Context(0, tune_cache=str(tmp_path / "t.json")) as c:
+        mid = c.mech_upload(m)
+        iid = c.state_upload(mid, small.rho, small.T, small.Y)
+        lay, blk, ms = c.autotune(mid, iid, 1e-6)
+        assert c.tuned(mid) == {(kin.FP64, 0): (lay, blk)}
+        c.advance([iid], [1e-6])
+        gpu = c.download(iid) + (c.download_schedule(iid),)
+        om, ref = run_oracle(orc, m, small, 1e-6)
+        s = compare(gpu, ref, small.rho, small.Y, 1e-6, om, 1e-10)
+        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, s
+        print(f"\n[autotune mech9 1024] layout={lay} block={blk} {ms:.3f} ms", flush=True)
+        c.instance_release(iid)
 
 
 def test_point_implicit_both_layouts(ctx, orc):
@@ -398,12 +495,10 @@ def test_divergence_test_off_matches_oracle(ctx, orc):
     for name, st, layout in (("mech9", synth.uniform_cells(31, 500, 9, 1.0), kin.LAYOUT_LANE),
                              ("mech36", synth.uniform_cells(32, 128, 36, 0.5), kin.LAYOUT_WAVE)):
         m = synth.mechanism(name)
-        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout, diverge_ratio=0.0))
-        om, ref = run_oracle(orc, m, st, 1e-6, diverge_ratio=0.0)
-        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, 0, 1e-10, opts=kin.solver_opts(layout=layout, diverge_ratio=0.0),
+                             orc_kw=dict(diverge_ratio=0.0))
         report(f"diverge off {name}", s)
-        assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
-        assert s["fail_Y"] == 0 and s["fail_T"] == 0
+        assert s["checked"] == st.n
 
 
 @pytest.mark.parametrize("ns,nr,ne", [(20, 120, 3), (28, 200, 4), (45, 360, 4), (60, 480, 4)])
@@ -416,14 +511,12 @@ def test_wave_layout_other_row_lengths(ctx, orc, ns, nr, ne):
                                               n_reactions=nr, frac_third_body=0.15,
                                               frac_irreversible=0.3))
     st = synth.uniform_cells(200 + ns, 128, ns, 0.5)
-    om, ref = run_oracle(orc, m, st, 1e-6)
-    for prec, rtol in ((kin.FP64, 1e-10), (kin.FP32_LU, 1e-6)):
-        gpu = run_gpu(ctx, m, st, 1e-6, prec=prec)
-        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, rtol)
+    mid = ctx.mech_upload(m)
+    for prec, rtol, bound in ((kin.FP64, 1e-10, 2), (kin.FP32_LU, 1e-6, 0.1)):
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, prec, rtol, mech_id=mid, max_mismatch=bound)
         report(f"gen{ns} prec {prec}", s)
-        if prec == kin.FP64:
-            assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
-        assert s["fail_Y"] == 0 and s["fail_T"] == 0
+        assert s["checked"] == st.n
+    ctx.mech_release(mid)
 
 
 def both_sides_mech():
@@ -445,18 +538,15 @@ def both_sides_mech():
 def test_species_on_both_sides_both_layouts(ctx, orc):
     """A species on both sides of a reaction enters the wave layout's reactant and product
     slots separately; both layouts against the oracle, FP64."""
-    from tests.parity import compare
     from paper_1110_4903_amd import kin
     m = both_sides_mech()
     st = synth.uniform_cells(77, 300, m.ns, 1.0)
-    om, ref = run_oracle(orc, m, st, 1e-6)
-    assert np.all(ref[2] < 2)
+    mid = ctx.mech_upload(m)
     for layout in (kin.LAYOUT_LANE, kin.LAYOUT_WAVE):
-        gpu = run_gpu(ctx, m, st, 1e-6, opts=kin.solver_opts(layout=layout))
-        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, 1e-10)
+        s, _, ref = every_cell(ctx, orc, m, st, 1e-6, 0, 1e-10, opts=kin.solver_opts(layout=layout), mech_id=mid)
         report(f"both sides layout {layout}", s)
-        assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2, (layout, s)
-        assert s["fail_Y"] == 0 and s["fail_T"] == 0, (layout, s)
+        assert np.all(ref[2] < 2) and s["checked"] == st.n, (layout, s)
+    ctx.mech_release(mid)
 
 
 @pytest.mark.parametrize("name", ["mech9", "mech36"])
@@ -522,7 +612,8 @@ def big_mech(ns, nr):
 
 @pytest.mark.parametrize("case", ["mech9", "mech36", "gen100"])
 def test_global_layout_against_oracle(ctx, orc, case):
-    """The global-memory layout (one thread per cell, Jacobian in HBM): the 9- and 36-species
+    """The global-memory layout (one wavefront per cell, the cell's matrix column-major in HBM):
+    the 9- and 36-species
     mechanisms forced onto it, and a 100-species mechanism that selects it by itself, FP64 and
     FP32-LU, against the oracle."""
     from tests.parity import compare
@@ -532,18 +623,14 @@ def test_global_layout_against_oracle(ctx, orc, case):
     else:
         m, n, alpha = synth.mechanism(case), 128, 1.0 if case == "mech9" else 0.5
     st = synth.uniform_cells(500 + m.ns, n, m.ns, alpha)
-    om, ref = run_oracle(orc, m, st, 1e-6)
     mid = ctx.mech_upload(m)
     if case == "gen100":
         assert ctx.query_int(kin.Q_LAYOUT, mid) == kin.LAYOUT_GLOBAL
     opts = kin.solver_opts(layout=kin.LAYOUT_GLOBAL)
-    for prec, rtol in ((kin.FP64, 1e-10), (kin.FP32_LU, 1e-6)):
-        gpu = run_gpu(ctx, m, st, 1e-6, prec=prec, opts=opts, mech_id=mid)
-        s = compare(gpu, ref, st.rho, st.Y, 1e-6, om, rtol)
+    for prec, rtol, bound in ((kin.FP64, 1e-10, 2), (kin.FP32_LU, 1e-6, 0.1)):
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, prec, rtol, opts=opts, mech_id=mid, max_mismatch=bound)
         report(f"global {case} prec {prec}", s)
-        if prec == kin.FP64:
-            assert s["status_mismatch"] == 0 and s["schedule_mismatch"] <= 2
-        assert s["fail_Y"] == 0 and s["fail_T"] == 0
+        assert s["checked"] == st.n
     ctx.mech_release(mid)
 
 

@@ -116,12 +116,14 @@ def controller_reference(orc, om, rho, e0, x0, dt, opts):
     x = np.array(x0, dtype=np.float64)
     t, l, deepest, iters, failed = Fraction(0), 0, 0, 0, False
     sched, taken = SCHED_SEED, []
+    outcomes = controller_reference.outcomes = []
     while t < 1:
         if iters >= opts.max_iters:
             return orc.FAILED, np.array(x0), deepest, iters, sched, taken
         rc, xn, it, _ = om.be_substep(rho, e0, x, math.ldexp(dt, -l), opts)
         iters += it
         ok = rc == 0
+        outcomes.append(ok)
         sched = ((sched ^ (2 * l + int(ok))) * SCHED_PRIME) % (1 << 64)
         if ok:
             x = xn
@@ -178,6 +180,47 @@ def test_controller_with_tiny_level_cap_and_iteration_budget(orc):
                                                        np.r_[st.Y[:, c], st.T[c]], 1e-6, opts)
             assert (s, lv, it, sh) == (s1[c], l1[c], i1[c], int(h1[c])), (kw, c)
             assert np.array_equal(x, np.r_[Y1[:, c], T1[c]]), (kw, c)
+
+
+def pack_schedule(outcomes, words):
+    """Schedule record of one cell: word 0 the attempt count, then the accept bits."""
+    rec = np.zeros(words, np.uint64)
+    rec[0] = len(outcomes)
+    for j, ok in enumerate(outcomes[:64 * (words - 1)]):
+        if ok:
+            rec[1 + j // 64] |= np.uint64(1) << np.uint64(j % 64)
+    return rec
+
+
+def test_follow_own_schedule_is_bitwise_the_adaptive_step(orc):
+    """Following a recorded schedule: fed the accept/reject sequence that the independent driver
+    above records for the oracle's own adaptive run, orc_follow reproduces that run bitwise
+    (state, status, level, schedule hash): an accepted attempt is the same Newton iteration
+    sequence to the same converged iterate, a rejected one is skipped.  A schedule cut short
+    (the other side failed the cell) leaves the input state with status 2, and a truncated
+    record is refused (-2)."""
+    m = synth.mechanism("mech9")
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(93, 64, m.ns, 1.0)
+    e0 = om.energy_batch(st.T, st.Y)
+    opts = orc.default_opts()
+    T1, Y1, s1, l1, i1, h1 = om.advance(st.rho, st.T, st.Y, 1e-6, e0=e0, with_sched=True)
+    recs = []
+    for c in range(st.n):
+        controller_reference(orc, om, st.rho[c], e0[c], np.r_[st.Y[:, c], st.T[c]], 1e-6, opts)
+        recs.append(pack_schedule(controller_reference.outcomes, 8))
+    trace = np.array(recs)
+    assert (trace[:, 0] > 1).sum() >= 8
+    T2, Y2, s2, l2, i2, h2 = om.follow(st.rho, st.T, st.Y, 1e-6, e0, trace)
+    assert np.array_equal(s2, s1) and np.array_equal(l2, l1) and np.array_equal(h2, h1)
+    assert np.array_equal(T2, T1) and np.array_equal(Y2, Y1)
+    assert np.all(i2 <= i1)  # rejected attempts cost nothing when followed
+    cut = trace.copy()
+    cut[:, 0] = np.maximum(cut[:, 0].astype(np.int64) - 1, 0).astype(np.uint64)
+    T3, Y3, s3 = om.follow(st.rho, st.T, st.Y, 1e-6, e0, cut)[:3]
+    assert np.all(s3 == 2) and np.array_equal(T3, st.T) and np.array_equal(Y3, st.Y)
+    short = np.array([pack_schedule([True] * 70, 2)] * 2)
+    assert np.all(om.follow(st.rho[:2], st.T[:2], st.Y[:, :2], 1e-6, e0[:2], short)[2] == -2)
 
 
 # ---------------------------------------------------------------------------------------------
