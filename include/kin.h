@@ -212,6 +212,25 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
 kin_status kin_advance_trace(kin_ctx *ctx, int32_t inst_id, double dt, kin_precision prec,
                              const kin_solver_opts *s, int32_t words, uint64_t *trace, void *stream);
 
+/* kin_advance without any device allocation, for callers that cannot allocate: code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  Same arguments, checks,
+ * per-cell results and diagnostics as kin_advance, bitwise.  The launches (instances grouped
+ * by mechanism and layout, at most 64 per launch) go out one after another on `stream`, in
+ * index order (no cost order, no internal graph or streams).  Their work counters and the
+ * matrices of global-layout launches live in a fixed 256 MiB array of device memory that each
+ * device holds from the library's first context on it until the process ends; a global-layout
+ * launch keeps as many cells in flight as that array has matrix slots for, which bounds its
+ * parallelism, not its size.  Limits: at most 64 instances per call (KIN_EINVAL beyond).
+ * Lane-layout kernels must already be compiled for the block size in use (kin_mech_upload does
+ * so for the default, kin_set_layout for another); otherwise KIN_EINVAL.  All calls on one
+ * device share that array: two calls whose work overlaps on the device (different streams, or
+ * different contexts or host threads, not ordered by the caller) race on it and give undefined
+ * results.  Calls ordered on one stream are safe.
+ * Paper: no passage; the callers are those that cannot allocate (the computation is that of
+ * kin_advance). */
+kin_status kin_advance_noalloc(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
+                               kin_precision prec, const kin_solver_opts *s, void *stream);
+
 /* Copy an instance's state (T[n], Y[Ns][n]), the conserved internal energy e0[n] and the
  * per-cell diagnostics of the last advance into caller buffers; any pointer may be NULL.
  * Re-uploading T, Y with this e0 resumes the run bitwise (checkpoint / restart).

@@ -14,6 +14,7 @@
 // Eq. "kinetics"; energy bookkeeping of Sec. 2).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "kin_internal.h"
@@ -797,6 +798,31 @@ __global__ void __launch_bounds__(64) gwave_kernel(WaveTables t, AdvanceArgs a, 
     }
 }
 }  // namespace
+
+// Fixed device memory of the allocation-free advance (kin_advance_noalloc): its work counters
+// and the matrices of its global-layout launches, in place of the counters and the
+// stream-ordered workspace that kin_advance allocates.  Every device the library runs on holds
+// its own copy until the process ends.  Host code never uses this name as an address: the
+// per-device address comes from scratch_address().
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *addr[kScratchMaxDevices] = {};
+    if (device < 0 || device >= kScratchMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        // the caller has made `device` current
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<unsigned char *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 size_t global_work_doubles_per_slot(int ns, int ntb)
 {

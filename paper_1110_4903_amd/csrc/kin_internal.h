@@ -195,6 +195,17 @@ struct AdvanceArgs {
     int trace_words;
 };
 
+// Fixed device memory of the allocation-free advance (kin_global.hip): kScratchLaunches 64-bit
+// work counters at offset 0, then the global layout's matrix workspace from offset
+// kScratchWorkOffset to the end.  256 MiB per device.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kScratchLaunches = 64;
+constexpr size_t kScratchWorkOffset = 4096;
+constexpr int kScratchMaxDevices = 64;
+// Device address of the fixed memory on `device`, which must be current.  Looked up once per
+// device and kept.
+hipError_t scratch_address(int device, unsigned char **out);
+
 // Host launchers of the precompiled kernels (kin_wave.hip).
 int wave_npad(int n);
 hipError_t launch_conserved_in(const WaveTables &t, long long n, long long ld, double *rho, double *T,

@@ -101,6 +101,8 @@ struct kin_ctx {
     kin_status plan_status = KIN_OK;
     // with a budget: one device pool of that size, carved first-fit into instance arenas
     char *pool = nullptr;
+    // the device's fixed memory for kin_advance_noalloc (counters, then workspace)
+    unsigned char *scratch = nullptr;
     std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
 };
 
@@ -206,6 +208,9 @@ kin_status kin_create(kin_ctx **out, const kin_ctx_opts *o)
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, c->device)) != hipSuccess) return err(KIN_EDEVICE, hipGetErrorString(e));
     c->num_cu = prop.multiProcessorCount;
+    // address of this device's fixed memory for the allocation-free advance (once per device)
+    if ((e = scratch_address(c->device, &c->scratch)) != hipSuccess)
+        return err(KIN_EDEVICE, std::string("fixed device memory: ") + hipGetErrorString(e));
     if (c->budget) {
         c->budget &= ~(uint64_t)255;
         if (c->budget == 0) return err(KIN_EINVAL, "budget below 256 bytes");
@@ -910,7 +915,7 @@ static size_t global_work_doubles(const Mech &m, long long total)
 // a.counter must already be zero (stream order).  gwork: the workspace of a global-layout
 // launch (global_work_doubles doubles); NULL allocates it stream-ordered on st.
 static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precision prec, int layout,
-                               int block, hipStream_t st, double *gwork = nullptr)
+                               int block, hipStream_t st, double *gwork = nullptr, long long gslots = 0)
 {
     const bool f32 = prec == KIN_FP32_LU;
     a.ns = m.h.ns;
@@ -929,7 +934,7 @@ static kin_status launch_spans(kin_ctx *ctx, Mech &m, AdvanceArgs &a, kin_precis
         void *params[] = {&a};
         KIN_HIP(ctx, hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
     } else if (layout == KIN_LAYOUT_GLOBAL) {
-        const long long S = global_slots(m, a.total);
+        const long long S = gslots > 0 ? std::min(gslots, global_slots(m, a.total)) : global_slots(m, a.total);
         if (gwork) {
             KIN_HIP(ctx, launch_global(m.tab, a, f32, gwork, S, st));
         } else {
@@ -1206,6 +1211,49 @@ kin_status kin_advance_trace(kin_ctx *ctx, int32_t inst_id, double dt, kin_preci
     s = launch_spans(ctx, m, a, prec, layout, block, st);
     if (s == KIN_OK) in.iters_current = true;
     return s;
+}
+
+kin_status kin_advance_noalloc(kin_ctx *ctx, const int32_t *inst_ids, const double *dts, int32_t n,
+                               kin_precision prec, const kin_solver_opts *sopt, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    kin_solver_opts o;
+    if ((s = check_advance(ctx, inst_ids, dts, n, prec, sopt, o)) != KIN_OK) return s;
+    if (n > kScratchLaunches)
+        return err(KIN_EINVAL, "kin_advance_noalloc takes at most " + std::to_string(kScratchLaunches) +
+                                   " instances per call (one fixed work counter per launch)");
+    if (!ctx->scratch) return err(KIN_EDEVICE, "no fixed device memory on this device");
+    std::vector<Launch> launches;
+    plan_launches(ctx, inst_ids, dts, n, o, prec, launches);
+    if ((int)launches.size() > kScratchLaunches) return err(KIN_EINVAL, "too many launches for the fixed counters");
+    unsigned long long *counters = reinterpret_cast<unsigned long long *>(ctx->scratch);
+    double *work = reinterpret_cast<double *>(ctx->scratch + kScratchWorkOffset);
+    const size_t work_bytes = kScratchBytes - kScratchWorkOffset;
+    // everything that would allocate (lane kernels not compiled for this block) is refused up
+    // front, before any launch
+    for (const Launch &L : launches) {
+        if (L.layout == KIN_LAYOUT_LANE && !(L.m->mod && L.m->lane_block == L.block))
+            return err(KIN_EINVAL, "the lane-layout kernels of this mechanism are not compiled for " +
+                                       std::to_string(L.block) + " threads per block; kin_set_layout or kin_advance compiles them");
+        if (L.layout == KIN_LAYOUT_GLOBAL &&
+            sizeof(double) * global_work_doubles_per_slot(L.m->h.ns, L.m->tab.ntb) > work_bytes)
+            return err(KIN_EINVAL, "one cell's matrix exceeds the fixed workspace");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (size_t q = 0; q < launches.size(); ++q) {
+        Launch &L = launches[q];
+        L.a.counter = counters + q;
+        KIN_HIP(ctx, launch_zero_u64(counters + q, 1, st));
+        long long gslots = 0;
+        if (L.layout == KIN_LAYOUT_GLOBAL)  // launches are stream-ordered, so they share it
+            gslots = (long long)(work_bytes / (sizeof(double) * global_work_doubles_per_slot(L.m->h.ns, L.m->tab.ntb)));
+        s = launch_spans(ctx, *L.m, L.a, prec, L.layout, L.block, st, L.layout == KIN_LAYOUT_GLOBAL ? work : nullptr, gslots);
+        if (s != KIN_OK) return s;
+    }
+    for (int k = 0; k < n; ++k) ctx->insts[inst_ids[k]]->iters_current = true;
+    return KIN_OK;
 }
 
 kin_status kin_download(kin_ctx *ctx, int32_t inst_id, double *T, double *Y, double *e0,

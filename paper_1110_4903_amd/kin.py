@@ -35,7 +35,8 @@ EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destr
            "kin_advance", "kin_download", "kin_sync", "kin_instance_release", "kin_footprint",
            "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune",
            "kin_stream_create", "kin_stream_destroy", "kin_state_upload_conserved",
-           "kin_download_conserved", "kin_state_reset_conserved", "kin_advance_trace")
+           "kin_download_conserved", "kin_state_reset_conserved", "kin_advance_noalloc",
+           "kin_advance_trace")
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -85,6 +86,7 @@ _lib.kin_mech_release.argtypes = [_vp, _i32]
 _lib.kin_state_upload.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp, _vp, C.c_int, _vp, _vp]
 _lib.kin_state_reset.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
+_lib.kin_advance_noalloc.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_advance_trace.argtypes = [_vp, _i32, C.c_double, C.c_int, _vp, _i32, _vp, _vp]
 _lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_sync.argtypes = [_vp, _vp]
@@ -288,6 +290,16 @@ class Context:
             raise ValueError("one dt per instance")
         _check(_lib.kin_advance(self._h, ids.ctypes.data, dd.ctypes.data, int(ids.shape[0]), prec,
                                 C.byref(opts) if opts is not None else None, _stream_handle(stream)))
+
+    def advance_noalloc(self, inst_ids: Sequence[int], dts: Sequence[float], prec: int = FP64,
+                        opts: Optional[SolverOpts] = None, stream=None):
+        """kin_advance_noalloc: the same step with no device allocation (fixed device memory)."""
+        ids = np.ascontiguousarray(inst_ids, dtype=np.int32)
+        dd = np.ascontiguousarray(dts, dtype=np.float64)
+        if ids.shape != dd.shape:
+            raise ValueError("one dt per instance")
+        _check(_lib.kin_advance_noalloc(self._h, ids.ctypes.data, dd.ctypes.data, int(ids.shape[0]), prec,
+                                        C.byref(opts) if opts is not None else None, _stream_handle(stream)))
 
     def advance_trace(self, inst_id: int, dt: float, prec: int = FP64, opts: Optional[SolverOpts] = None,
                       words: int = 16):
