@@ -54,11 +54,16 @@ def device_state(torch, st):
 
 def time_steps(torch, ctx, iid, state, dt, prec, steps, warmup, stream, opts=None):
     """Warm up, reset to the input state, then time `steps` advance calls with events recorded on
-    the launch stream.  Returns (total_s, per-launch seconds)."""
+    the launch stream.  Returns (total_s, per-advance seconds, per-launch seconds of the advance
+    kernel alone).  The latter come from the events the library records on the launch stream
+    right around its advance kernel (the context is created with kernel timing on); an advance's
+    own time also holds the work-counter clear and, for a cost-ordered step, the ordering
+    kernels."""
     for _ in range(warmup):
         ctx.advance([iid], [dt], prec=prec, stream=stream, opts=opts)
     ctx.state_reset(iid, state["rho"], state["T"], state["Y"], stream=stream)
     torch.cuda.synchronize()
+    ctx.kernel_times()  # drop the warm-up's records
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
     for k in range(steps):
@@ -66,7 +71,9 @@ def time_steps(torch, ctx, iid, state, dt, prec, steps, warmup, stream, opts=Non
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     per = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(steps)]
-    return sum(per), per
+    kern = [1e-3 * t for t in ctx.kernel_times()]
+    assert len(kern) == steps, (len(kern), steps)
+    return sum(per), per, kern
 
 
 def replay_stats(torch, ctx, iid, state, dt, prec, steps, stream, opts=None):
@@ -85,12 +92,16 @@ def replay_stats(torch, ctx, iid, state, dt, prec, steps, stream, opts=None):
     return its, st_hist, lv_max, out
 
 
-def form_stats(n, steps, tot, per, its, hist, lvmax, flops_per_iter):
+def form_stats(n, steps, tot, per, kern, its, hist, lvmax, flops_per_iter):
+    """Throughput of a form, and the advance kernel's achieved rate: the flop model's flops per
+    Newton iteration times the iterations of all timed launches, over the kernel's total time
+    (total over total, not a mean of per-launch rates)."""
     return dict(cells=n, steps=steps, seconds=tot, cells_per_s=n * steps / tot,
-                kernel_ms_avg=1e3 * float(np.mean(per)),
+                advance_ms_avg=1e3 * float(np.mean(per)), kernel_ms_avg=1e3 * float(np.mean(kern)),
+                kernel_ms=[1e3 * k for k in kern], newton_iters=[int(i) for i in its],
                 newton_iters_per_cell=float(np.sum(its)) / (n * steps),
                 status_hist=hist.tolist(), max_level=lvmax,
-                tflops_model=float(np.mean([flops_per_iter * it / p / 1e12 for it, p in zip(its, per)])))
+                tflops_model=flops_per_iter * float(np.sum(its)) / float(np.sum(kern)) / 1e12)
 
 
 def method_difference(a, b):
@@ -109,9 +120,10 @@ def method_difference(a, b):
 def point_implicit_form(torch, ctx, kin, iid, st, dt, steps, n, flops_per_iter, newton_one_step, stream):
     """The paper's point-implicit step (one linearised backward-Euler step per dt), FP64."""
     o = kin.solver_opts(point_implicit=1)
-    tot, per = time_steps(torch, ctx, iid, st, dt, kin.FP64, steps, 1, stream, opts=o)
+    tot, per, kern = time_steps(torch, ctx, iid, st, dt, kin.FP64, steps, 1, stream, opts=o)
     its, hist, lvmax, _ = replay_stats(torch, ctx, iid, st, dt, kin.FP64, steps, stream, opts=o)
-    r = form_stats(n, steps, tot, per, its, hist, lvmax, flops_per_iter)
+    ctx.kernel_times()
+    r = form_stats(n, steps, tot, per, kern, its, hist, lvmax, flops_per_iter)
     one = replay_stats(torch, ctx, iid, st, dt, kin.FP64, 1, stream, opts=o)[3]
     r["difference_from_newton_be_one_step"] = method_difference(newton_one_step, one)
     return r
@@ -140,17 +152,24 @@ def run_headline(torch, ctx, kin, flops, synth, args, stream):
     iid9 = ctx.state_upload(mid9, st9["rho"], st9["T"], st9["Y"], stream=stream)
     torch.cuda.synchronize()
     f9 = flops.newton_iteration_flops(m9)["total"]
-    res, outs = {}, {}
-    forms = (("fp64", kin.FP64),) if args.only == "headline" else (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU))
+    res, outs, traces = {}, {}, {}
+    forms = (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU))
     for name, prec in forms:
         log(f"mech9 grid {nx}x{nx}, {args.steps} steps, {name}")
-        tot, per = time_steps(torch, ctx, iid9, st9, dt9, prec, args.steps, args.warmup, stream)
+        tot, per, kern = time_steps(torch, ctx, iid9, st9, dt9, prec, args.steps, args.warmup, stream)
         its, hist, lvmax, _ = replay_stats(torch, ctx, iid9, st9, dt9, prec, args.steps, stream)
-        res[f"mech9_{name}"] = form_stats(grid.n, args.steps, tot, per, its, hist, lvmax, f9)
-        # one step from the input state, for the deviation between the forms
+        res[f"mech9_{name}"] = form_stats(grid.n, args.steps, tot, per, kern, its, hist, lvmax, f9)
+        # one step from the input state, for the deviation between the forms; then the same step
+        # with the schedule recorder, for the comparison with the oracle (cpu_baseline)
         outs[name] = replay_stats(torch, ctx, iid9, st9, dt9, prec, 1, stream)[3]
-    if "fp32lu" in outs:
-        res["mech9_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
+        if args.only == "all" and not args.no_cpu:
+            ctx.state_reset(iid9, st9["rho"], st9["T"], st9["Y"], stream=stream)
+            traces[name] = ctx.advance_trace(iid9, dt9, prec, words=16)
+            again = ctx.download(iid9) + (ctx.download_schedule(iid9),)
+            assert all(np.array_equal(a, b, equal_nan=True) for a, b in zip(again, outs[name]))
+        ctx.kernel_times()
+    res["mech9_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
+    if args.only == "all":
         log(f"mech9 grid {nx}x{nx}, {args.steps} steps, point-implicit")
         res["mech9_point_implicit_fp64"] = point_implicit_form(torch, ctx, kin, iid9, st9, dt9, args.steps, grid.n,
                                                                f9, outs["fp64"], stream)
@@ -158,7 +177,7 @@ def run_headline(torch, ctx, kin, flops, synth, args, stream):
     res["mech9_layout"] = [ctx.query_int(kin.Q_LAYOUT, mid9), ctx.query_int(kin.Q_BLOCK, mid9)]
     ctx.instance_release(iid9)
     ctx.mech_release(mid9)
-    return res, grid, m9, dt9
+    return res, grid, m9, dt9, dict(outs=outs, traces=traces)
 
 
 def run_config0_end_to_end(torch, ctx, kin, synth, stream):
@@ -277,9 +296,10 @@ def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     res, outs = {}, {}
     for name, prec in (("fp64", kin.FP64), ("fp32lu", kin.FP32_LU)):
         log(f"mech36 {n36} cells, 1 step, {name}")
-        tot, per = time_steps(torch, ctx, iid36, st36, dt36, prec, 1, 1, stream)
+        tot, per, kern = time_steps(torch, ctx, iid36, st36, dt36, prec, 1, 1, stream)
         its, hist, lvmax, out = replay_stats(torch, ctx, iid36, st36, dt36, prec, 1, stream)
-        res[f"mech36_{name}"] = form_stats(n36, 1, tot, per, its, hist, lvmax, f36)
+        ctx.kernel_times()
+        res[f"mech36_{name}"] = form_stats(n36, 1, tot, per, kern, its, hist, lvmax, f36)
         outs[name] = out
     res["mech36_fp32lu"]["deviation_from_fp64_one_step"] = deviation(outs["fp64"], outs["fp32lu"])
     log(f"mech36 {n36} cells, 1 step, point-implicit")
@@ -292,22 +312,31 @@ def run_mech36(torch, ctx, kin, flops, synth, args, stream):
 
 
 def run_batch(torch, kin, synth, args, stream):
-    """64 uneven instances, FP32-LU, one graph launch vs 64 separate launches."""
+    """64 uneven instances, FP32-LU, one graph launch vs 64 separate launches.  The autotuner
+    picks each mechanism's layout at the size class of that mechanism's launch in the batch (all
+    its instances together: about 837k cells of mech9 and 1.26M of mech36), probing with the
+    launch's cell count capped at 262144 (the top size class starts there)."""
     n_inst = 16 if args.quick else 64
     hi = 16384 if args.quick else 262144
     insts = synth.batch_instances(seed=3, n_inst=n_inst, min_cells=1024, max_cells=hi)
     cache = os.path.join(tempfile.mkdtemp(prefix="kin_tune_"), "tune.json")
     res = {}
+    names = {0: "auto", 1: "lane", 2: "wave", 3: "global"}
     with kin.Context(0, tune_cache=cache) as ctx:
-        mids = {}
+        mids, layouts = {}, {}
         for name in ("mech9", "mech36"):
             m = synth.mechanism(name)
             mids[name] = ctx.mech_upload(m)
-            probe = synth.uniform_cells(7, 16384 if not args.quick else 4096, m.ns, 1.0 if name == "mech9" else 0.5)
+            group = sum(ins.n_cells for ins in insts if ins.mech == name)
+            if group == 0:
+                continue
+            probe = synth.uniform_cells(7, min(group, 262144), m.ns, 1.0 if name == "mech9" else 0.5)
             pid = ctx.state_upload(mids[name], probe.rho, probe.T, probe.Y)
-            log(f"autotune {name}")
+            log(f"autotune {name} at {probe.n} cells (launch of {group})")
             lay, blk, ms = ctx.autotune(mids[name], pid, 1e-6, kin.FP32_LU)
-            res[f"autotune_{name}"] = dict(layout="lane" if lay == kin.LAYOUT_LANE else "wave", block=blk, ms=ms)
+            layouts[name] = lay
+            res[f"autotune_{name}"] = dict(layout=names[lay], block=blk, ms=ms, probe_cells=probe.n,
+                                           launch_cells=group, size_class=kin.size_class(group))
             ctx.instance_release(pid)
         states, ids = [], []
         for ins in insts:
@@ -346,9 +375,12 @@ def run_batch(torch, kin, synth, args, stream):
         g = snapshot()
         reset()
         log("batch: 64 separate launches")
+        # the same layouts as the graph's launches, so that the results compare bitwise (a lone
+        # instance's own size class could pick another layout)
+        sep_opts = {k: kin.solver_opts(layout=v) for k, v in layouts.items()}
         e0.record(stream)
-        for i, dt in zip(ids, dts):
-            ctx.advance([i], [dt], prec=kin.FP32_LU, stream=stream)
+        for i, dt, ins in zip(ids, dts, insts):
+            ctx.advance([i], [dt], prec=kin.FP32_LU, stream=stream, opts=sep_opts[ins.mech])
         e1.record(stream)
         torch.cuda.synchronize()
         t_sep = e0.elapsed_time(e1) * 1e-3
@@ -414,12 +446,12 @@ def run_gpu(args):
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     res = {}
-    grid = m9 = dt9 = None
+    grid = m9 = dt9 = one_step = None
     if args.only == "copy":
-        return run_copy(torch), None, None, None
-    with kin.Context(0) as ctx:
+        return run_copy(torch), None, None, None, None
+    with kin.Context(0, time_kernels=True) as ctx:
         if args.only in ("all", "headline"):
-            head, grid, m9, dt9 = run_headline(torch, ctx, kin, flops, synth, args, stream)
+            head, grid, m9, dt9, one_step = run_headline(torch, ctx, kin, flops, synth, args, stream)
             res.update(head)
         if args.only in ("all", "mech36"):
             res.update(run_mech36(torch, ctx, kin, flops, synth, args, stream))
@@ -436,20 +468,57 @@ def run_gpu(args):
         res["batch64"] = run_batch(torch, kin, synth, args, stream)
     if args.only in ("all", "serve") and not args.no_serve:
         res["serving"] = run_serving(torch, kin, serve, synth, args)
-    return res, grid, m9, dt9
+    return res, grid, m9, dt9, one_step
 
 
-def cpu_baseline(grid, m9, dt9, steps, sample_stride):
-    """The FP64 oracle on the host cores over a strided sample of the headline grid."""
+def error_vs_oracle(om, grid, dt, gpu, ref, trace, rtol):
+    """Error of one GPU step against the FP64 oracle, every cell of the grid: cells whose
+    sub-step schedule (status, level, schedule hash) matches the oracle's own are compared with
+    its adaptive step, the others with the oracle following the GPU's recorded schedule.  Per
+    result: the largest relative error of T and of the mass fractions of at least 1e-14, the
+    99.9th percentile of the latter, and the count of results beyond the form's gate rtol (mass
+    fractions of at least 1e-10; smaller ones are reported by their largest absolute error)."""
+    same = (gpu[2] == ref[2]) & (gpu[3] == ref[3]) & (gpu[5] == ref[5])
+    mis = np.flatnonzero(~same)
+    Tr, Yr, sr = ref[0].copy(), ref[1].copy(), ref[2].copy()
+    follow_fail = 0
+    if mis.size:
+        sub = grid.subset(mis)
+        e0 = om.energy_batch(sub.T, sub.Y)
+        fol = om.follow(sub.rho, sub.T, sub.Y, dt, e0, trace[mis])
+        follow_fail = int(((fol[2] < 0) | (fol[5] != gpu[5][mis])).sum())
+        Tr[mis], Yr[:, mis], sr[mis] = fol[0], fol[1], fol[2]
+    ok = (sr < 2) & (gpu[2] < 2)
+    Yg, Yo = gpu[1][:, ok], Yr[:, ok]
+    dY = np.abs(Yg - Yo)
+    big = np.abs(Yo) >= 1e-14
+    rel = np.where(big, dY / np.maximum(np.abs(Yo), 1e-300), 0.0)
+    relT = np.abs(gpu[0][ok] - Tr[ok]) / Tr[ok]
+    gated = np.abs(Yo) >= 1e-10
+    return dict(cells=int(gpu[2].shape[0]), own_schedule=int(same.sum()), followed_gpu_schedule=int(mis.size),
+                follow_fail=follow_fail, compared=int(ok.sum()), gate_rtol=rtol,
+                max_rel_Y=float(rel.max()), p999_rel_Y=float(np.quantile(rel[big], 0.999)),
+                max_rel_T=float(relT.max()), beyond_gate_Y=int((gated & (rel > rtol)).sum()),
+                beyond_gate_T=int((relT > rtol).sum()),
+                max_abs_Y_below_1em10=float(dY[~gated].max()) if (~gated).any() else 0.0)
+
+
+def cpu_baseline(grid, m9, dt9, steps, sample_stride, one_step=None):
+    """The FP64 oracle on the host cores over a strided sample of the headline grid.  With the
+    GPU's one-step results and schedule records of the full grid (one_step), the oracle's first
+    step also states each form's error against the oracle, per result."""
     from oracle import oracle
     om = oracle.OracleMech(m9)
     idx = np.arange(0, grid.n, sample_stride)
     sub = grid.subset(idx)
     e0 = om.energy_batch(sub.T, sub.Y)
     T, Y = sub.T.copy(), sub.Y.copy()
+    first = None
     t0 = time.time()
-    for _ in range(steps):
-        T, Y, _, _, _ = om.advance(sub.rho, T, Y, dt9, e0=e0)
+    for k in range(steps):
+        T, Y, st_, lv_, it_, sh_ = om.advance(sub.rho, T, Y, dt9, e0=e0, with_sched=True)
+        if k == 0:
+            first = (T, Y, st_, lv_, it_, sh_)
     el = time.time() - t0
     # the same oracle on one thread, over every 64th cell of that sample
     sub1 = grid.subset(idx[::64])
@@ -459,11 +528,18 @@ def cpu_baseline(grid, m9, dt9, steps, sample_stride):
     for _ in range(steps):
         T, Y, _, _, _ = om.advance(sub1.rho, T, Y, dt9, e0=e1, nthreads=1)
     el1 = time.time() - t1
-    return dict(value=idx.shape[0] * steps / el, unit="cells/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{idx.shape[0]} cells (every {sample_stride}th of the {int(np.sqrt(grid.n))}^2 grid) x "
-                       f"{steps} steps of dt=1e-6 s, FP64, {el:.1f} s",
-                single_thread_cells_per_s=sub1.n * steps / el1,
-                single_thread_sample=f"{sub1.n} cells x {steps} steps, {el1:.1f} s")
+    out = dict(value=idx.shape[0] * steps / el, unit="cells/s", cores=oracle.num_threads(), kind="oracle",
+               sample=f"{idx.shape[0]} cells (every {sample_stride}th of the {int(np.sqrt(grid.n))}^2 grid) x "
+                      f"{steps} steps of dt=1e-6 s, FP64, {el:.1f} s",
+               single_thread_cells_per_s=sub1.n * steps / el1,
+               single_thread_sample=f"{sub1.n} cells x {steps} steps, {el1:.1f} s")
+    if one_step is not None and sample_stride == 1:
+        for name, rtol in (("fp64", 1e-10), ("fp32lu", 1e-6)):
+            if name in one_step["traces"]:
+                log(f"error of the {name} form against the oracle, every cell of one step")
+                out[f"error_vs_oracle_{name}_one_step"] = error_vs_oracle(
+                    om, grid, dt9, one_step["outs"][name], first, one_step["traces"][name], rtol)
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -489,6 +565,29 @@ def measured_traffic(launch_cells):
         return None
 
 
+VALU_PROFILE = os.path.join(HERE, "profiles", "valu_kin_lane_f64_mech9_grid1024.txt")
+
+
+def measured_valu(h):
+    """FP64 vector work of the headline kernel from the committed counter summary (rocprofv3 SQ
+    instruction counters over the same timed launches): floating-point operations per launch,
+    64 lanes per wave instruction, FMA 2, add, multiply and transcendental 1, over this run's
+    kernel time.  None when the summary is missing or the kernel has changed since."""
+    try:
+        with open(VALU_PROFILE) as f:
+            kv = dict(line.split("=", 1) for line in f.read().splitlines() if "=" in line and not line.startswith("#"))
+        if kv.get("kernel_source_hash", "").strip() != kernel_source_hash():
+            return None
+        flop = float(kv["fp64_flop_per_timed_run"])
+        secs = 1e-3 * float(np.sum(h["kernel_ms"]))
+        return {"fp64_flop_per_timed_run": flop, "achieved_TFLOPs_counter": flop / secs / 1e12,
+                "frac_counter": flop / secs / 1e12 / FP64_PEAK_TFLOPS,
+                "valu_fp64_share": float(kv["valu_fp64_share"]), "valu_busy": float(kv["valu_busy"]),
+                "source": os.path.relpath(VALU_PROFILE, HERE)}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,16 +605,19 @@ def main():
         print(json.dumps({"error": "this implementation runs on one GPU: the per-cell kinetics update has no "
                                    "cross-GPU exchange (cells shard trivially), so --gpus must be 1"}))
         sys.exit(2)
-    res, grid, m9, dt9 = run_gpu(args)
+    res, grid, m9, dt9, one_step = run_gpu(args)
     if grid is None:
         print(json.dumps({"only": args.only, "forms": res}))
         return
     cpu = None
     if not args.no_cpu and args.only == "all":
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(grid, m9, dt9, args.steps, 1 if not args.quick else 4)
+        cpu = cpu_baseline(grid, m9, dt9, args.steps, 1 if not args.quick else 4, one_step)
     h = res["mech9_fp64"]
     traffic = measured_traffic(grid.n)
+    from paper_1110_4903_amd import flops, synth
+    fl = flops.newton_iteration_flops(synth.mechanism("mech9"))
+    counters = measured_valu(h)
     side = int(np.sqrt(grid.n))
     line = {
         "metric": "cells/s advanced one dt (9-sp & 36-sp), FP32-LU vs FP64 at stated err; p99 latency",
@@ -535,7 +637,15 @@ def main():
                    "cells": grid.n, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": h["tflops_model"], "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": h["tflops_model"] / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "kin_lane_f64"},
+                     "kernel": "kin_lane_f64",
+                     "flops_per_newton_iteration": fl["total"],
+                     "flops_per_newton_iteration_exp_as_1": fl["total"] - (flops.TRANSCENDENTAL - 1) * fl["transcendentals"],
+                     "newton_iterations": int(np.sum(h["newton_iters"])),
+                     "kernel_seconds": 1e-3 * float(np.sum(h["kernel_ms"])),
+                     "frac_exp_as_1": (fl["total"] - (flops.TRANSCENDENTAL - 1) * fl["transcendentals"]) *
+                                      float(np.sum(h["newton_iters"])) / (1e-3 * float(np.sum(h["kernel_ms"]))) /
+                                      1e12 / FP64_PEAK_TFLOPS,
+                     "counters": counters},
         "cpu_baseline": cpu,
         "forms": res,
     }

@@ -77,7 +77,12 @@ typedef struct {
                               * per instance); an upload that finds no free block of its
                               * footprint fails with KIN_ENOMEM. */
     const char *tune_cache;  /* autotuner cache file (JSON); NULL = $KIN_TUNE_CACHE or none */
+    uint32_t flags;          /* KIN_CTX_* bits, 0 = none */
 } kin_ctx_opts;
+
+/* kin_ctx_opts.flags: record a pair of events on the launch stream right around the advance
+ * kernel of every single-instance kin_advance, for kin_kernel_times. */
+enum { KIN_CTX_TIME_KERNELS = 1 };
 
 /* Mechanism description (host memory, copied by kin_mech_upload; the caller keeps it).
  * Reactions have up to three reactant and three product entries (index, coefficient);
@@ -286,6 +291,14 @@ kin_status kin_state_reset_conserved(kin_ctx *ctx, int32_t inst_id, const double
  * Eq. operator_splitting. */
 kin_status kin_download_conserved(kin_ctx *ctx, int32_t inst_id, double *rho_s, double *E_sens,
                                   kin_mem where, void *stream);
+
+/* Durations (ms) of the advance kernels of the single-instance kin_advance calls made since
+ * the previous call, in launch order, measured by events recorded on the launch stream around
+ * each kernel (only with KIN_CTX_TIME_KERNELS; the work-counter clear and the ordering kernels
+ * of a cost-ordered step are outside).  Waits for those kernels.  Writes up to cap values into
+ * ms (may be NULL with cap 0), the number recorded into *count, and forgets them.
+ * Paper: Sec. 5.2 (the kernel's performance measured on the device). */
+kin_status kin_kernel_times(kin_ctx *ctx, double *ms, int32_t cap, int32_t *count);
 
 /* Wait for `stream` (NULL = the null stream).
  * Paper: no passage (stream synchronisation). */

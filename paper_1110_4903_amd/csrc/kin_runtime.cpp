@@ -103,6 +103,10 @@ struct kin_ctx {
     char *pool = nullptr;
     // the device's fixed memory for kin_advance_noalloc (counters, then workspace)
     unsigned char *scratch = nullptr;
+    // KIN_CTX_TIME_KERNELS: event pairs around advance kernels, the first kev_used recorded
+    bool time_kernels = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> kev;
+    size_t kev_used = 0;
     std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
 };
 
@@ -202,6 +206,7 @@ kin_status kin_create(kin_ctx **out, const kin_ctx_opts *o)
     c->device = o ? o->device : 0;
     if (c->device < 0 || c->device >= ndev) return err(KIN_EINVAL, "device ordinal out of range");
     c->budget = o ? o->hbm_budget : 0;
+    c->time_kernels = o && (o->flags & KIN_CTX_TIME_KERNELS);
     if (o && o->tune_cache) c->tune_cache = o->tune_cache;
     else if (const char *env = std::getenv("KIN_TUNE_CACHE")) c->tune_cache = env;
     if ((e = hipSetDevice(c->device)) != hipSuccess) return err(KIN_EDEVICE, hipGetErrorString(e));
@@ -235,6 +240,10 @@ void kin_destroy(kin_ctx *ctx)
         }
         for (hipStream_t st : ctx->cap) hipStreamDestroy(st);
         for (hipEvent_t ev : ctx->join) hipEventDestroy(ev);
+        for (auto &p : ctx->kev) {
+            hipEventDestroy(p.first);
+            hipEventDestroy(p.second);
+        }
         if (ctx->fork) hipEventDestroy(ctx->fork);
         hipFree(ctx->counters);
         if (ctx->pool) hipFree(ctx->pool);
@@ -1177,9 +1186,44 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
             a.span[0].order = ar.order;
         }
     }
+    hipEvent_t k1 = nullptr;
+    if (ctx->time_kernels) {
+        if (ctx->kev_used == ctx->kev.size()) {
+            hipEvent_t a0, a1;
+            KIN_HIP(ctx, hipEventCreate(&a0));
+            KIN_HIP(ctx, hipEventCreate(&a1));
+            ctx->kev.push_back({a0, a1});
+        }
+        KIN_HIP(ctx, hipEventRecord(ctx->kev[ctx->kev_used].first, st));
+        k1 = ctx->kev[ctx->kev_used].second;
+    }
     s = launch_spans(ctx, m, a, prec, layout, block, st);
-    if (s == KIN_OK) in.iters_current = true;
-    return s;
+    if (s != KIN_OK) return s;
+    if (k1) {
+        KIN_HIP(ctx, hipEventRecord(k1, st));
+        ctx->kev_used++;
+    }
+    in.iters_current = true;
+    return KIN_OK;
+}
+
+kin_status kin_kernel_times(kin_ctx *ctx, double *ms, int32_t cap, int32_t *count)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!count || cap < 0 || (cap > 0 && !ms)) return err(KIN_EINVAL, "bad kernel-time arguments");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    *count = (int32_t)ctx->kev_used;
+    for (size_t k = 0; k < ctx->kev_used; ++k) {
+        KIN_HIP(ctx, hipEventSynchronize(ctx->kev[k].second));
+        if ((int32_t)k < cap) {
+            float t = 0.f;
+            KIN_HIP(ctx, hipEventElapsedTime(&t, ctx->kev[k].first, ctx->kev[k].second));
+            ms[k] = t;
+        }
+    }
+    ctx->kev_used = 0;
+    return KIN_OK;
 }
 
 kin_status kin_advance_trace(kin_ctx *ctx, int32_t inst_id, double dt, kin_precision prec,

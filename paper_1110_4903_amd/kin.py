@@ -36,7 +36,7 @@ EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destr
            "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune",
            "kin_stream_create", "kin_stream_destroy", "kin_state_upload_conserved",
            "kin_download_conserved", "kin_state_reset_conserved", "kin_advance_noalloc",
-           "kin_advance_trace")
+           "kin_advance_trace", "kin_kernel_times")
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -56,7 +56,11 @@ class KinError(RuntimeError):
 
 
 class CtxOpts(C.Structure):
-    _fields_ = [("device", C.c_int32), ("hbm_budget", C.c_uint64), ("tune_cache", C.c_char_p)]
+    _fields_ = [("device", C.c_int32), ("hbm_budget", C.c_uint64), ("tune_cache", C.c_char_p),
+                ("flags", C.c_uint32)]
+
+
+CTX_TIME_KERNELS = 1
 
 
 class MechDesc(C.Structure):
@@ -88,6 +92,7 @@ _lib.kin_state_reset.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_advance_noalloc.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_advance_trace.argtypes = [_vp, _i32, C.c_double, C.c_int, _vp, _i32, _vp, _vp]
+_lib.kin_kernel_times.argtypes = [_vp, _vp, _i32, _vp]
 _lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_sync.argtypes = [_vp, _vp]
 _lib.kin_download_schedule.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
@@ -177,9 +182,11 @@ def _stream_handle(stream) -> Optional[int]:
 class Context:
     """A libkin context on one GPU."""
 
-    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_cache: Optional[str] = None):
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune_cache: Optional[str] = None,
+                 time_kernels: bool = False):
         self._h = C.c_void_p()
-        o = CtxOpts(device, hbm_budget, tune_cache.encode() if tune_cache else None)
+        o = CtxOpts(device, hbm_budget, tune_cache.encode() if tune_cache else None,
+                    CTX_TIME_KERNELS if time_kernels else 0)
         _check(_lib.kin_create(C.byref(self._h), C.byref(o)))
         self.mech_ns = {}
         self.inst_info = {}
@@ -300,6 +307,13 @@ class Context:
             raise ValueError("one dt per instance")
         _check(_lib.kin_advance_noalloc(self._h, ids.ctypes.data, dd.ctypes.data, int(ids.shape[0]), prec,
                                         C.byref(opts) if opts is not None else None, _stream_handle(stream)))
+
+    def kernel_times(self):
+        """Durations (ms) of the advance kernels since the last call (kin_kernel_times)."""
+        cnt = C.c_int32()
+        buf = np.zeros(4096, np.float64)
+        _check(_lib.kin_kernel_times(self._h, buf.ctypes.data, buf.shape[0], C.byref(cnt)))
+        return buf[:min(cnt.value, buf.shape[0])].tolist()
 
     def advance_trace(self, inst_id: int, dt: float, prec: int = FP64, opts: Optional[SolverOpts] = None,
                       words: int = 16):

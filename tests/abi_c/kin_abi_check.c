@@ -42,7 +42,7 @@ int main(void)
                        A, b, Ta, rev, tb, NULL};
 
     kin_ctx *ctx = NULL;
-    kin_ctx_opts o = {0, 0, NULL};
+    kin_ctx_opts o = {0, 0, NULL, 0};
     CHECK(kin_create(&ctx, &o));
     int32_t mid = -1, iid = -1;
     CHECK(kin_mech_upload(ctx, &d, &mid));
