@@ -286,6 +286,67 @@ def run_global_tier(torch, ctx, kin, flops, synth, args, stream):
     return res
 
 
+def run_fluid(torch, ctx, kin, synth, args, stream):
+    """The fluid step (Sec. 3.1: dimensionally split MP5 / HLLE sweeps, three Runge-Kutta stages
+    each) and the operator-split step (Sec. 2: the fluid step, then the chemistry sub-step through
+    the conserved-variable adapter) on the headline's band grid of the 9-species mixture, FP64,
+    periodic, 0.1 mm cells, with a shear flow u = 50 sin(2 pi y) m/s, v = 30 cos(2 pi x) m/s
+    added to the band state.  The conserved input is made by the library from (rho, T, Y) through
+    its adapter.  The step size is the CFL bound at 0.4.  Reported: fluid steps per second and
+    cells/s, the split step's time and the chemistry's share of it, and the fluid step's
+    algorithmic HBM bandwidth (each of the six stages reads its input state, stages 2 and 3 also
+    the sweep's start state, and writes its output: 128 (Ns + 3) bytes per cell-step)."""
+    nx = 256 if args.quick else 1024
+    m, grid, _ = synth.workload_grid_mech9(nx, nx)
+    ns, n = m.ns, grid.n
+    mid = ctx.mech_upload(m)
+    st = device_state(torch, grid)
+    iid = ctx.state_upload(mid, st["rho"], st["T"], st["Y"], stream=stream)
+    rho_s = torch.empty((ns, n), dtype=torch.float64, device="cuda")
+    Es = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.download_conserved_device(iid, rho_s, Es, stream=stream)
+    x = (torch.arange(nx, dtype=torch.float64, device="cuda") + 0.5) / nx
+    u = (50.0 * torch.sin(2 * np.pi * x))[:, None].expand(nx, nx).reshape(n)       # varies with y (rows)
+    v = (30.0 * torch.cos(2 * np.pi * x))[None, :].expand(nx, nx).reshape(n)       # varies with x
+    rho = st["rho"]
+    Q = torch.cat([rho_s, (rho * u)[None], (rho * v)[None], (Es + 0.5 * rho * (u * u + v * v))[None]]).contiguous()
+    fid = ctx.fluid_create(mid, nx, nx, 1e-4, 1e-4, kin.BC_PERIODIC)
+    ctx.fluid_upload(fid, Q, stream=stream)
+    dt = ctx.fluid_max_dt(fid, 0.4, stream=stream)
+    steps = args.steps
+    for k in range(2):
+        ctx.fluid_step(fid, dt, y_first=bool(k & 1), stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        ctx.fluid_step(fid, dt, y_first=bool(k & 1), stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_fluid = e0.elapsed_time(e1) * 1e-3 / steps
+    ctx.fluid_upload(fid, Q, stream=stream)
+    ctx.split_step(fid, iid, dt, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        ctx.split_step(fid, iid, dt, y_first=bool(k & 1), stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_split = e0.elapsed_time(e1) * 1e-3 / steps
+    status = ctx.download(iid)[2]
+    bytes_step = 128 * (ns + 3) * n
+    res = dict(grid=f"{nx}x{nx}", cells=n, dt=dt, steps=steps, fluid_ms_per_step=1e3 * t_fluid,
+               fluid_cells_per_s=n / t_fluid, split_ms_per_step=1e3 * t_split, split_cells_per_s=n / t_split,
+               chemistry_share_of_split=(t_split - t_fluid) / t_split,
+               chemistry_status_hist=np.bincount(status, minlength=4).tolist(),
+               algorithmic_bytes_per_cell_step=128 * (ns + 3), achieved_GB_s=bytes_step / t_fluid / 1e9,
+               hbm_peak_GB_s=8000.0, frac=bytes_step / t_fluid / 1e9 / 8000.0)
+    ctx.fluid_release(fid)
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+    return res
+
+
 def run_mech36(torch, ctx, kin, flops, synth, args, stream):
     n36 = (1 << 14) if args.quick else (1 << 18)
     m36, s36, dt36 = synth.workload_mech36(n36)
@@ -464,6 +525,9 @@ def run_gpu(args):
         if args.only in ("all", "global"):
             log("global-memory layout, 100 species, 65536 cells")
             res["gen100_global_fp64"] = run_global_tier(torch, ctx, kin, flops, synth, args, stream)
+        if args.only in ("all", "fluid"):
+            log("fluid step and operator-split step on the headline grid")
+            res["mech9_fluid_split_fp64"] = run_fluid(torch, ctx, kin, synth, args, stream)
     if args.only in ("all", "batch") and not args.no_batch:
         res["batch64"] = run_batch(torch, kin, synth, args, stream)
     if args.only in ("all", "serve") and not args.no_serve:
@@ -598,7 +662,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=80)
     ap.add_argument("--quick", action="store_true", help="small sizes, for smoke runs")
-    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "global", "batch", "serve", "copy"),
+    ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "global", "fluid", "batch", "serve", "copy"),
                     help="run one part (for profiler runs); the JSON line needs the headline")
     args = ap.parse_args()
     if args.gpus != 1:

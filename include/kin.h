@@ -365,6 +365,50 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
 kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double dt,
                         kin_precision prec, int32_t *layout, int32_t *block, double *best_ms);
 
+/* ---- The fluid step and the operator-split step ---------------------------------------------
+ * A fluid grid of nx x ny cells of one mechanism holds the conserved variables of Sec. 2,
+ * Q = (rho_s [Ns], rho u, rho v, E), as device memory [Ns + 3][ny][nx] (x fastest; SI units:
+ * kg/m^3, kg/(m^2 s), J/m^3), with E = sum_s rho_s e_s(T) + rho |u|^2 / 2 and each species'
+ * energy without its formation energy, e_s(T) - e_s(298.15 K) from the NASA-7 data (Sec. 2,
+ * Eq. energy; the same energy as the conserved-variable adapter above).  Pressure is Dalton's
+ * law (Eq. dalton) and the sound speed that of the frozen mixture, c^2 = (c_p / c_v) P / rho.
+ * Boundaries: KIN_BC_PERIODIC, or KIN_BC_OUTFLOW (zero-gradient) on all four sides. */
+enum { KIN_BC_PERIODIC = 0, KIN_BC_OUTFLOW = 1 };
+
+/* Create a fluid grid (spacings dx, dy in m) for a mechanism; the library allocates its state
+ * and workspace (about 3 (Ns + 3) + 4 doubles per cell plus the face fluxes).
+ * Paper: Sec. 4.1, the whole domain stored as one-dimensional arrays per variable. */
+kin_status kin_fluid_create(kin_ctx *ctx, int32_t mech_id, int32_t nx, int32_t ny, double dx, double dy,
+                            int32_t bc, int32_t *fluid_id);
+/* Free a fluid grid.  Paper: no passage (resource release). */
+kin_status kin_fluid_release(kin_ctx *ctx, int32_t fluid_id);
+/* Copy Q [Ns + 3][ny][nx] in or out (host copies complete before return, device copies are
+ * enqueued on `stream`).  Paper: Sec. 2 (the conserved variables) and Sec. 4.1 (their layout). */
+kin_status kin_fluid_upload(kin_ctx *ctx, int32_t fluid_id, const double *Q, kin_mem where, void *stream);
+/* Copy Q out, as kin_fluid_upload copies it in.  Paper: Sec. 2 and Sec. 4.1, as kin_fluid_upload. */
+kin_status kin_fluid_download(kin_ctx *ctx, int32_t fluid_id, double *Q, kin_mem where, void *stream);
+/* Largest stable step: cfl times min over cells of dx / (|u| + c) and dy / (|v| + c); waits for
+ * `stream`.  0 if a cell has no valid state.  Paper: Sec. 3.1 (the explicit time integration
+ * these bounds limit). */
+kin_status kin_fluid_max_dt(kin_ctx *ctx, int32_t fluid_id, double cfl, double *dt, void *stream);
+/* One convective step of dt (Sec. 3.1): dimensional splitting, an x sweep then a y sweep (the
+ * reverse with y_first != 0; alternating the order from step to step is the caller's choice),
+ * each sweep three stages of the third-order strong-stability-preserving Runge-Kutta scheme over
+ * the flux difference of MP5 faces (Eq. mp5, limited by Eqs. mp and ump, on the primitive
+ * variables rho_s, u_n, u_t, P) and the HLLE flux (Eq. fluxhlle, taken in its upwind form:
+ * (b+ F_L - b- F_R) / (b+ - b-) + b+ b- / (b+ - b-) (Q_R - Q_L)).  Asynchronous on `stream`.
+ * Paper: Sec. 3.1 (fluid dynamics) and Sec. 4.1 (one thread per cell or face). */
+kin_status kin_fluid_step(kin_ctx *ctx, int32_t fluid_id, double dt, int32_t y_first, void *stream);
+/* One operator-split step of dt (Sec. 2, Eq. operator_splitting): the convective step above,
+ * then the chemistry sub-step of the same cells through the conserved-variable adapter
+ * (kin_state_reset_conserved with the partial densities and E - rho |u|^2 / 2, kin_advance of
+ * dt with prec and s, kin_download_conserved back; momentum and kinetic energy are unchanged by
+ * the chemistry).  inst_id must be an instance of the fluid's mechanism with nx ny cells (its
+ * state is overwritten).  Asynchronous on `stream`.
+ * Paper: Sec. 2, Eq. operator_splitting, with Eq. energy for the formation-energy source. */
+kin_status kin_split_step(kin_ctx *ctx, int32_t fluid_id, int32_t inst_id, double dt, int32_t y_first,
+                          kin_precision prec, const kin_solver_opts *s, void *stream);
+
 /* Generate the lane-layout source for a mechanism and compile it for gfx950 with hipRTC,
  * without a device, both as kin_advance runs them and with the schedule recorder of
  * kin_advance_trace.  log (may be NULL) receives up to log_len bytes of compiler output.

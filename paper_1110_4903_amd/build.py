@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libkin.so")
-SOURCES = ["kin_runtime.cpp", "kin_codegen.cpp", "kin_wave.hip", "kin_global.hip", "kin_order.hip"]
+SOURCES = ["kin_runtime.cpp", "kin_codegen.cpp", "kin_wave.hip", "kin_global.hip", "kin_order.hip", "kin_fluid.hip"]
 HEADERS = ["kin_internal.h", "kin_lane_template.h", "kin_xlane.h"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -1,0 +1,314 @@
+// kin_fluid.hip -- the fluid step of the operator-split reactive Euler solver (Sec. 3.1), on a
+// 2-D grid whose cells hold the conserved variables of Sec. 2, Q = (rho_s [Ns], rho u, rho v, E),
+// E = sum_s rho_s e_s + rho |u|^2 / 2 with each species' energy taken without its formation
+// energy, e_s(T) = e_s^NASA(T) - e_s^NASA(T_ref), T_ref = 298.15 K (Sec. 2, Eq. energy); the
+// chemistry sub-step of the split (the conserved-variable adapter) uses the same energy.
+//
+// A step is dimensionally split: an x sweep then a y sweep (or the reverse).  A sweep is three
+// Runge-Kutta stages (the strong-stability-preserving third-order scheme), and a stage is three
+// kernels, each bound by HBM bandwidth:
+//   fluid_prim    per cell: Q -> primitive W = (rho_s, u, v, P) and T (Newton on the energy,
+//                 from the cell's previous T), with P from Dalton's law (Sec. 2, Eq. dalton);
+//   fluid_flux    per face: MP5 left and right states of every primitive variable (Sec. 3.1,
+//                 Eq. mp5) with the monotonicity-preserving bound (Eqs. mp, ump), and the HLLE
+//                 flux between them (Eq. fluxhlle);
+//   fluid_update  per cell: the stage's combination of the sweep's start state, the stage state
+//                 and dt times the flux difference.
+// One thread per cell or face; consecutive threads take consecutive x, so every array access
+// of a wavefront is one or two contiguous runs of a row.  The face kernel reads its six-cell
+// stencil from the primitive array, which neighbouring threads share through the caches.
+// Species are streamed (three passes per face), so no per-species array lives in registers.
+#include <hip/hip_runtime.h>
+
+#include "kin_internal.h"
+
+namespace kin {
+namespace {
+
+constexpr double kRuJ = 8.31446261815324e3;   // J/(kmol K): R / M with M in g/mol gives J/(kg K)
+constexpr double kAlphaMP = 2.0;
+
+__device__ __forceinline__ double minmod(double a, double b)
+{
+    return (a * b > 0.0) ? (a > 0.0 ? fmin(a, b) : fmax(a, b)) : 0.0;
+}
+
+// Left state of the face j + 1/2 from cells j-2..j+2 (Eq. mp5), limited by the median with u_j
+// and u_j + minmod(u_{j+1} - u_j, alpha (u_j - u_{j-1})) (Eqs. mp, ump); the right state is the
+// same function of the mirrored stencil.
+__device__ __forceinline__ double mp5(double um2, double um1, double u0, double up1, double up2)
+{
+    const double uL = (2.0 * um2 - 13.0 * um1 + 47.0 * u0 + 27.0 * up1 - 3.0 * up2) / 60.0;
+    const double ump = u0 + minmod(up1 - u0, kAlphaMP * (u0 - um1));
+    return uL + minmod(u0 - uL, ump - uL);
+}
+
+// Sensible energy e_s(T) - e_s(T_ref) (J/kg) and c_v,s (J/(kg K)) of species s.
+__device__ __forceinline__ void species_e_cv(const WaveTables &t, int s, double T, double &e, double &cv)
+{
+    const double *a = t.nasa + 14 * s + (T < t.Tmid[s] ? 0 : 7);
+    const double Rs = kRuJ / t.M[s];
+    const double cpR = fma(T, fma(T, fma(T, fma(T, a[4], a[3]), a[2]), a[1]), a[0]);
+    const double hR = fma(T, fma(T, fma(T, fma(T, fma(T, a[4] * 0.2, a[3] * 0.25), a[2] * (1.0 / 3.0)), a[1] * 0.5), a[0]), a[5]);
+    e = Rs * (hR - T) - t.ef[s];
+    cv = Rs * (cpR - 1.0);
+}
+
+struct Grid {
+    int ns, nx, ny, bc;   // bc: 0 periodic, 1 zero-gradient
+    long long n;          // nx * ny
+};
+
+__global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double *W, double *Tc)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int ns = g.ns;
+    const long long n = g.n;
+    double rho = 0.0, rR = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const double r = Q[(size_t)s * n + i];
+        rho += r;
+        rR = fma(r, kRuJ / t.M[s], rR);
+        W[(size_t)s * n + i] = r;
+    }
+    const double u = Q[(size_t)ns * n + i] / rho, v = Q[(size_t)(ns + 1) * n + i] / rho;
+    const double eint = Q[(size_t)(ns + 2) * n + i] - 0.5 * rho * (u * u + v * v);
+    double T = Tc[i];
+    if (!(T >= 100.0 && T <= 1e4)) T = 1000.0;
+    for (int it = 0; it < 60; ++it) {
+        double f = -eint, d = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            double e, cv;
+            species_e_cv(t, s, T, e, cv);
+            const double r = Q[(size_t)s * n + i];
+            f = fma(r, e, f);
+            d = fma(r, cv, d);
+        }
+        const double dT = f / d;
+        T -= dT;
+        if (!(fabs(dT) > 1e-13 * fabs(T))) break;   // converged, or not a number
+    }
+    Tc[i] = T;
+    W[(size_t)ns * n + i] = u;
+    W[(size_t)(ns + 1) * n + i] = v;
+    W[(size_t)(ns + 2) * n + i] = rR * T;
+}
+
+// Cell index along the sweep direction k (0..len-1 after the boundary rule) of an offset one.
+__device__ __forceinline__ int wrap(int k, int len, int bc)
+{
+    if (bc == 0) return k < 0 ? k + len : (k >= len ? k - len : k);
+    return k < 0 ? 0 : (k >= len ? len - 1 : k);
+}
+
+// Face fluxes of a sweep along x (DIR 0) or y (DIR 1).  Face a along the sweep lies between
+// cells a - 1 and a; faces are stored [var][ny][nx + 1] (x) or [var][ny + 1][nx] (y).
+template <int DIR>
+__global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double *F)
+{
+    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int fw = DIR == 0 ? g.nx + 1 : g.nx;      // faces per row of the face array
+    const int fh = DIR == 0 ? g.ny : g.ny + 1;
+    if (f >= (long long)fw * fh) return;
+    const int fx = (int)(f % fw), fy = (int)(f / fw);
+    const int a = DIR == 0 ? fx : fy;                 // face index along the sweep
+    const int len = DIR == 0 ? g.nx : g.ny;
+    const long long n = g.n;
+    const int ns = g.ns;
+    // cells a-3 .. a+2 along the sweep (j = a - 1 is the face's left cell)
+    long long c[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int q = wrap(a - 3 + k, len, g.bc);
+        c[k] = DIR == 0 ? (long long)fy * g.nx + q : (long long)q * g.nx + fx;
+    }
+    auto recon = [&](const double *w, double &L, double &R) {
+        const double v0 = w[c[0]], v1 = w[c[1]], v2 = w[c[2]], v3 = w[c[3]], v4 = w[c[4]], v5 = w[c[5]];
+        L = mp5(v0, v1, v2, v3, v4);
+        R = mp5(v5, v4, v3, v2, v1);
+    };
+    const double *Wun = W + (size_t)(DIR == 0 ? ns : ns + 1) * n;
+    const double *Wut = W + (size_t)(DIR == 0 ? ns + 1 : ns) * n;
+    double unL, unR, utL, utR, PL, PR;
+    recon(Wun, unL, unR);
+    recon(Wut, utL, utR);
+    recon(W + (size_t)(ns + 2) * n, PL, PR);
+    // pass 1: densities and gas constants of the two states
+    double rL = 0.0, rR = 0.0, RL = 0.0, RR = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        double L, R;
+        recon(W + (size_t)s * n, L, R);
+        const double Rs = kRuJ / t.M[s];
+        rL += L;
+        rR += R;
+        RL = fma(L, Rs, RL);
+        RR = fma(R, Rs, RR);
+    }
+    const double TL = PL / RL, TR = PR / RR;
+    // pass 2: energies and heat capacities at the two temperatures
+    double eL = 0.0, eR = 0.0, cvL = 0.0, cvR = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        double L, R, e, cv;
+        recon(W + (size_t)s * n, L, R);
+        species_e_cv(t, s, TL, e, cv);
+        eL = fma(L, e, eL);
+        cvL = fma(L, cv, cvL);
+        species_e_cv(t, s, TR, e, cv);
+        eR = fma(R, e, eR);
+        cvR = fma(R, cv, cvR);
+    }
+    const double EL = eL + 0.5 * rL * (unL * unL + utL * utL);
+    const double ER = eR + 0.5 * rR * (unR * unR + utR * utR);
+    const double cL = sqrt((cvL + RL) / cvL * PL / rL), cR = sqrt((cvR + RR) / cvR * PR / rR);
+    const double sL = sqrt(rL), sR = sqrt(rR);
+    const double uh = (sL * unL + sR * unR) / (sL + sR);
+    const double c2h = (sL * cL * cL + sR * cR * cR) / (sL + sR) +
+                       0.5 * sL * sR / ((sL + sR) * (sL + sR)) * (unR - unL) * (unR - unL);
+    const double ch = sqrt(c2h);
+    const double bp = fmax(0.0, fmax(uh + ch, unR + cR));
+    const double bm = fmin(0.0, fmin(uh - ch, unL - cL));
+    const double idb = 1.0 / (bp - bm), pm = bp * bm * idb;
+    auto hlle = [&](double FL, double FR, double QL, double QR) { return (bp * FL - bm * FR) * idb + pm * (QR - QL); };
+    const long long fo = DIR == 0 ? (long long)fy * (g.nx + 1) + fx : (long long)fy * g.nx + fx;
+    const long long fn = (long long)fw * fh;
+    // pass 3: species fluxes
+    for (int s = 0; s < ns; ++s) {
+        double L, R;
+        recon(W + (size_t)s * n, L, R);
+        F[(size_t)s * fn + fo] = hlle(L * unL, R * unR, L, R);
+    }
+    F[(size_t)(DIR == 0 ? ns : ns + 1) * fn + fo] =
+        hlle(rL * unL * unL + PL, rR * unR * unR + PR, rL * unL, rR * unR);
+    F[(size_t)(DIR == 0 ? ns + 1 : ns) * fn + fo] = hlle(rL * unL * utL, rR * unR * utR, rL * utL, rR * utR);
+    F[(size_t)(ns + 2) * fn + fo] = hlle(unL * (EL + PL), unR * (ER + PR), EL, ER);
+}
+
+// Qout = a0 Q0 + a1 (Q + dt L), L = -(F_{a+1} - F_a) / h (in place allowed: each thread reads
+// and writes only its own cell).
+template <int DIR>
+__global__ void fluid_update_kernel(Grid g, const double *Q0, const double *Q, double *Qout, const double *F,
+                                    double dt, double h, double a0, double a1)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int x = (int)(i % g.nx), y = (int)(i / g.nx);
+    const int nv = g.ns + 3;
+    const long long fn = DIR == 0 ? (long long)(g.nx + 1) * g.ny : (long long)g.nx * (g.ny + 1);
+    const long long fl = DIR == 0 ? (long long)y * (g.nx + 1) + x : i;
+    const long long fr = DIR == 0 ? fl + 1 : fl + g.nx;
+    for (int v = 0; v < nv; ++v) {
+        const double L = -(F[(size_t)v * fn + fr] - F[(size_t)v * fn + fl]) / h;
+        const double q = Q[(size_t)v * g.n + i] + dt * L;
+        Qout[(size_t)v * g.n + i] = a0 != 0.0 ? a0 * Q0[(size_t)v * g.n + i] + a1 * q : a1 * q;
+    }
+}
+
+// Largest (|u| + c) / dx and (|v| + c) / dy over the grid (positive doubles order like their
+// bit patterns, so an unsigned 64-bit atomic maximum finds it).
+__global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *W, const double *Tc, double dx, double dy,
+                                   unsigned long long *out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < g.n) {
+        const long long n = g.n;
+        double rho = 0.0, rR = 0.0, cv = 0.0;
+        const double T = Tc[i];
+        for (int s = 0; s < g.ns; ++s) {
+            const double rs = W[(size_t)s * n + i];
+            double e, cvs;
+            species_e_cv(t, s, T, e, cvs);
+            rho += rs;
+            rR = fma(rs, kRuJ / t.M[s], rR);
+            cv = fma(rs, cvs, cv);
+        }
+        const double P = W[(size_t)(g.ns + 2) * n + i];
+        const double c = sqrt((cv + rR) / cv * P / rho);
+        r = fmax((fabs(W[(size_t)g.ns * n + i]) + c) / dx, (fabs(W[(size_t)(g.ns + 1) * n + i]) + c) / dy);
+        if (!(r >= 0.0)) r = __builtin_inf();   // a bad cell makes the step size zero
+    }
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
+}
+
+// Kinetic energy of each cell (kept for the way back), and E - KE, the energy the chemistry
+// sub-step sees; after it, E = E_sens + KE with the same KE (chemistry changes neither the
+// density nor the momentum).
+__global__ void fluid_kinetic_kernel(Grid g, const double *Q, double *KE, double *Es)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const long long n = g.n;
+    double rho = 0.0;
+    for (int s = 0; s < g.ns; ++s) rho += Q[(size_t)s * n + i];
+    const double mx = Q[(size_t)g.ns * n + i], my = Q[(size_t)(g.ns + 1) * n + i];
+    const double ke = 0.5 * (mx * mx + my * my) / rho;
+    KE[i] = ke;
+    Es[i] = Q[(size_t)(g.ns + 2) * n + i] - ke;
+}
+
+__global__ void fluid_energy_back_kernel(Grid g, double *Q, const double *KE, const double *Es)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    Q[(size_t)(g.ns + 2) * g.n + i] = Es[i] + KE[i];
+}
+
+}  // namespace
+
+hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &fg, int dir, double dt, double h,
+                              double *Q, double *Q1, double *W, double *T, double *F, hipStream_t s)
+{
+    const Grid g{t.ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
+    const int block = 256;
+    const unsigned gc = (unsigned)((g.n + block - 1) / block);
+    const long long nf = dir == 0 ? (long long)(g.nx + 1) * g.ny : (long long)g.nx * (g.ny + 1);
+    const unsigned gf = (unsigned)((nf + block - 1) / block);
+    // (a0, a1, stage input, stage output): Q1 = Q + dt L(Q); Q1 <- 3/4 Q + 1/4 (Q1 + dt L(Q1));
+    // Q <- 1/3 Q + 2/3 (Q1 + dt L(Q1))
+    const double a0[3] = {0.0, 0.75, 1.0 / 3.0}, a1[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int k = 0; k < 3; ++k) {
+        const double *in = k == 0 ? Q : Q1;
+        double *out = k == 2 ? Q : Q1;
+        hipLaunchKernelGGL(fluid_prim_kernel, dim3(gc), dim3(block), 0, s, t, g, in, W, T);
+        if (dir == 0) {
+            hipLaunchKernelGGL(fluid_flux_kernel<0>, dim3(gf), dim3(block), 0, s, t, g, W, F);
+            hipLaunchKernelGGL(fluid_update_kernel<0>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
+        } else {
+            hipLaunchKernelGGL(fluid_flux_kernel<1>, dim3(gf), dim3(block), 0, s, t, g, W, F);
+            hipLaunchKernelGGL(fluid_update_kernel<1>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &fg, const double *Q, double *W, double *T,
+                              double dx, double dy, unsigned long long *out, hipStream_t s)
+{
+    const Grid g{t.ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
+    const int block = 256;
+    const unsigned gc = (unsigned)((g.n + block - 1) / block);
+    hipLaunchKernelGGL(fluid_prim_kernel, dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    hipLaunchKernelGGL(fluid_speed_kernel, dim3(gc), dim3(block), 0, s, t, g, W, T, dx, dy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluid_kinetic(const FluidGrid &fg, int ns, const double *Q, double *KE, double *Es, hipStream_t s)
+{
+    const Grid g{ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
+    const int block = 256;
+    hipLaunchKernelGGL(fluid_kinetic_kernel, dim3((unsigned)((g.n + block - 1) / block)), dim3(block), 0, s, g, Q, KE, Es);
+    return hipGetLastError();
+}
+
+hipError_t launch_fluid_energy_back(const FluidGrid &fg, int ns, double *Q, const double *KE, const double *Es,
+                                    hipStream_t s)
+{
+    const Grid g{ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
+    const int block = 256;
+    hipLaunchKernelGGL(fluid_energy_back_kernel, dim3((unsigned)((g.n + block - 1) / block)), dim3(block), 0, s, g, Q, KE, Es);
+    return hipGetLastError();
+}
+
+}  // namespace kin

@@ -206,6 +206,24 @@ constexpr int kScratchMaxDevices = 64;
 // device and kept.
 hipError_t scratch_address(int device, unsigned char **out);
 
+// Fluid grid (kin_fluid.hip): nx x ny cells, conserved variables [ns + 3][ny][nx]; bc 0 periodic,
+// 1 zero-gradient (transmissive) in both directions.
+struct FluidGrid {
+    int nx, ny, bc;
+};
+// One dimensionally split sweep (dir 0 = x, 1 = y) of dt: three Runge-Kutta stages of the MP5 /
+// HLLE update, Q in place; Q1 (stage state), W (primitives), T (temperatures, also the Newton
+// start values) and F (face fluxes, (ns + 3) (nx + 1) (ny + 1) doubles) are workspace.
+hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &g, int dir, double dt, double h, double *Q,
+                              double *Q1, double *W, double *T, double *F, hipStream_t s);
+// Largest (|u| + c) / dx, (|v| + c) / dy over the grid into *out (bit pattern, zero beforehand).
+hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &g, const double *Q, double *W, double *T,
+                              double dx, double dy, unsigned long long *out, hipStream_t s);
+// KE = rho |u|^2 / 2 and Es = E - KE per cell; and back, E = Es + KE.
+hipError_t launch_fluid_kinetic(const FluidGrid &g, int ns, const double *Q, double *KE, double *Es, hipStream_t s);
+hipError_t launch_fluid_energy_back(const FluidGrid &g, int ns, double *Q, const double *KE, const double *Es,
+                                    hipStream_t s);
+
 // Host launchers of the precompiled kernels (kin_wave.hip).
 int wave_npad(int n);
 hipError_t launch_conserved_in(const WaveTables &t, long long n, long long ld, double *rho, double *T,

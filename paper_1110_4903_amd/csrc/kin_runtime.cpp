@@ -70,6 +70,16 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static uint64_t inst_bytes(int ns, long long n) { return (uint64_t)arena_bytes(n, ns); }
 
+// A fluid grid: conserved state Q [ns + 3][ny][nx] and the workspace of its sweeps, one allocation.
+struct Fluid {
+    int mech = 0;
+    FluidGrid g{};
+    double dx = 0.0, dy = 0.0;
+    void *buf = nullptr;
+    double *Q = nullptr, *Q1 = nullptr, *W = nullptr, *T = nullptr, *F = nullptr, *KE = nullptr, *Es = nullptr;
+    unsigned long long *speed = nullptr;
+};
+
 // A cached, instantiated graph of one batched advance.
 struct Plan {
     hipGraphExec_t exec = nullptr;
@@ -89,7 +99,8 @@ struct kin_ctx {
     std::recursive_mutex mu;
     std::map<int, std::unique_ptr<kin::Mech>> mechs;
     std::map<int, std::unique_ptr<kin::Inst>> insts;
-    int next_mech = 1, next_inst = 1;
+    std::map<int, std::unique_ptr<kin::Fluid>> fluids;
+    int next_mech = 1, next_inst = 1, next_fluid = 1;
     // batched advances: capture streams (default priority), per-launch work counters and
     // instantiated graphs keyed by the launch description
     std::vector<hipStream_t> cap;
@@ -246,6 +257,7 @@ void kin_destroy(kin_ctx *ctx)
         }
         if (ctx->fork) hipEventDestroy(ctx->fork);
         hipFree(ctx->counters);
+        for (auto &kv : ctx->fluids) hipFree(kv.second->buf);
         if (ctx->pool) hipFree(ctx->pool);
         else
             for (auto &kv : ctx->insts) hipFree(kv.second->buf);
@@ -1527,6 +1539,170 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     if (layout_out) *layout_out = win.first;
     if (block_out) *block_out = win.second;
     if (best_ms) *best_ms = best;
+    return KIN_OK;
+}
+
+kin_status kin_fluid_create(kin_ctx *ctx, int32_t mech_id, int32_t nx, int32_t ny, double dx, double dy,
+                            int32_t bc, int32_t *fluid_id)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!fluid_id || nx < 1 || ny < 1 || !(dx > 0.0) || !(dy > 0.0) || !std::isfinite(dx) || !std::isfinite(dy) ||
+        (bc != KIN_BC_PERIODIC && bc != KIN_BC_OUTFLOW))
+        return err(KIN_EINVAL, "bad fluid grid arguments");
+    if ((long long)nx * ny > (1LL << 31)) return err(KIN_EINVAL, "fluid grid too large");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->mechs.find(mech_id);
+    if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");
+    Mech &m = *it->second;
+    std::unique_ptr<Fluid> f(new Fluid());
+    f->mech = mech_id;
+    f->g = FluidGrid{nx, ny, bc};
+    f->dx = dx;
+    f->dy = dy;
+    // arrays [var][n] with stride n = nx ny (the instance arena's layout of Y), each array
+    // starting on a 256-byte boundary
+    const size_t n = (size_t)nx * ny, nv = (size_t)m.h.ns + 3;
+    const size_t nf = nv * (size_t)(nx + 1) * (ny + 1);
+    auto up = [](size_t d) { return (d + 31) & ~(size_t)31; };
+    const size_t doubles = 3 * up(nv * n) + 3 * up(n) + 32 + up(nf);
+    KIN_HIP(ctx, hipMalloc(&f->buf, sizeof(double) * doubles));
+    double *p = static_cast<double *>(f->buf);
+    f->Q = p; p += up(nv * n);
+    f->Q1 = p; p += up(nv * n);
+    f->W = p; p += up(nv * n);
+    f->T = p; p += up(n);
+    f->KE = p; p += up(n);
+    f->Es = p; p += up(n);
+    f->speed = reinterpret_cast<unsigned long long *>(p); p += 32;
+    f->F = p;
+    // Newton start temperature of the first sweep
+    std::vector<double> T0(n, 1000.0);
+    KIN_HIP(ctx, hipMemcpy(f->T, T0.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    m.refs++;
+    const int id = ctx->next_fluid++;
+    ctx->fluids[id] = std::move(f);
+    *fluid_id = id;
+    return KIN_OK;
+}
+
+kin_status kin_fluid_release(kin_ctx *ctx, int32_t fluid_id)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->fluids.find(fluid_id);
+    if (it == ctx->fluids.end()) return err(KIN_ENOTFOUND, "unknown fluid id");
+    ctx->mechs[it->second->mech]->refs--;
+    KIN_HIP(ctx, hipFree(it->second->buf));
+    ctx->fluids.erase(it);
+    return KIN_OK;
+}
+
+static kin_status find_fluid(kin_ctx *ctx, int32_t fluid_id, Fluid *&f, Mech *&m)
+{
+    auto it = ctx->fluids.find(fluid_id);
+    if (it == ctx->fluids.end()) return err(KIN_ENOTFOUND, "unknown fluid id");
+    f = it->second.get();
+    m = ctx->mechs[f->mech].get();
+    return KIN_OK;
+}
+
+kin_status kin_fluid_upload(kin_ctx *ctx, int32_t fluid_id, const double *Q, kin_mem where, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!Q || !mem_ok(where)) return err(KIN_EINVAL, "bad fluid upload arguments");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Fluid *f;
+    Mech *m;
+    if ((s = find_fluid(ctx, fluid_id, f, m)) != KIN_OK) return s;
+    const size_t bytes = sizeof(double) * ((size_t)m->h.ns + 3) * (size_t)f->g.nx * f->g.ny;
+    return copy_in(ctx, f->Q, Q, bytes, where, static_cast<hipStream_t>(stream));
+}
+
+kin_status kin_fluid_download(kin_ctx *ctx, int32_t fluid_id, double *Q, kin_mem where, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!Q || !mem_ok(where)) return err(KIN_EINVAL, "bad fluid download arguments");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Fluid *f;
+    Mech *m;
+    if ((s = find_fluid(ctx, fluid_id, f, m)) != KIN_OK) return s;
+    const size_t bytes = sizeof(double) * ((size_t)m->h.ns + 3) * (size_t)f->g.nx * f->g.ny;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KIN_HIP(ctx, hipMemcpyAsync(Q, f->Q, bytes, out_kind(where), st));
+    if (where == KIN_MEM_HOST) KIN_HIP(ctx, hipStreamSynchronize(st));
+    return KIN_OK;
+}
+
+kin_status kin_fluid_max_dt(kin_ctx *ctx, int32_t fluid_id, double cfl, double *dt, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!dt || !(cfl > 0.0)) return err(KIN_EINVAL, "bad CFL arguments");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Fluid *f;
+    Mech *m;
+    if ((s = find_fluid(ctx, fluid_id, f, m)) != KIN_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KIN_HIP(ctx, launch_zero_u64(f->speed, 1, st));
+    KIN_HIP(ctx, launch_fluid_speed(m->tab, f->g, f->Q, f->W, f->T, f->dx, f->dy, f->speed, st));
+    unsigned long long bits = 0;
+    KIN_HIP(ctx, hipMemcpyAsync(&bits, f->speed, sizeof bits, hipMemcpyDeviceToHost, st));
+    KIN_HIP(ctx, hipStreamSynchronize(st));
+    double r;
+    std::memcpy(&r, &bits, sizeof r);
+    *dt = (r > 0.0 && std::isfinite(r)) ? cfl / r : 0.0;
+    return KIN_OK;
+}
+
+static kin_status fluid_step(kin_ctx *ctx, Fluid &f, Mech &m, double dt, int y_first, hipStream_t st)
+{
+    for (int k = 0; k < 2; ++k) {
+        const int dir = (k == 0) == (y_first == 0) ? 0 : 1;
+        KIN_HIP(ctx, launch_fluid_sweep(m.tab, f.g, dir, dt, dir == 0 ? f.dx : f.dy, f.Q, f.Q1, f.W, f.T, f.F, st));
+    }
+    return KIN_OK;
+}
+
+kin_status kin_fluid_step(kin_ctx *ctx, int32_t fluid_id, double dt, int32_t y_first, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return err(KIN_EINVAL, "dt must be finite and >= 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Fluid *f;
+    Mech *m;
+    if ((s = find_fluid(ctx, fluid_id, f, m)) != KIN_OK) return s;
+    return fluid_step(ctx, *f, *m, dt, y_first, static_cast<hipStream_t>(stream));
+}
+
+kin_status kin_split_step(kin_ctx *ctx, int32_t fluid_id, int32_t inst_id, double dt, int32_t y_first,
+                          kin_precision prec, const kin_solver_opts *sopt, void *stream)
+{
+    kin_status s = enter(ctx);
+    if (s != KIN_OK) return s;
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return err(KIN_EINVAL, "dt must be finite and >= 0");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    Fluid *f;
+    Mech *m;
+    if ((s = find_fluid(ctx, fluid_id, f, m)) != KIN_OK) return s;
+    auto iit = ctx->insts.find(inst_id);
+    if (iit == ctx->insts.end()) return err(KIN_ENOTFOUND, "unknown instance id");
+    const long long n = (long long)f->g.nx * f->g.ny;
+    if (iit->second->mech != f->mech || iit->second->n != n)
+        return err(KIN_EINVAL, "the instance must hold the fluid grid's cells, of the same mechanism");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((s = fluid_step(ctx, *f, *m, dt, y_first, st)) != KIN_OK) return s;
+    // the chemistry sub-step on the same cells: partial densities and sensible energy in, the
+    // fluid sweep's last temperatures as the inversion's start values, and back
+    KIN_HIP(ctx, launch_fluid_kinetic(f->g, m->h.ns, f->Q, f->KE, f->Es, st));
+    if ((s = kin_state_reset_conserved(ctx, inst_id, f->Q, f->Es, f->T, KIN_MEM_DEVICE, stream)) != KIN_OK) return s;
+    if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, sopt, stream)) != KIN_OK) return s;
+    if ((s = kin_download_conserved(ctx, inst_id, f->Q, f->Es, KIN_MEM_DEVICE, stream)) != KIN_OK) return s;
+    KIN_HIP(ctx, launch_fluid_energy_back(f->g, m->h.ns, f->Q, f->KE, f->Es, st));
     return KIN_OK;
 }
 

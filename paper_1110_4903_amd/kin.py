@@ -36,7 +36,10 @@ EXPORTS = ("kin_default_solver_opts", "kin_last_error", "kin_create", "kin_destr
            "kin_query", "kin_set_layout", "kin_jit_check", "kin_download_schedule", "kin_autotune",
            "kin_stream_create", "kin_stream_destroy", "kin_state_upload_conserved",
            "kin_download_conserved", "kin_state_reset_conserved", "kin_advance_noalloc",
-           "kin_advance_trace", "kin_kernel_times")
+           "kin_advance_trace", "kin_kernel_times", "kin_fluid_create", "kin_fluid_release",
+           "kin_fluid_upload", "kin_fluid_download", "kin_fluid_max_dt", "kin_fluid_step",
+           "kin_split_step")
+BC_PERIODIC, BC_OUTFLOW = 0, 1
 
 if not os.path.exists(SO):
     raise ImportError(f"{SO} is not built: run `python -m paper_1110_4903_amd.build`")
@@ -93,6 +96,13 @@ _lib.kin_advance.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_advance_noalloc.argtypes = [_vp, _vp, _vp, _i32, C.c_int, _vp, _vp]
 _lib.kin_advance_trace.argtypes = [_vp, _i32, C.c_double, C.c_int, _vp, _i32, _vp, _vp]
 _lib.kin_kernel_times.argtypes = [_vp, _vp, _i32, _vp]
+_lib.kin_fluid_create.argtypes = [_vp, _i32, _i32, _i32, C.c_double, C.c_double, _i32, _vp]
+_lib.kin_fluid_release.argtypes = [_vp, _i32]
+_lib.kin_fluid_upload.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
+_lib.kin_fluid_download.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
+_lib.kin_fluid_max_dt.argtypes = [_vp, _i32, C.c_double, _vp, _vp]
+_lib.kin_fluid_step.argtypes = [_vp, _i32, C.c_double, _i32, _vp]
+_lib.kin_split_step.argtypes = [_vp, _i32, _i32, C.c_double, _i32, C.c_int, _vp, _vp]
 _lib.kin_download.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp]
 _lib.kin_sync.argtypes = [_vp, _vp]
 _lib.kin_download_schedule.argtypes = [_vp, _i32, _vp, C.c_int, _vp]
@@ -307,6 +317,39 @@ class Context:
             raise ValueError("one dt per instance")
         _check(_lib.kin_advance_noalloc(self._h, ids.ctypes.data, dd.ctypes.data, int(ids.shape[0]), prec,
                                         C.byref(opts) if opts is not None else None, _stream_handle(stream)))
+
+    # -- fluid step and operator-split step ---------------------------------------------------
+    def fluid_create(self, mech_id: int, nx: int, ny: int, dx: float, dy: float, bc: int = BC_PERIODIC) -> int:
+        fid = C.c_int32()
+        _check(_lib.kin_fluid_create(self._h, mech_id, nx, ny, float(dx), float(dy), bc, C.byref(fid)))
+        self.fluid_info = getattr(self, "fluid_info", {})
+        self.fluid_info[fid.value] = (self.mech_ns[mech_id] + 3, ny, nx)
+        return fid.value
+
+    def fluid_release(self, fluid_id: int):
+        _check(_lib.kin_fluid_release(self._h, fluid_id))
+
+    def fluid_upload(self, fluid_id: int, Q, stream=None):
+        p, kind = _ptr(Q)
+        _check(_lib.kin_fluid_upload(self._h, fluid_id, p, kind, _stream_handle(stream)))
+
+    def fluid_download(self, fluid_id: int):
+        Q = np.empty(self.fluid_info[fluid_id])
+        _check(_lib.kin_fluid_download(self._h, fluid_id, Q.ctypes.data, MEM_HOST, None))
+        return Q
+
+    def fluid_max_dt(self, fluid_id: int, cfl: float, stream=None) -> float:
+        dt = C.c_double()
+        _check(_lib.kin_fluid_max_dt(self._h, fluid_id, float(cfl), C.byref(dt), _stream_handle(stream)))
+        return dt.value
+
+    def fluid_step(self, fluid_id: int, dt: float, y_first: bool = False, stream=None):
+        _check(_lib.kin_fluid_step(self._h, fluid_id, float(dt), int(bool(y_first)), _stream_handle(stream)))
+
+    def split_step(self, fluid_id: int, inst_id: int, dt: float, y_first: bool = False, prec: int = FP64,
+                   opts: Optional[SolverOpts] = None, stream=None):
+        _check(_lib.kin_split_step(self._h, fluid_id, inst_id, float(dt), int(bool(y_first)), prec,
+                                   C.byref(opts) if opts is not None else None, _stream_handle(stream)))
 
     def kernel_times(self):
         """Durations (ms) of the advance kernels since the last call (kin_kernel_times)."""

@@ -81,7 +81,7 @@ def test_c_program_compiles_against_header(tmp_path):
 # Results, 5.2 Performance Results), 6 Conclusion, Appendix A.
 PAPER_SECTIONS = {"1", "2", "3", "3.1", "3.2", "4", "4.1", "4.2", "5", "5.1", "5.2", "6"}
 # Calls that serve no passage of the paper (library plumbing) say so explicitly.
-PLUMBING = {"kin_last_error", "kin_destroy", "kin_sync"}
+PLUMBING = {"kin_last_error", "kin_destroy", "kin_sync", "kin_fluid_release"}
 # The allocation-free advance names the callers it is for in place of a passage.
 NO_ALLOC = {"kin_advance_noalloc"}
 
