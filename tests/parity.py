@@ -60,25 +60,58 @@ def compare(gpu, ref, rho, Y0, dt, om, rtol, sample=None, extra=None):
     )
 
 
-def point_implicit_floor(om, rho, Y0, T0, Y1, T1, dt, eps):
+def point_implicit_floor(om, rho, Y0, T0, Y1, T1, dt, eps, cap=1e-6):
     """Extra tolerance of the point-implicit step, whose result is a single linear solve
     (I - dt J(x_n)) dx = dt f(x_n) with no Newton correction: a perturbation of A of relative
     size eps moves dx by up to cond(A) eps |dx|.  The mass-fraction floor is
-    1e3 eps cond_1(D A) |dx_s| per cell, with D the row equilibration the FP32-LU form applies.
-    The temperature follows from the mass fractions through e(Y, T) = e0, so its floor is
-    sum_s |e_s| floor_s / c_v."""
+    1e3 eps cond_1(D A) |dx_s| per cell, with D the row equilibration the FP32-LU form applies,
+    capped at cap |dx_s|.  The temperature follows from the mass fractions through
+    e(Y, T) = e0, so its floor is sum_s |e_s| floor_s / c_v.  Returns (floor_Y, floor_T, over):
+    `over` marks the cells whose uncapped floor passed the cap; the value gate does not hold
+    for them, and their solve is checked by its backward error instead (point_implicit_residual)."""
     n, ns = Y0.shape[1], Y0.shape[0]
     fy = np.zeros_like(Y0)
     ft = np.zeros(n)
+    over = np.zeros(n, bool)
     unit = np.eye(ns)
     for c in range(n):
         x = np.r_[Y0[:, c], T0[c]]
         A = np.eye(ns + 1) - dt * om.jacobian(rho[c], x)
         A = A / np.abs(A).max(axis=1, keepdims=True)
-        fy[:, c] = 1e3 * eps * np.linalg.cond(A, 1) * np.abs(Y1[:, c] - Y0[:, c])
+        k = 1e3 * eps * np.linalg.cond(A, 1)
+        over[c] = k > cap
+        fy[:, c] = min(k, cap) * np.abs(Y1[:, c] - Y0[:, c])
         es = np.array([om.energy(unit[s], T1[c]) for s in range(ns)])
         ft[c] = np.abs(es) @ fy[:, c] / om.cv(Y1[:, c], T1[c])
-    return fy, ft
+    return fy, ft, over
+
+
+def point_implicit_residual(om, rho, Y0, T0, Y_gpu, dt):
+    """Componentwise backward error of the GPU's point-implicit solve, evaluated in long double
+    with the oracle's J(x_n) and f(x_n): dx_Y = Y_gpu - Y0 and the temperature change dx_T that
+    fits the whole system best (the GPU reports T after the energy inversion, not T + dx_T:
+    weighted least squares over all rows, weights the rows' scales, two passes), then max over
+    the rows of |r_i| / (sum_j |A_ij| (|dx_j| + eps |Y_gpu,j|) + dt |f_i|), r = A dx - dt f
+    (the eps term covers the rounding of Y0 + dx).  Small whatever cond(A) is: it checks the
+    solve itself, not its sensitivity."""
+    n, ns = Y0.shape[1], Y0.shape[0]
+    out = np.zeros(n)
+    ld = np.longdouble
+    for c in range(n):
+        x = np.r_[Y0[:, c], T0[c]]
+        A = np.eye(ns + 1, dtype=ld) - ld(dt) * om.jacobian(rho[c], x).astype(ld)
+        b = ld(dt) * om.rhs(rho[c], x).astype(ld)
+        dx = np.zeros(ns + 1, dtype=ld)
+        dx[:ns] = Y_gpu[:, c].astype(ld) - Y0[:, c].astype(ld)
+        rest = A[:, :ns] @ dx[:ns] - b              # residual without the temperature change
+        roun = np.abs(A[:, :ns]) @ (EPS64 * np.abs(Y_gpu[:, c]).astype(ld))
+        scale = np.abs(A[:, :ns]) @ np.abs(dx[:ns]) + np.abs(b) + roun
+        for _ in range(2):
+            w2 = 1 / scale ** 2
+            dx[ns] = -np.sum(w2 * A[:, ns] * rest) / np.sum(w2 * A[:, ns] ** 2)
+            scale = np.abs(A) @ np.abs(dx) + np.abs(b) + roun
+        out[c] = float(np.max(np.abs(rest + A[:, ns] * dx[ns]) / scale))
+    return out
 
 
 def gpu_traces(ctx, mech_id, st, dt, prec, opts=None, steps=1, words=64):

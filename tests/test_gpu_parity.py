@@ -462,10 +462,15 @@ def test_autotune_is_per_size_class(ctx, orc, tmp_path):
 def test_point_implicit_both_layouts(ctx, orc):
     """The paper's point-implicit step (one linearised backward-Euler step over dt), FP64: mech9
     through both layouts and mech36 through the wave layout, against the oracle.  Gate: 1e-10
-    relative plus the conditioning floor of a single linear solve
-    (tests/parity.point_implicit_floor); one iteration and level 0 everywhere.  The FP32-LU
-    form is refused for this step (no Newton refinement)."""
-    from tests.parity import compare, point_implicit_floor
+    relative plus the conditioning floor of a single linear solve, capped at 1e-6 |dx|
+    (tests/parity.point_implicit_floor); cells whose floor would pass the cap (condition numbers
+    beyond about 4e6) are compared instead by the componentwise backward error of the GPU's solve
+    against the oracle's J and f in long double (tests/parity.point_implicit_residual, gate 1e-8:
+    the oracle's own elimination reaches 1e-9 on these stiff matrices, and a 1e-6 relative error
+    planted in one component of dx gives 1e-7), and counted.
+    One iteration and level 0 everywhere.  The FP32-LU form is refused for this step (no Newton
+    refinement)."""
+    from tests.parity import compare, point_implicit_floor, point_implicit_residual
     from paper_1110_4903_amd import kin
     prec, rtol, eps = 0, 1e-10, np.finfo(np.float64).eps
     cases = [("mech9", synth.uniform_cells(23, 2000, 9, 1.0), 1e-7, kin.LAYOUT_LANE),
@@ -475,11 +480,19 @@ def test_point_implicit_both_layouts(ctx, orc):
         m = synth.mechanism(name)
         gpu = run_gpu(ctx, m, st, dt, prec=prec, opts=kin.solver_opts(layout=layout, point_implicit=1))
         om, ref = run_oracle(orc, m, st, dt, point_implicit=1)
-        extra = point_implicit_floor(om, st.rho, st.Y, st.T, ref[1], ref[0], dt, eps)
-        s = compare(gpu, ref, st.rho, st.Y, dt, om, rtol, extra=extra)
+        fy, ft, over = point_implicit_floor(om, st.rho, st.Y, st.T, ref[1], ref[0], dt, eps)
+        keep = np.flatnonzero(~over)
+        s = compare(tuple(a[..., keep] for a in gpu), tuple(a[..., keep] for a in ref), st.rho[keep],
+                    st.Y[:, keep], dt, om, rtol, extra=(fy[:, keep], ft[keep]))
+        hard = np.flatnonzero(over & (gpu[2] < 2) & (ref[2] < 2))
+        be = point_implicit_residual(om, st.rho[hard], st.Y[:, hard], st.T[hard], gpu[1][:, hard], dt)
+        s.update(floor_capped_cells=int(over.sum()), backward_checked=int(hard.size),
+                 max_backward_error=float(be.max()) if be.size else 0.0)
         report(f"point-implicit {name} layout={layout}", s)
         assert np.all(gpu[3] == 0) and np.all(gpu[4][gpu[2] < 3] == 1)
-        assert s["status_mismatch"] == 0 and s["fail_Y"] == 0 and s["fail_T"] == 0, s
+        assert np.array_equal(gpu[2], ref[2])
+        assert s["fail_Y"] == 0 and s["fail_T"] == 0, s
+        assert np.all(be <= 1e-8), be.max()
     m = synth.mechanism("mech9")
     st = synth.uniform_cells(25, 8, 9, 1.0)
     with pytest.raises(kin.KinError) as e:
