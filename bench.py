@@ -540,8 +540,9 @@ def error_vs_oracle(om, grid, dt, gpu, ref, trace, rtol):
     sub-step schedule (status, level, schedule hash) matches the oracle's own are compared with
     its adaptive step, the others with the oracle following the GPU's recorded schedule.  Per
     result: the largest relative error of T and of the mass fractions of at least 1e-14, the
-    99.9th percentile of the latter, and the count of results beyond the form's gate rtol (mass
-    fractions of at least 1e-10; smaller ones are reported by their largest absolute error)."""
+    99.9th percentile of the latter, the count of results beyond the form's gate rtol (mass
+    fractions of at least 1e-10; smaller ones are reported by their largest absolute error) and
+    the count of cells with any result beyond it."""
     same = (gpu[2] == ref[2]) & (gpu[3] == ref[3]) & (gpu[5] == ref[5])
     mis = np.flatnonzero(~same)
     Tr, Yr, sr = ref[0].copy(), ref[1].copy(), ref[2].copy()
@@ -564,6 +565,7 @@ def error_vs_oracle(om, grid, dt, gpu, ref, trace, rtol):
                 max_rel_Y=float(rel.max()), p999_rel_Y=float(np.quantile(rel[big], 0.999)),
                 max_rel_T=float(relT.max()), beyond_gate_Y=int((gated & (rel > rtol)).sum()),
                 beyond_gate_T=int((relT > rtol).sum()),
+                cells_beyond_gate=int(((gated & (rel > rtol)).any(0) | (relT > rtol)).sum()),
                 max_abs_Y_below_1em10=float(dY[~gated].max()) if (~gated).any() else 0.0)
 
 
