@@ -105,6 +105,13 @@ __device__ __forceinline__ bool kin_invert_T(const double *Kp, const double (&x)
 // In-register LU with partial pivoting (first row of largest |a_ik|), applied to the
 // right-hand side as it goes, then back substitution.  R is the factorisation type.
 // Returns false on an exactly zero pivot.
+//
+// The row exchange is done with selects, since a register file cannot be indexed by a
+// per-lane row.  It is done row by row, and only for the rows that are some lane's pivot row
+// in this column (a wavefront-uniform test per row): each lane exchanges with exactly one row,
+// so the result is that of the exchange, and a wavefront pays for the rows its lanes use
+// rather than for every row below the diagonal.  The reciprocal of each pivot replaces the
+// pivot in U, for the multipliers and the back substitution alike.
 template <typename R>
 __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N])
 {
@@ -121,28 +128,25 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
             p = gt ? i : p;
         }
         ok = ok && (amax != R(0));
-        // Row exchange by selects; skipped for the whole wavefront when no lane pivots off
-        // the diagonal (the common case for I - hJ at moderate h).
         if (__any(p != k)) {
 #pragma unroll
-            for (int j = k; j < KIN_N; ++j) {
-                const R rk = A[k][j];
-                R pv = rk;
+            for (int i = k + 1; i < KIN_N; ++i) {
+                if (__any(p == i)) {
+                    const bool sw = p == i;
 #pragma unroll
-                for (int i = k + 1; i < KIN_N; ++i) pv = (p == i) ? A[i][j] : pv;
-#pragma unroll
-                for (int i = k + 1; i < KIN_N; ++i) A[i][j] = (p == i) ? rk : A[i][j];
-                A[k][j] = pv;
+                    for (int j = k; j < KIN_N; ++j) {
+                        const R rk = A[k][j], ri = A[i][j];
+                        A[k][j] = sw ? ri : rk;
+                        A[i][j] = sw ? rk : ri;
+                    }
+                    const R rk = b[k], ri = b[i];
+                    b[k] = sw ? ri : rk;
+                    b[i] = sw ? rk : ri;
+                }
             }
-            const R rk = b[k];
-            R pv = rk;
-#pragma unroll
-            for (int i = k + 1; i < KIN_N; ++i) pv = (p == i) ? b[i] : pv;
-#pragma unroll
-            for (int i = k + 1; i < KIN_N; ++i) b[i] = (p == i) ? rk : b[i];
-            b[k] = pv;
         }
         const R inv = R(1) / A[k][k];
+        A[k][k] = inv;
 #pragma unroll
         for (int i = k + 1; i < KIN_N; ++i) {
             const R l = A[i][k] * inv;
@@ -156,7 +160,7 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
         R s = b[i];
 #pragma unroll
         for (int j = i + 1; j < KIN_N; ++j) s = fma(-A[i][j], b[j], s);
-        b[i] = s / A[i][i];
+        b[i] = s * A[i][i];
     }
     return ok;
 }
@@ -166,7 +170,7 @@ enum { KIN_CONTINUE = 0, KIN_ACCEPTED = 1, KIN_ATTEMPT_FAILED = 2 };
 
 // One Newton iteration on the backward-Euler system of sub-step size h started from x:
 // updates the iterate xk.  F32: the Newton matrix and right-hand side are row-equilibrated
-// in FP64, rounded to FP32, factored and solved in FP32; the correction is promoted back to
+// in FP64 (by powers of two, so exactly), rounded to FP32, factored and solved in FP32; the correction is promoted back to
 // FP64 (residual, rates and exponentials stay FP64).  On convergence the iterate is checked
 // for negative mass fractions and its temperature is reset to the root of e(Y, T) = e0.
 template <bool F32>
@@ -178,15 +182,16 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
     double A[KIN_N][KIN_N];
     kin_eval(kin_launder(a.K), rho, xk, f, A);
     double b[KIN_N];
+    // chk stays 0 exactly when every entry is finite (0 times an infinity or a NaN is a NaN)
     double chk = 0.0;
 #pragma unroll
     for (int i = 0; i < KIN_N; ++i) {
         b[i] = -((xk[i] - x[i]) - h * f[i]);
-        chk += b[i] - b[i];
+        chk = fma(0.0, b[i], chk);
 #pragma unroll
         for (int j = 0; j < KIN_N; ++j) {
             A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
-            chk += A[i][j] - A[i][j];
+            chk = fma(0.0, A[i][j], chk);
         }
     }
     if (!(chk == 0.0)) return KIN_ATTEMPT_FAILED;  // some entry of A or G is not finite
@@ -207,13 +212,15 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
         float Af[KIN_N][KIN_N], bf[KIN_N];
 #pragma unroll
         for (int i = 0; i < KIN_N; ++i) {
+            // scale the row by the power of two that brings its largest entry into [0.5, 1)
             double m = 0.0;
 #pragma unroll
             for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(P[i][j]));
-            const double s = 1.0 / m;
+            int e;
+            (void)frexp(m, &e);
 #pragma unroll
-            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)(P[i][j] * s);
-            bf[i] = (float)(q[i] * s);
+            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)ldexp(P[i][j], -e);
+            bf[i] = (float)ldexp(q[i], -e);
         }
         if (!kin_lu_solve<float>(Af, bf)) return KIN_ATTEMPT_FAILED;
 #pragma unroll
@@ -261,18 +268,31 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
 
 // Persistent lanes.  Every loop trip performs one Newton iteration for the cell each lane
 // holds, so lanes whose cells need many iterations (sub-step halving) do not hold back the
-// rest of their wavefront: a lane that finishes its cell stores it and takes the next cell
-// index from a global counter (one atomic per wavefront per refill).
+// rest of their wavefront: a lane that finishes its cell stores it and takes the next cell.
+//
+// Cells reach the lanes through a per-wavefront queue in LDS: the wavefront claims KIN_QCHUNK
+// consecutive launch positions with one atomic, and its 64 lanes load those cells' states into
+// the queue together; lanes that need a cell then read a queue slot.  One claim and one load
+// round trip serve 64 refills, and the cache lines of neighbouring cells are read and written
+// by one wavefront, through one L2, instead of by whichever wavefronts of the device refilled
+// at that moment.
 //
 // Sub-stepping is dyadic, time counted in ticks of dt 2^-Lc so that every sub-step boundary
 // is exact.  Adaptive (L_forced < 0): start at h = dt, halve on a failed attempt and retry
 // from the last accepted state, double after an accepted sub-step that ends on a boundary of
 // the doubled step; a level beyond L_max or more than max_iters Newton iterations fail the
 // cell, which keeps its input state.  Replay (L_forced >= 0): 2^L_forced equal sub-steps.
+#define KIN_QCHUNK 64
+#define KIN_QV (KIN_N + 3)   // queued doubles per cell: rho, e0, dt, then Y_1..Y_Ns, T
+#define KIN_QI 4             // queued integers per cell: arena base, span cells, cell, launch cell
+
 template <bool F32>
 __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
 {
+    __shared__ double kin_qv[KIN_BLOCK / 64][KIN_QV][KIN_QCHUNK];
+    __shared__ long long kin_qi[KIN_BLOCK / 64][KIN_QI][KIN_QCHUNK];
     const int lane = (int)(threadIdx.x & 63u);
+    const int wv = (int)(threadIdx.x >> 6);
     const bool adapt = a.L_forced < 0;
     const int Lc = adapt ? a.L_max : a.L_forced;
     const unsigned long long end = 1ull << Lc;
@@ -282,7 +302,9 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     long long nspan_cells = 0;
     double dt = 0.0;
     bool need = true;    // the lane has no cell in progress
-    bool done = false;   // the counter ran past the last cell
+    bool done = false;   // no cell is left for the lane
+    int qn = 0, qh = 0;  // valid slots of the wavefront's queue, next slot to hand out
+    bool qend = false;   // the counter ran past the last cell
     double rho = 0.0, e0 = 0.0;
     double x[KIN_N], xk[KIN_N];
 #pragma unroll
@@ -296,65 +318,100 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
 #endif
 
     for (;;) {
-        // ---- hand new cells to lanes that need one ----------------------------------------
+        // ---- hand queued cells to lanes that need one, refilling the queue ---------------------
+        // Take the cell in queue slot q: its state to registers, or, for an invalid input,
+        // status 3 written at once (the lane then still needs a cell).
+        auto take = [&](const int q) {
+            base = (char *)kin_qi[wv][0][q];
+            nspan_cells = kin_qi[wv][1][q];
+            i = kin_qi[wv][2][q];
+#ifdef KIN_TRACE
+            tr = a.trace + (size_t)kin_qi[wv][3][q] * a.trace_words;
+            tr[0] = 0;
+#endif
+            need = false;
+            rho = kin_qv[wv][0][q];
+            e0 = kin_qv[wv][1][q];
+            dt = kin_qv[wv][2][q];
+#pragma unroll
+            for (int s = 0; s < KIN_N; ++s) x[s] = kin_qv[wv][3 + s][q];
+            double chk = rho - rho + e0 - e0 + dt - dt;
+#pragma unroll
+            for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
+            if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
+                x[KIN_NS] > KIN_T_MAX) {
+                kin_stat(base, nspan_cells, 0)[i] = 3;
+                kin_stat(base, nspan_cells, 1)[i] = 0;
+                kin_stat(base, nspan_cells, 2)[i] = 0;
+                kin_sched(base, nspan_cells)[i] = KIN_SCHED_SEED;
+                need = true;
+            } else {
+#pragma unroll
+                for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
+                t = 0;
+                l = adapt ? 0 : a.L_forced;
+                level = l;
+                k = 0;
+                iters = 0;
+                failed = false;
+                hsh = KIN_SCHED_SEED;
+            }
+        };
         const unsigned long long want = __ballot(need && !done);
         if (want) {
-            const int leader = __ffsll((long long)want) - 1;
             const int cnt = __popcll(want);
-            unsigned long long gbase = 0;
-            if (lane == leader) gbase = atomicAdd(a.counter, (unsigned long long)cnt);
-            gbase = __shfl(gbase, leader);
-            if (need && !done) {
-                const unsigned int lo = (unsigned int)want, hi = (unsigned int)(want >> 32);
-                const int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-                const unsigned long long gi = gbase + (unsigned long long)rank;
-                if (gi >= (unsigned long long)a.total) {
-                    done = true;
-                    i = -1;
-                } else {
+            const unsigned int lo = (unsigned int)want, hi = (unsigned int)(want >> 32);
+            const int rank = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            const bool wants = need && !done;
+            // first from what is left in the queue (read before the queue is refilled) ...
+            const int take1 = min(cnt, qn - qh);
+            if (wants && rank < take1) take(qh + rank);
+            qh += take1;
+            // ... then from a freshly claimed chunk
+            if (cnt > take1 && !qend) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                unsigned long long g0 = 0;
+                if (lane == 0) g0 = atomicAdd(a.counter, (unsigned long long)KIN_QCHUNK);
+                g0 = __shfl(g0, 0);
+                const long long left = a.total - (long long)g0;
+                qn = left <= 0 ? 0 : (left < KIN_QCHUNK ? (int)left : KIN_QCHUNK);
+                qh = 0;
+                qend = qn == 0;
+                if (lane < qn) {
+                    const unsigned long long gi = g0 + (unsigned long long)lane;
                     int j = 0;
                     while (j + 1 < a.nspan && (unsigned long long)a.span[j + 1].start <= gi) ++j;
-                    base = a.span[j].base;
-                    nspan_cells = a.span[j].n;
-                    dt = a.span[j].dt;
-                    i = (long long)gi - a.span[j].start;
+                    char *b = a.span[j].base;
+                    const long long n = a.span[j].n;
+                    long long c = (long long)gi - a.span[j].start;
                     if (a.span[j].order) {
-                        const long long c = a.span[j].order[i];
-                        if ((unsigned long long)c < (unsigned long long)nspan_cells) i = c;
+                        const long long o = a.span[j].order[c];
+                        if ((unsigned long long)o < (unsigned long long)n) c = o;
                     }
-#ifdef KIN_TRACE
-                    tr = a.trace + (size_t)(a.span[j].start + i) * a.trace_words;
-                    tr[0] = 0;
-#endif
-                    need = false;
-                    const double *Yin = kin_Y(base, nspan_cells);
-                    rho = kin_rho(base, nspan_cells)[i];
-                    e0 = kin_e0(base, nspan_cells)[i];
+                    const double *Yin = kin_Y(b, n);
+                    kin_qv[wv][0][lane] = kin_rho(b, n)[c];
+                    kin_qv[wv][1][lane] = kin_e0(b, n)[c];
+                    kin_qv[wv][2][lane] = a.span[j].dt;
 #pragma unroll
-                    for (int s = 0; s < KIN_NS; ++s) x[s] = Yin[s * nspan_cells + i];
-                    x[KIN_NS] = kin_T(base, nspan_cells)[i];
-                    double chk = rho - rho + e0 - e0 + dt - dt;
-#pragma unroll
-                    for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
-                    if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
-                        x[KIN_NS] > KIN_T_MAX) {
-                        kin_stat(base, nspan_cells, 0)[i] = 3;
-                        kin_stat(base, nspan_cells, 1)[i] = 0;
-                        kin_stat(base, nspan_cells, 2)[i] = 0;
-                        kin_sched(base, nspan_cells)[i] = KIN_SCHED_SEED;
-                        need = true;
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
-                        t = 0;
-                        l = adapt ? 0 : a.L_forced;
-                        level = l;
-                        k = 0;
-                        iters = 0;
-                        failed = false;
-                        hsh = KIN_SCHED_SEED;
-                    }
+                    for (int s = 0; s < KIN_NS; ++s) kin_qv[wv][3 + s][lane] = Yin[s * n + c];
+                    kin_qv[wv][3 + KIN_NS][lane] = kin_T(b, n)[c];
+                    kin_qi[wv][0][lane] = (long long)b;
+                    kin_qi[wv][1][lane] = n;
+                    kin_qi[wv][2][lane] = c;
+                    kin_qi[wv][3][lane] = a.span[j].start + c;
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int take2 = min(cnt - take1, qn);
+                if (wants && rank >= take1 && rank - take1 < take2) take(rank - take1);
+                qh = take2;
+            }
+            if (wants && need && qend && qh >= qn) {
+                done = true;
+                i = -1;
             }
         }
         if (!__any(!need)) {
