@@ -242,8 +242,21 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
     for (int s = 0; s < ns; ++s) emit_thermo(o, K, m, s, true, false);
     for (int s = 0; s < ns; ++s)
         o << "    const double c" << s << " = x[" << s << "] * (rc * " << K(1.0 / m.M[s]) << ");\n";
-    o << "#pragma unroll\n    for (int i = 0; i < KIN_N; ++i) {\n        f[i] = 0.0;\n"
-         "#pragma unroll\n        for (int j = 0; j < KIN_N; ++j) J[i][j] = 0.0;\n    }\n";
+    // f[s] and the species rows of J accumulate over the reactions; an entry's first term is
+    // assigned, not added to a zero.  The species-by-species block accumulates sum_r nu dq_r,
+    // and the mass ratios M_s / M_k are applied once after the reactions, so the reaction
+    // blocks need no per-entry constants.
+    std::vector<bool> f_set(ns, false), J_set((size_t)ns * (ns + 1), false);
+    auto accum = [&](const std::string &dst, bool &set, const std::string &coef, const std::string &v) {
+        if (!set) {
+            if (coef == "1.0") o << "        " << dst << " = " << v << ";\n";
+            else if (coef == "-1.0") o << "        " << dst << " = -" << v << ";\n";
+            else o << "        " << dst << " = " << coef << " * " << v << ";\n";
+            set = true;
+        } else {
+            o << "        " << dst << " = fma(" << coef << ", " << v << ", " << dst << ");\n";
+        }
+    };
     for (int r = 0; r < m.nr; ++r) {
         const Rxn &x = m.rx[r];
         o << "    { // reaction " << r << "\n";
@@ -305,29 +318,49 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
             if (!p.nu) continue;
             const int s = p.sp;
             const double nu = (double)p.nu;
-            o << "        f[" << s << "] = fma(" << lit(nu) << ", q, f[" << s << "]);\n";
-            o << "        J[" << s << "][KIN_NS] = fma(" << lit(nu) << ", dqT, J[" << s << "][KIN_NS]);\n";
+            {
+                bool fs = f_set[s];
+                accum("f[" + std::to_string(s) + "]", fs, lit(nu), "q");
+                f_set[s] = fs;
+            }
+            auto jref = [&](int k) { return J_set[(size_t)s * (ns + 1) + k]; };
+            {
+                bool js = jref(ns);
+                accum("J[" + std::to_string(s) + "][KIN_NS]", js, lit(nu), "dqT");
+                J_set[(size_t)s * (ns + 1) + ns] = js;
+            }
             for (int k = 0; k < x.npart; ++k) {
                 if (!has_dq[k]) continue;
                 const int sk = x.part[k].sp;
-                o << "        J[" << s << "][" << sk << "] = fma(" << K(nu * m.M[s] / m.M[sk]) << ", dq" << k
-                  << ", J[" << s << "][" << sk << "]);\n";
+                bool js = jref(sk);
+                accum("J[" + std::to_string(s) + "][" + std::to_string(sk) + "]", js, lit(nu), "dq" + std::to_string(k));
+                J_set[(size_t)s * (ns + 1) + sk] = js;
             }
             if (x.tb >= 0) {
                 for (int k = 0; k < ns; ++k) {
                     double a2 = m.eff[(size_t)x.tb * ns + k];
                     if (a2 == 0.0) continue;
-                    o << "        J[" << s << "][" << k << "] = fma(" << K(nu * m.M[s] / m.M[k] * a2) << ", D, J[" << s
-                      << "][" << k << "]);\n";
+                    bool js = jref(k);
+                    accum("J[" + std::to_string(s) + "][" + std::to_string(k) + "]", js, K(nu * a2), "D");
+                    J_set[(size_t)s * (ns + 1) + k] = js;
                 }
             }
         }
         o << "    }\n";
     }
+    for (int s = 0; s < ns; ++s) {
+        if (!f_set[s]) o << "    f[" << s << "] = 0.0;\n";
+        for (int k = 0; k <= ns; ++k)
+            if (!J_set[(size_t)s * (ns + 1) + k]) o << "    J[" << s << "][" << k << "] = 0.0;\n";
+    }
     // species rows of f, temperature column, energy row
     for (int s = 0; s < ns; ++s) {
         o << "    {\n        const double ms = " << K(m.M[s]) << " * irc;\n";
-        o << "        f[" << s << "] *= ms;\n        J[" << s << "][KIN_NS] *= ms;\n    }\n";
+        o << "        f[" << s << "] *= ms;\n        J[" << s << "][KIN_NS] *= ms;\n";
+        for (int k = 0; k < ns; ++k)
+            if (k != s && J_set[(size_t)s * (ns + 1) + k])
+                o << "        J[" << s << "][" << k << "] *= " << K(m.M[s] / m.M[k]) << ";\n";
+        o << "    }\n";
     }
     o << "    double cv = 0.0, dcv = 0.0, de = 0.0;\n";
     o << "    double ek[KIN_NS], cvk[KIN_NS];\n";
