@@ -103,8 +103,9 @@ __device__ __forceinline__ bool kin_invert_T(const double *Kp, const double (&x)
 }
 
 // In-register LU with partial pivoting (first row of largest |a_ik|), applied to the
-// right-hand side as it goes, then back substitution.  R is the factorisation type.
-// Returns false on an exactly zero pivot.
+// right-hand side as it goes, then back substitution.  R is the factorisation type; in FP32
+// the pivoting is by threshold (below).  Returns false on an exactly zero pivot, or in FP32
+// a non-finite one.
 //
 // The row exchange is done with selects, since a register file cannot be indexed by a
 // per-lane row.  It is done row by row, and only for the rows that are some lane's pivot row
@@ -127,7 +128,10 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
             amax = gt ? v : amax;
             p = gt ? i : p;
         }
-        ok = ok && (amax != R(0));
+        ok = ok && (amax != R(0)) && (sizeof(R) == 8 || __builtin_isfinite(amax));  // FP32 overflow
+        // FP32: threshold pivoting, the diagonal kept while it is at least a tenth of the
+        // column's largest candidate
+        if (sizeof(R) == 4 && fabs(A[k][k]) >= R(0.1) * amax) p = k;
         if (__any(p != k)) {
 #pragma unroll
             for (int i = k + 1; i < KIN_N; ++i) {
@@ -169,9 +173,9 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
 enum { KIN_CONTINUE = 0, KIN_ACCEPTED = 1, KIN_ATTEMPT_FAILED = 2 };
 
 // One Newton iteration on the backward-Euler system of sub-step size h started from x:
-// updates the iterate xk.  F32: the Newton matrix and right-hand side are row-equilibrated
-// in FP64 (by powers of two, so exactly), rounded to FP32, factored and solved in FP32; the correction is promoted back to
-// FP64 (residual, rates and exponentials stay FP64).  On convergence the iterate is checked
+// updates the iterate xk.  F32: the Newton matrix and right-hand side are rounded to FP32,
+// factored with threshold pivoting and solved in FP32; the correction is promoted back to FP64
+// (residual, rates and exponentials stay FP64).  On convergence the iterate is checked
 // for negative mass fractions and its temperature is reset to the root of e(Y, T) = e0.
 template <bool F32>
 __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const double rho,
@@ -212,15 +216,9 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
         float Af[KIN_N][KIN_N], bf[KIN_N];
 #pragma unroll
         for (int i = 0; i < KIN_N; ++i) {
-            // scale the row by the power of two that brings its largest entry into [0.5, 1)
-            double m = 0.0;
 #pragma unroll
-            for (int j = 0; j < KIN_N; ++j) m = fmax(m, fabs(P[i][j]));
-            int e;
-            (void)frexp(m, &e);
-#pragma unroll
-            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)ldexp(P[i][j], -e);
-            bf[i] = (float)ldexp(q[i], -e);
+            for (int j = 0; j < KIN_N; ++j) Af[i][j] = (float)P[i][j];
+            bf[i] = (float)q[i];
         }
         if (!kin_lu_solve<float>(Af, bf)) return KIN_ATTEMPT_FAILED;
 #pragma unroll
