@@ -342,15 +342,17 @@ typedef enum {
  * Sec. 4.2 (the kernel layout chosen for a mechanism). */
 kin_status kin_query(const kin_ctx *ctx, int32_t what, int64_t arg, void *out);
 
-/* Set a mechanism's layout and block size for every launch: lane 64/128/256 threads, wave 1..4
- * wavefronts, global 64 threads per block.  Drops the autotuner's per-size choices.
+/* Set a mechanism's layout and block size for every launch: lane 64/128/256 threads (a block's
+ * LDS, 512 (2 ns + 9) bytes per wavefront, must stay within 64 KiB: 256 threads up to ns = 11),
+ * wave 1..4 wavefronts, global 64 threads per block.  KIN_EINVAL otherwise.  Drops the
+ * autotuner's per-size choices.
  * Paper: Sec. 4.1, block size as a tuning parameter; Sec. 4.2, the choice between keeping the
  * Jacobian in global memory or in on-chip memory. */
 kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t block);
 
 /* Autotuner: time one advance of an existing instance with every admissible kernel layout
  * and block size of its mechanism (lane layout with 64, 128 or 256 threads per block when
- * ns <= 15; wave layout with 1, 2 or 4 wavefronts per block; the global layout above 63
+ * ns <= 15, within 64 KiB of LDS per block; wave layout with 1, 2 or 4 wavefronts per block; the global layout above 63
  * species), and keep the fastest for launches of the instance's size class and this
  * precision.  Size classes of a launch's cell count (a batched advance counts all instances
  * of a mechanism together): below 4096, 16384, 65536, 262144, and the rest.  A launch of a

@@ -14,6 +14,13 @@ namespace kin {
 constexpr int kNsMax = 255;         // species of a mechanism (the global-memory layout)
 constexpr int kWaveNsMax = 63;      // N = Ns + 1 <= 64: one matrix row per wavefront lane
 constexpr int kLaneNsMax = 15;      // lane layout holds the whole matrix in registers
+// LDS of a lane-layout block: per wavefront a queue of 64 cells ((Ns + 4) doubles and 4
+// integers each) and the 64 lanes' sub-step start states (Ns + 1 doubles each)
+inline size_t lane_lds_bytes(int ns, int block) { return (size_t)(block / 64) * 64 * 8 * (2 * (ns + 1) + 7); }
+inline bool lane_block_ok(int ns, int block)
+{
+    return ns <= kLaneNsMax && (block == 64 || block == 128 || block == 256) && lane_lds_bytes(ns, block) <= 65536;
+}
 constexpr double kRu = 8.31446261815324;          // J/(mol K)
 constexpr double kRuCgs = 8.31446261815324e7;     // erg/(mol K)
 constexpr double kPatmCgs = 1.01325e6;            // dyn/cm^2 (one standard atmosphere)

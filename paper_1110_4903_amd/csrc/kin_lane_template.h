@@ -172,14 +172,14 @@ __device__ __forceinline__ bool kin_lu_solve(R (&A)[KIN_N][KIN_N], R (&b)[KIN_N]
 // Outcome of one Newton iteration of a lane.
 enum { KIN_CONTINUE = 0, KIN_ACCEPTED = 1, KIN_ATTEMPT_FAILED = 2 };
 
-// One Newton iteration on the backward-Euler system of sub-step size h started from x:
-// updates the iterate xk.  F32: the Newton matrix and right-hand side are rounded to FP32,
+// One Newton iteration on the backward-Euler system of sub-step size h started from x
+// (component i at x[64 i], the lane's LDS row): updates the iterate xk.  F32: the Newton matrix and right-hand side are rounded to FP32,
 // factored with threshold pivoting and solved in FP32; the correction is promoted back to FP64
 // (residual, rates and exponentials stay FP64).  On convergence the iterate is checked
 // for negative mass fractions and its temperature is reset to the root of e(Y, T) = e0.
 template <bool F32>
 __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const double rho,
-                                                    const double e0, const double (&x)[KIN_N],
+                                                    const double e0, const double *x,
                                                     double (&xk)[KIN_N], const double h, double &r_prev)
 {
     double f[KIN_N];
@@ -190,7 +190,7 @@ __device__ __forceinline__ int kin_newton_iteration(const KinLaneArgs &a, const 
     double chk = 0.0;
 #pragma unroll
     for (int i = 0; i < KIN_N; ++i) {
-        b[i] = -((xk[i] - x[i]) - h * f[i]);
+        b[i] = -((xk[i] - x[64 * i]) - h * f[i]);
         chk = fma(0.0, b[i], chk);
 #pragma unroll
         for (int j = 0; j < KIN_N; ++j) {
@@ -289,6 +289,9 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
 {
     __shared__ double kin_qv[KIN_BLOCK / 64][KIN_QV][KIN_QCHUNK];
     __shared__ long long kin_qi[KIN_BLOCK / 64][KIN_QI][KIN_QCHUNK];
+    // each lane's sub-step start state x (component s at x[64 s]): kept in LDS, where it is
+    // read once per Newton iteration, instead of in registers through the whole iteration
+    __shared__ double kin_xs[KIN_BLOCK / 64][KIN_N][64];
     const int lane = (int)(threadIdx.x & 63u);
     const int wv = (int)(threadIdx.x >> 6);
     const bool adapt = a.L_forced < 0;
@@ -304,9 +307,10 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
     int qn = 0, qh = 0;  // valid slots of the wavefront's queue, next slot to hand out
     bool qend = false;   // the counter ran past the last cell
     double rho = 0.0, e0 = 0.0;
-    double x[KIN_N], xk[KIN_N];
+    double xk[KIN_N];
+    double *const x = &kin_xs[wv][0][lane];
 #pragma unroll
-    for (int s = 0; s < KIN_N; ++s) { x[s] = 0.0; xk[s] = 0.0; }
+    for (int s = 0; s < KIN_N; ++s) xk[s] = 0.0;
     unsigned long long t = 0, hsh = KIN_SCHED_SEED;
     int l = 0, k = 0, iters = 0, level = 0;
     bool failed = false;
@@ -332,12 +336,12 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
             e0 = kin_qv[wv][1][q];
             dt = kin_qv[wv][2][q];
 #pragma unroll
-            for (int s = 0; s < KIN_N; ++s) x[s] = kin_qv[wv][3 + s][q];
+            for (int s = 0; s < KIN_N; ++s) xk[s] = kin_qv[wv][3 + s][q];
             double chk = rho - rho + e0 - e0 + dt - dt;
 #pragma unroll
-            for (int s = 0; s < KIN_N; ++s) chk += x[s] - x[s];
-            if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || x[KIN_NS] < KIN_T_MIN ||
-                x[KIN_NS] > KIN_T_MAX) {
+            for (int s = 0; s < KIN_N; ++s) chk += xk[s] - xk[s];
+            if (!(chk == 0.0) || !(rho > 0.0) || !(dt >= 0.0) || xk[KIN_NS] < KIN_T_MIN ||
+                xk[KIN_NS] > KIN_T_MAX) {
                 kin_stat(base, nspan_cells, 0)[i] = 3;
                 kin_stat(base, nspan_cells, 1)[i] = 0;
                 kin_stat(base, nspan_cells, 2)[i] = 0;
@@ -345,7 +349,7 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 need = true;
             } else {
 #pragma unroll
-                for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
+                for (int s = 0; s < KIN_N; ++s) x[64 * s] = xk[s];
                 t = 0;
                 l = adapt ? 0 : a.L_forced;
                 level = l;
@@ -442,14 +446,14 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
 #endif
             if (outcome == KIN_ACCEPTED) {
 #pragma unroll
-                for (int s = 0; s < KIN_N; ++s) x[s] = xk[s];
+                for (int s = 0; s < KIN_N; ++s) x[64 * s] = xk[s];
                 t += 1ull << (Lc - l);
                 if (adapt && l > 0 && (t & ((1ull << (Lc - l + 1)) - 1ull)) == 0ull) --l;
                 k = 0;
                 if (t >= end) st = failed ? 1 : 0;
             } else if (outcome == KIN_ATTEMPT_FAILED) {
 #pragma unroll
-                for (int s = 0; s < KIN_N; ++s) xk[s] = x[s];
+                for (int s = 0; s < KIN_N; ++s) xk[s] = x[64 * s];
                 k = 0;
                 if (!adapt) {
                     st = 2;
@@ -464,8 +468,8 @@ __device__ __forceinline__ void kin_lane_run(const KinLaneArgs &a)
                 if (st != 2) {
                     double *Yout = kin_Y(base, nspan_cells);
 #pragma unroll
-                    for (int s = 0; s < KIN_NS; ++s) Yout[s * nspan_cells + i] = x[s];
-                    kin_T(base, nspan_cells)[i] = x[KIN_NS];
+                    for (int s = 0; s < KIN_NS; ++s) Yout[s * nspan_cells + i] = x[64 * s];
+                    kin_T(base, nspan_cells)[i] = x[64 * KIN_NS];
                 }
                 kin_stat(base, nspan_cells, 0)[i] = st;
                 kin_stat(base, nspan_cells, 1)[i] = level;

@@ -602,7 +602,7 @@ kin_status kin_mech_upload(kin_ctx *ctx, const kin_mech_desc *d, int32_t *mech_i
                 if (it == cache.end() || it->second.size() < 2) continue;
                 const int lay = (int)it->second[0], blk = (int)it->second[1];
                 const bool ok = (lay == KIN_LAYOUT_WAVE && blk >= 1 && blk <= 4 && m->h.ns <= kWaveNsMax) ||
-                                (lay == KIN_LAYOUT_LANE && m->h.ns <= kLaneNsMax && (blk == 64 || blk == 128 || blk == 256)) ||
+                                (lay == KIN_LAYOUT_LANE && lane_block_ok(m->h.ns, blk)) ||
                                 (lay == KIN_LAYOUT_GLOBAL && blk == 64);
                 if (ok) m->tuned[{prec, c}] = {lay, blk};
             }
@@ -653,7 +653,8 @@ kin_status kin_set_layout(kin_ctx *ctx, int32_t mech_id, int32_t layout, int32_t
     Mech &m = *it->second;
     if (layout == KIN_LAYOUT_LANE) {
         if (m.h.ns > kLaneNsMax) return err(KIN_EINVAL, "lane layout needs ns <= 15");
-        if (block != 64 && block != 128 && block != 256) return err(KIN_EINVAL, "lane block must be 64, 128 or 256");
+        if (!lane_block_ok(m.h.ns, block))
+            return err(KIN_EINVAL, "lane block must be 64, 128 or 256 threads within 64 KiB of LDS for this mechanism");
         if ((s = build_lane(ctx, m, block)) != KIN_OK) return s;
     } else if (layout == KIN_LAYOUT_WAVE) {
         if (m.h.ns > kWaveNsMax) return err(KIN_EINVAL, "wave layout needs ns <= 63");
@@ -1485,7 +1486,8 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
     if (in.mech != mech_id) return err(KIN_EINVAL, "instance belongs to another mechanism");
     std::vector<std::pair<int, int>> cand;
     if (m.h.ns <= kLaneNsMax)
-        for (int b : {64, 128, 256}) cand.push_back({KIN_LAYOUT_LANE, b});
+        for (int b : {64, 128, 256})
+            if (lane_block_ok(m.h.ns, b)) cand.push_back({KIN_LAYOUT_LANE, b});
     if (m.h.ns <= kWaveNsMax) {
         for (int b : {1, 2, 4})
             if (wave_lds_bytes(m.tab, false) * (size_t)b <= 65536) cand.push_back({KIN_LAYOUT_WAVE, b});

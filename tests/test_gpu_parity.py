@@ -532,6 +532,30 @@ def test_wave_layout_other_row_lengths(ctx, orc, ns, nr, ne):
     ctx.mech_release(mid)
 
 
+@pytest.mark.parametrize("ns,nr,ne,block", [(15, 40, 3, 128), (11, 30, 3, 256)])
+def test_lane_layout_largest_systems(ctx, orc, ns, nr, ne, block):
+    """The lane layout at its largest systems: 15 species (a 16 x 16 Newton matrix in registers)
+    at 128 threads per block, and 11 species at 256 threads, the largest block whose queue and
+    start states fit 64 KiB of LDS; 300 cells, FP64 and FP32-LU, every cell against the oracle.
+    256 threads for 15 species is refused (EINVAL)."""
+    from paper_1110_4903_amd import kin
+    m = synth.make_mechanism(synth.MechRecipe(f"gen{ns}", seed=300 + ns, n_elements=ne, n_species=ns,
+                                              n_reactions=nr, frac_third_body=0.15,
+                                              frac_irreversible=0.3))
+    st = synth.uniform_cells(400 + ns, 300, ns, 0.5)
+    mid = ctx.mech_upload(m)
+    if ns == 15:
+        with pytest.raises(kin.KinError) as e:
+            ctx.set_layout(mid, kin.LAYOUT_LANE, 256)
+        assert e.value.status == kin.EINVAL
+    ctx.set_layout(mid, kin.LAYOUT_LANE, block)
+    for prec, rtol, bound in ((kin.FP64, 1e-10, 3), (kin.FP32_LU, 1e-6, 0.1)):
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, prec, rtol, mech_id=mid, max_mismatch=bound)
+        report(f"lane gen{ns} block {block} prec {prec}", s)
+        assert s["checked"] == st.n
+    ctx.mech_release(mid)
+
+
 def both_sides_mech():
     """H, H2, O, OH, H2O, O2: a third-order reaction with H on both sides (3 H => H2 + H), a
     product with nu = 2, an irreversible reaction and a third-body reaction."""
