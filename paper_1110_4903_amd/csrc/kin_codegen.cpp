@@ -161,10 +161,11 @@ static std::string horner(const std::vector<std::string> &c, const std::vector<b
     return e;
 }
 
-// NASA-7 species functions of species s at (T, iT, lT) into cp{s}, h{s} (h/RT), s{s} (s/R),
-// dc{s} (d(cp/R)/dT).  With two different coefficient sets the set is selected by T < T_mid.
+// NASA-7 species functions of species s at (T, iT, lT) into cp{s}, h{s} (h/RT, unless need_h
+// is false and an earlier h{s} at the same T is in scope), s{s} (s/R), dc{s} (d(cp/R)/dT).
+// With two different coefficient sets the set is selected by T < T_mid.
 static void emit_thermo(std::ostringstream &o, Consts &K, const MechHost &m, int s, bool need_s,
-                        bool need_dc)
+                        bool need_dc, bool need_h = true)
 {
     const double *lo = &m.nasa[14 * s], *hi = &m.nasa[14 * s + 7];
     const bool one = m.single_range(s);
@@ -179,7 +180,7 @@ static void emit_thermo(std::ostringstream &o, Consts &K, const MechHost &m, int
         for (int k = 0; k < 5; ++k) { c.push_back(coef(lo[k], hi[k])); z.push_back(is_zero(k)); }
         o << "    const double cp" << s << " = " << horner(c, z) << ";\n";
     }
-    {
+    if (need_h) {
         std::vector<std::string> c; std::vector<bool> z;
         for (int k = 0; k < 5; ++k) { c.push_back(coef(lo[k] / (k + 1), hi[k] / (k + 1))); z.push_back(is_zero(k)); }
         o << "    const double h" << s << " = fma(" << coef(lo[5], hi[5]) << ", iT, " << horner(c, z) << ");\n";
@@ -227,6 +228,31 @@ static std::string mass_action_grad(const std::string &k, const int *sp, const i
     return e;
 }
 
+// e^x of the rate expressions (finite arguments: T is confined to [200, 6000] K).  Cody and
+// Waite's reduction x = k ln2 + r, k = rint(x / ln2), |r| <= ln2 / 2, with ln2 split in a high
+// part of 32 significant bits (k * hi exact for |k| < 2^21) and the rest; e^r by its Taylor
+// polynomial to degree 12 (truncation below 2.3e-16 relative), then 2^k by ldexp, which gives
+// infinity or zero beyond the double range.  About two ulp, in 18 instructions.
+static const char *kLaneExp =
+    "__device__ __forceinline__ double kin_exp(double x)\n{\n"
+    "    const double k = rint(x * 1.4426950408889634);\n"
+    "    double r = fma(-k, 0x1.62e42fee00000p-1, x);\n"
+    "    r = fma(-k, 0x1.a39ef35793c76p-33, r);\n"
+    "    double p = 1.0 / 479001600.0;\n"
+    "    p = fma(p, r, 1.0 / 39916800.0);\n"
+    "    p = fma(p, r, 1.0 / 3628800.0);\n"
+    "    p = fma(p, r, 1.0 / 362880.0);\n"
+    "    p = fma(p, r, 1.0 / 40320.0);\n"
+    "    p = fma(p, r, 1.0 / 5040.0);\n"
+    "    p = fma(p, r, 1.0 / 720.0);\n"
+    "    p = fma(p, r, 1.0 / 120.0);\n"
+    "    p = fma(p, r, 1.0 / 24.0);\n"
+    "    p = fma(p, r, 1.0 / 6.0);\n"
+    "    p = fma(p, r, 0.5);\n"
+    "    p = fma(p, r, 1.0);\n"
+    "    p = fma(p, r, 1.0);\n"
+    "    return ldexp(p, (int)k);\n}\n\n";
+
 std::string lane_source(const MechHost &m, int block, std::vector<double> &consts)
 {
     const int ns = m.ns;
@@ -265,7 +291,7 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
         if (x.b != 0.0) lk = "fma(" + K(x.b) + ", lT, " + lk + ")";
         if (x.Ta != 0.0) lk = "fma(" + K(-x.Ta) + ", iT, " + lk + ")";
         o << "        const double lkf = " << lk << ";\n";
-        o << "        const double kf = exp(lkf);\n";
+        o << "        const double kf = kin_exp(lkf);\n";
         o << "        const double dlkf = " << ((x.b != 0.0 || x.Ta != 0.0) ? "fma(" + K(x.Ta) + ", iT, " + K(x.b) + ") * iT" : std::string("0.0")) << ";\n";
         o << "        const double pf = " << mass_action("kf", x.reac_sp, x.reac_nu, x.nreac) << ";\n";
         if (x.rev) {
@@ -276,7 +302,7 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
                 sh = "fma(" + lit((double)x.part[k].nu) + ", h" + std::to_string(x.part[k].sp) + ", " + sh + ")";
             }
             o << "        const double lKc = " << lit((double)x.dnu) << " * lPaRT - " << sg << ";\n";
-            o << "        const double kb = exp(lkf - lKc);\n";
+            o << "        const double kb = kin_exp(lkf - lKc);\n";
             o << "        const double dlKc = (" << lit((double)-x.dnu) << " + " << sh << ") * iT;\n";
             o << "        const double pb = " << mass_action("kb", x.prod_sp, x.prod_nu, x.nprod) << ";\n";
             o << "        const double D = pf - pb;\n";
@@ -366,7 +392,7 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
     o << "    double ek[KIN_NS], cvk[KIN_NS];\n";
     for (int s = 0; s < ns; ++s) {
         o << "    {\n";
-        emit_thermo(o, K, m, s, false, true);
+        emit_thermo(o, K, m, s, false, true, false);   // h_s from the first pass
         const double rm = kRu * 1e3 / m.M[s];
         o << "    ek[" << s << "] = " << K(rm) << " * T * (h" << s << " - 1.0);\n";
         o << "    cvk[" << s << "] = " << K(rm) << " * (cp" << s << " - 1.0);\n";
@@ -407,6 +433,7 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
             "// scalar loads of each reaction's constants next to that reaction.\n"
             "__device__ __forceinline__ kin_cptr kin_fence_k(kin_cptr p)\n{\n"
             "    asm volatile(\"\" : \"+s\"(p));\n    return p;\n}\n\n";
+    head << kLaneExp;
     consts = K.tab;
     // the launch passes the host's AdvanceArgs by value as the kernel's KinLaneArgs
     std::ostringstream tail;
