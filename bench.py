@@ -457,33 +457,38 @@ def run_batch(torch, kin, synth, args, stream):
 
 def run_serving(torch, kin, serve, synth, args):
     """Calibrate the saturated rate with every request present at t = 0, then serve Poisson
-    arrivals at fractions of it.  The 36-species requests run on streams confined to all but
-    32 compute units (reserve_cu), which keeps the 9-species requests from queueing behind
-    them; one run without the reservation is kept for comparison."""
+    arrivals at fractions of it.  The 36-species requests run on two streams confined to all
+    but 32 compute units (reserve_cu), the 9-species requests on two other streams, which keeps
+    the 9-species requests from queueing behind them, for compute units or in a hardware queue.
+    Kept for comparison: one stream per slot, no reservation, and requests above 65536 cells
+    served as parts of at most that size (serve.split)."""
     n_req = 20 if args.quick else args.serve_requests
     budget = 256 << 20
     out = {}
-    plan = (("fp32lu", kin.FP32_LU, 32, (0.5, 0.8, 0.95)), ("fp64", kin.FP64, 32, (0.8,)),
-            ("fp32lu_no_reserve", kin.FP32_LU, 0, (0.8,)))
+    # (name, precision, reserved CUs, split size, streams per class, loads)
+    plan = (("fp32lu", kin.FP32_LU, 32, None, 2, (0.5, 0.8, 0.95)), ("fp64", kin.FP64, 32, None, 2, (0.8,)),
+            ("fp32lu_stream_per_slot", kin.FP32_LU, 32, None, None, (0.8,)),
+            ("fp32lu_no_reserve", kin.FP32_LU, 0, None, 2, (0.8,)),
+            ("fp32lu_split_65536", kin.FP32_LU, 32, 65536, 2, (0.8,)))
     with kin.Context(0, hbm_budget=budget) as ctx:
         mids = {name: ctx.mech_upload(synth.mechanism(name)) for name in ("mech9", "mech36")}
-        for name, prec, reserve, loads in plan:
-            be = serve.KinBackend(ctx, mids, prec, n_slots=16, reserve_cu=reserve)
+        for name, prec, reserve, chunk, nstreams, loads in plan:
+            be = serve.KinBackend(ctx, mids, prec, n_slots=16, reserve_cu=reserve, n_streams=nstreams)
             reqs = synth.serving_requests(4, n_req, rate_per_s=1.0)
             jobs = serve.make_jobs(reqs, time_scale=0.0)
             for j, r in zip(jobs, reqs):
-                be.prepare(j, r.inst.states())
+                be.prepare(j, r.inst.states(), max_chunk=chunk)
             log(f"serving {name}: saturation run, {n_req} requests")
-            sat = serve.run(jobs, be, budget, 16).summary()
+            sat = serve.run(jobs, be, budget, 16, max_chunk=chunk).summary()
             rate = sat["cells_per_s"] / synth.mean_request_cells()
-            runs = {"reserve_cu": reserve, "saturated": sat}
+            runs = {"reserve_cu": reserve, "max_chunk": chunk, "streams_per_class": nstreams or 16, "saturated": sat}
             for load in loads:
                 reqs = synth.serving_requests(4, n_req, rate_per_s=load * rate)
                 jobs = serve.make_jobs(reqs)
                 for j, r in zip(jobs, reqs):
-                    be.prepare(j, r.inst.states())
+                    be.prepare(j, r.inst.states(), max_chunk=chunk)
                 log(f"serving {name}: load {load}")
-                runs[f"load_{load}"] = serve.run(jobs, be, budget, 16).summary()
+                runs[f"load_{load}"] = serve.run(jobs, be, budget, 16, max_chunk=chunk).summary()
             be.close()
             out[name] = runs
     return out
@@ -662,7 +667,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=80)
+    ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--quick", action="store_true", help="small sizes, for smoke runs")
     ap.add_argument("--only", default="all", choices=("all", "headline", "mech36", "adapter", "global", "fluid", "batch", "serve", "copy"),
                     help="run one part (for profiler runs); the JSON line needs the headline")

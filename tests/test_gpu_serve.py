@@ -23,26 +23,34 @@ def _jobs(seed, n):
     return reqs, serve.make_jobs(reqs)
 
 
-@pytest.mark.parametrize("prec,reserve", [(0, 0), (1, 0), (1, 32)])
-def test_alone_equals_mix(prec, reserve):
+@pytest.mark.parametrize("prec,reserve,chunk,nstreams", [(0, 0, None, None), (1, 0, None, None), (1, 32, None, 2),
+                                                        (0, 32, 700, 2)])
+def test_alone_equals_mix(prec, reserve, chunk, nstreams):
+    """chunk: requests above that many cells are served as parts (joined afterwards); nstreams:
+    streams per request class shared by the slots (None: one per slot)."""
     budget = 8 << 20
     ctx, mids = _setup(budget)
     try:
         reqs, jobs = _jobs(40 + prec, 24)
-        be = serve.KinBackend(ctx, mids, prec, n_slots=6, reserve_cu=reserve)
+        be = serve.KinBackend(ctx, mids, prec, n_slots=6, reserve_cu=reserve, n_streams=nstreams)
         for j, r in zip(jobs, reqs):
-            be.prepare(j, r.inst.states())
-        rep = serve.run(jobs, be, budget, 6)
+            be.prepare(j, r.inst.states(), max_chunk=chunk)
+        rep = serve.run(jobs, be, budget, 6, max_chunk=chunk)
         s = rep.summary()
-        print(f"\n[serve mix prec={prec} reserve={reserve}] " + " ".join(f"{k}={v}" for k, v in s.items()), flush=True)
+        print(f"\n[serve mix prec={prec} reserve={reserve} chunk={chunk} streams={nstreams}] " + " ".join(f"{k}={v}" for k, v in s.items()),
+              flush=True)
         assert s["rejected"] == 0 and s["requests"] == len(jobs)
         assert rep.max_bytes_in_use <= budget and ctx.bytes_in_use() == 0
         assert ctx.largest_free() == budget
         assert rep.max_in_flight > 1, "no two requests overlapped"
+        if chunk:
+            assert any(j.n_cells > chunk for j in jobs)
         mixed = {r.rid: tuple(np.copy(a) for a in r.result) for r in rep.records}
-        # each request alone, in a fresh loop with one slot and no other traffic
-        for j in jobs:
+        # each request alone and unsplit, in a fresh loop with one slot and no other traffic
+        for j, r in zip(jobs, reqs):
             j.arrival = 0.0
+            if chunk:
+                be.prepare(j, r.inst.states())
             rep1 = serve.run([j], be, budget, 1)
             alone = rep1.records[0].result
             for a, b in zip(alone, mixed[j.rid]):

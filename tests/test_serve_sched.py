@@ -119,3 +119,78 @@ def test_percentile_nearest_rank():
     x = list(range(1, 101))
     assert serve.percentile(x, 50) == 50 and serve.percentile(x, 99) == 99 and serve.percentile(x, 100) == 100
     assert serve.percentile([3.0], 99) == 3.0
+
+
+class PartBackend(SimBackend):
+    """SimBackend whose results name the cells each part covered; join() checks their order."""
+
+    def finish(self, slot):
+        part, fp, _ = self.running.pop(slot)
+        self.used -= fp
+        return (part.rid, part.index, part.offset, part.n_cells)
+
+    def join(self, job, results):
+        assert [r[1] for r in results] == list(range(len(results)))
+        assert results[0][2] == 0 and sum(r[3] for r in results) == job.n_cells
+        assert all(a[2] + a[3] == b[2] for a, b in zip(results, results[1:]))
+        return job.rid
+
+
+@pytest.mark.parametrize("n,chunk", [(1, 4), (10, 4), (12, 4), (100000, 65536), (7, None), (7, 7)])
+def test_split_covers_the_cells(n, chunk):
+    job = serve.Job(0, 0.0, "mech9", n, 1e-6)
+    parts = serve.split(job, chunk)
+    assert parts[0].offset == 0 and sum(p.n_cells for p in parts) == n
+    assert all(a.offset + a.n_cells == b.offset for a, b in zip(parts, parts[1:]))
+    assert [p.index for p in parts] == list(range(len(parts)))
+    if chunk:
+        sizes = [p.n_cells for p in parts]
+        assert max(sizes) <= chunk and max(sizes) - min(sizes) <= 1
+        assert len(parts) == -(-n // chunk)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_split_requests_budget_order_and_joining(seed):
+    """Requests above 20k cells go as parts: budget and slots hold, requests start in arrival
+    order with their parts in order, every request is joined from all its parts in cell order."""
+    jobs = _jobs(seed, 200, 40.0)
+    budget = 30_000_000
+    clk = SimClock()
+    be = PartBackend(clk, 1.0e6, BPC, budget)
+    rep = serve.run(jobs, be, budget, 8, clk, max_chunk=20000)
+    assert len(rep.records) == len(jobs)
+    # a split request's result comes from join(); an unsplit one's is its single part's
+    assert all(r.result == (r.rid if r.n_cells > 20000 else (r.rid, 0, 0, r.n_cells)) for r in rep.records)
+    assert rep.max_bytes_in_use <= budget and be.peak <= budget and rep.max_in_flight <= 8
+    assert rep.start_order == sorted(rep.start_order)
+    assert all(r.done >= r.admitted >= r.arrival for r in rep.records)
+    assert be.used == 0 and not be.running
+    assert any(j.n_cells > 20000 for j in jobs)
+
+
+def test_split_single_slot_keeps_latencies():
+    """With one slot the parts of a request run back to back, so splitting changes no latency
+    (service times add up): the records equal those of the unsplit run."""
+    rng = np.random.default_rng(3)
+    arr = np.cumsum(rng.exponential(1.0, 40))
+    n = rng.integers(100, 5000, 40)
+    mk = lambda: [serve.Job(k, float(a), "mech9", int(c), 1e-6) for k, (a, c) in enumerate(zip(arr, n))]
+    out = []
+    for chunk in (None, 700):
+        clk = SimClock()
+        rep = serve.run(mk(), PartBackend(clk, 1000.0, BPC, 10**9), 10**9, 1, clk, max_chunk=chunk)
+        out.append(sorted((r.rid, r.admitted, r.done) for r in rep.records))
+    for (r0, a0, d0), (r1, a1, d1) in zip(*out):
+        assert r0 == r1 and a0 == pytest.approx(a1, abs=1e-9) and d0 == pytest.approx(d1, abs=1e-9)
+
+
+def test_split_request_runs_its_parts_side_by_side():
+    """A lone request of 4 parts on 4 free slots: the parts start together and the request is
+    done after a quarter of its unsplit service time; wait and size statistics are reported."""
+    clk = SimClock()
+    rep = serve.run([serve.Job(0, 0.0, "mech9", 4000, 1e-6)], PartBackend(clk, 1000.0, BPC, 10**9), 10**9, 4,
+                    clk, max_chunk=1000)
+    r = rep.records[0]
+    assert r.done == pytest.approx(1.0) and r.wait == 0.0 and rep.max_in_flight == 4
+    s = rep.summary()
+    assert s["wait_p99_ms"] == 0.0 and s["cells_lt16k_n"] == 1 and s["cells_lt16k_p99_ms"] == pytest.approx(1e3)
