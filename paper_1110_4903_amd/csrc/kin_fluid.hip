@@ -21,12 +21,14 @@
 #include <hip/hip_runtime.h>
 
 #include "kin_internal.h"
+#include "kin_xlane.h"
 
 namespace kin {
 namespace {
 
 constexpr double kRuJ = 8.31446261815324e3;   // J/(kmol K): R / M with M in g/mol gives J/(kg K)
 constexpr double kAlphaMP = 2.0;
+constexpr int kFluidNsRegs = 16;   // species counts whose face states the flux kernel keeps in registers
 
 __device__ __forceinline__ double minmod(double a, double b)
 {
@@ -43,14 +45,20 @@ __device__ __forceinline__ double mp5(double um2, double um1, double u0, double 
     return uL + minmod(u0 - uL, ump - uL);
 }
 
-// Sensible energy e_s(T) - e_s(T_ref) (J/kg) and c_v,s (J/(kg K)) of species s.
+// Sensible energy e_s(T) - e_s(T_ref) (J/kg) and c_v,s (J/(kg K)) of species s.  The species
+// index is uniform across the wavefront, so both coefficient ranges come through scalar loads
+// and each lane selects its range.
 __device__ __forceinline__ void species_e_cv(const WaveTables &t, int s, double T, double &e, double &cv)
 {
-    const double *a = t.nasa + 14 * s + (T < t.Tmid[s] ? 0 : 7);
-    const double Rs = kRuJ / t.M[s];
+    const auto *nasa = uniform_table(t.nasa) + 14 * s;
+    const bool lo = T < uniform_table(t.Tmid)[s];
+    double a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = lo ? nasa[k] : nasa[7 + k];
+    const double Rs = kRuJ / uniform_table(t.M)[s];
     const double cpR = fma(T, fma(T, fma(T, fma(T, a[4], a[3]), a[2]), a[1]), a[0]);
     const double hR = fma(T, fma(T, fma(T, fma(T, fma(T, a[4] * 0.2, a[3] * 0.25), a[2] * (1.0 / 3.0)), a[1] * 0.5), a[0]), a[5]);
-    e = Rs * (hR - T) - t.ef[s];
+    e = Rs * (hR - T) - uniform_table(t.ef)[s];
     cv = Rs * (cpR - 1.0);
 }
 
@@ -59,32 +67,47 @@ struct Grid {
     long long n;          // nx * ny
 };
 
+// NSR > 0: the cell's partial densities stay in registers through the Newton iterations
+// (mechanisms of at most NSR species); NSR = 0 reads them again in each iteration.
+template <int NSR>
 __global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double *W, double *Tc)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int ns = g.ns;
     const long long n = g.n;
+    double rs[NSR > 0 ? NSR : 1];
+    auto each_species = [&](auto body) {
+        if constexpr (NSR > 0) {
+#pragma unroll
+            for (int s = 0; s < NSR; ++s)
+                if (s < ns) body(s);
+        } else {
+            for (int s = 0; s < ns; ++s) body(s);
+        }
+    };
+    auto rho_s = [&](int s) { return NSR > 0 ? rs[s] : Q[(size_t)s * n + i]; };
     double rho = 0.0, rR = 0.0;
-    for (int s = 0; s < ns; ++s) {
+    each_species([&](int s) {
         const double r = Q[(size_t)s * n + i];
+        if constexpr (NSR > 0) rs[s] = r;
         rho += r;
-        rR = fma(r, kRuJ / t.M[s], rR);
+        rR = fma(r, kRuJ / uniform_table(t.M)[s], rR);
         W[(size_t)s * n + i] = r;
-    }
+    });
     const double u = Q[(size_t)ns * n + i] / rho, v = Q[(size_t)(ns + 1) * n + i] / rho;
     const double eint = Q[(size_t)(ns + 2) * n + i] - 0.5 * rho * (u * u + v * v);
     double T = Tc[i];
     if (!(T >= 100.0 && T <= 1e4)) T = 1000.0;
     for (int it = 0; it < 60; ++it) {
         double f = -eint, d = 0.0;
-        for (int s = 0; s < ns; ++s) {
+        each_species([&](int s) {
             double e, cv;
             species_e_cv(t, s, T, e, cv);
-            const double r = Q[(size_t)s * n + i];
+            const double r = rho_s(s);
             f = fma(r, e, f);
             d = fma(r, cv, d);
-        }
+        });
         const double dT = f / d;
         T -= dT;
         if (!(fabs(dT) > 1e-13 * fabs(T))) break;   // converged, or not a number
@@ -104,7 +127,9 @@ __device__ __forceinline__ int wrap(int k, int len, int bc)
 
 // Face fluxes of a sweep along x (DIR 0) or y (DIR 1).  Face a along the sweep lies between
 // cells a - 1 and a; faces are stored [var][ny][nx + 1] (x) or [var][ny + 1][nx] (y).
-template <int DIR>
+// NSR > 0: mechanisms of at most NSR species keep each species' two reconstructed states in
+// registers (one reconstruction per species); NSR = 0 streams them (three per species).
+template <int DIR, int NSR>
 __global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double *F)
 {
     const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,30 +159,55 @@ __global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double 
     recon(Wun, unL, unR);
     recon(Wut, utL, utR);
     recon(W + (size_t)(ns + 2) * n, PL, PR);
+    // species states: reconstructed once into registers (NSR), or again in each pass below
+    double Ls[NSR > 0 ? NSR : 1], Rsv[NSR > 0 ? NSR : 1];
+    if (NSR > 0) {
+#pragma unroll
+        for (int s = 0; s < (NSR > 0 ? NSR : 1); ++s)
+            if (s < ns) recon(W + (size_t)s * n, Ls[s], Rsv[s]);
+    }
+    auto state = [&](int s, double &L, double &R) {
+        if (NSR > 0) {
+            L = Ls[s];
+            R = Rsv[s];
+        } else {
+            recon(W + (size_t)s * n, L, R);
+        }
+    };
+    // body(s) for every species: unrolled over the register arrays, or a plain loop
+    auto each_species = [&](auto body) {
+        if constexpr (NSR > 0) {
+#pragma unroll
+            for (int s = 0; s < NSR; ++s)
+                if (s < ns) body(s);
+        } else {
+            for (int s = 0; s < ns; ++s) body(s);
+        }
+    };
     // pass 1: densities and gas constants of the two states
     double rL = 0.0, rR = 0.0, RL = 0.0, RR = 0.0;
-    for (int s = 0; s < ns; ++s) {
+    each_species([&](int s) {
         double L, R;
-        recon(W + (size_t)s * n, L, R);
-        const double Rs = kRuJ / t.M[s];
+        state(s, L, R);
+        const double Rs = kRuJ / uniform_table(t.M)[s];
         rL += L;
         rR += R;
         RL = fma(L, Rs, RL);
         RR = fma(R, Rs, RR);
-    }
+    });
     const double TL = PL / RL, TR = PR / RR;
     // pass 2: energies and heat capacities at the two temperatures
     double eL = 0.0, eR = 0.0, cvL = 0.0, cvR = 0.0;
-    for (int s = 0; s < ns; ++s) {
+    each_species([&](int s) {
         double L, R, e, cv;
-        recon(W + (size_t)s * n, L, R);
+        state(s, L, R);
         species_e_cv(t, s, TL, e, cv);
         eL = fma(L, e, eL);
         cvL = fma(L, cv, cvL);
         species_e_cv(t, s, TR, e, cv);
         eR = fma(R, e, eR);
         cvR = fma(R, cv, cvR);
-    }
+    });
     const double EL = eL + 0.5 * rL * (unL * unL + utL * utL);
     const double ER = eR + 0.5 * rR * (unR * unR + utR * utR);
     const double cL = sqrt((cvL + RL) / cvL * PL / rL), cR = sqrt((cvR + RR) / cvR * PR / rR);
@@ -173,11 +223,11 @@ __global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double 
     const long long fo = DIR == 0 ? (long long)fy * (g.nx + 1) + fx : (long long)fy * g.nx + fx;
     const long long fn = (long long)fw * fh;
     // pass 3: species fluxes
-    for (int s = 0; s < ns; ++s) {
+    each_species([&](int s) {
         double L, R;
-        recon(W + (size_t)s * n, L, R);
+        state(s, L, R);
         F[(size_t)s * fn + fo] = hlle(L * unL, R * unR, L, R);
-    }
+    });
     F[(size_t)(DIR == 0 ? ns : ns + 1) * fn + fo] =
         hlle(rL * unL * unL + PL, rR * unR * unR + PR, rL * unL, rR * unR);
     F[(size_t)(DIR == 0 ? ns + 1 : ns) * fn + fo] = hlle(rL * unL * utL, rR * unR * utR, rL * utL, rR * utR);
@@ -271,12 +321,16 @@ hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &fg, int dir,
     for (int k = 0; k < 3; ++k) {
         const double *in = k == 0 ? Q : Q1;
         double *out = k == 2 ? Q : Q1;
-        hipLaunchKernelGGL(fluid_prim_kernel, dim3(gc), dim3(block), 0, s, t, g, in, W, T);
+        const bool regs = g.ns <= kFluidNsRegs;
+        if (regs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, in, W, T);
+        else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, in, W, T);
         if (dir == 0) {
-            hipLaunchKernelGGL(fluid_flux_kernel<0>, dim3(gf), dim3(block), 0, s, t, g, W, F);
+            if (regs) hipLaunchKernelGGL((fluid_flux_kernel<0, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, W, F);
+            else hipLaunchKernelGGL((fluid_flux_kernel<0, 0>), dim3(gf), dim3(block), 0, s, t, g, W, F);
             hipLaunchKernelGGL(fluid_update_kernel<0>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
         } else {
-            hipLaunchKernelGGL(fluid_flux_kernel<1>, dim3(gf), dim3(block), 0, s, t, g, W, F);
+            if (regs) hipLaunchKernelGGL((fluid_flux_kernel<1, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, W, F);
+            else hipLaunchKernelGGL((fluid_flux_kernel<1, 0>), dim3(gf), dim3(block), 0, s, t, g, W, F);
             hipLaunchKernelGGL(fluid_update_kernel<1>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
         }
     }
@@ -289,7 +343,8 @@ hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &fg, const do
     const Grid g{t.ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
     const int block = 256;
     const unsigned gc = (unsigned)((g.n + block - 1) / block);
-    hipLaunchKernelGGL(fluid_prim_kernel, dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    if (g.ns <= kFluidNsRegs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
     hipLaunchKernelGGL(fluid_speed_kernel, dim3(gc), dim3(block), 0, s, t, g, W, T, dx, dy, out);
     return hipGetLastError();
 }
