@@ -20,6 +20,8 @@
 // Species are streamed (three passes per face), so no per-species array lives in registers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kin_internal.h"
 #include "kin_xlane.h"
 
@@ -67,13 +69,16 @@ struct Grid {
     long long n;          // nx * ny
 };
 
-// NSR > 0: the cell's partial densities stay in registers through the Newton iterations
-// (mechanisms of at most NSR species); NSR = 0 reads them again in each iteration.
-template <int NSR>
-__global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double *W, double *Tc)
+// Primitive variables of cell i from its conserved state q (ns partial densities, two momenta,
+// E; q(v) returns variable v): u, v, P = rho R T into W's last three rows and T into Tc, by
+// Newton on the sensible energy from the cell's previous T.  The partial densities are W's
+// species rows by definition, so the face kernel reads them from the state itself.
+// NSR > 0: the partial densities stay in registers through the Newton iterations (mechanisms
+// of at most NSR species); NSR = 0 reads them through q again in each iteration.
+template <int NSR, typename QV>
+__device__ __forceinline__ void cell_primitives(const WaveTables &t, const Grid &g, long long i, QV q, double *W,
+                                                double *Tc)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
     const int ns = g.ns;
     const long long n = g.n;
     double rs[NSR > 0 ? NSR : 1];
@@ -86,17 +91,16 @@ __global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double 
             for (int s = 0; s < ns; ++s) body(s);
         }
     };
-    auto rho_s = [&](int s) { return NSR > 0 ? rs[s] : Q[(size_t)s * n + i]; };
+    auto rho_s = [&](int s) { return NSR > 0 ? rs[s] : q(s); };
     double rho = 0.0, rR = 0.0;
     each_species([&](int s) {
-        const double r = Q[(size_t)s * n + i];
+        const double r = q(s);
         if constexpr (NSR > 0) rs[s] = r;
         rho += r;
         rR = fma(r, kRuJ / uniform_table(t.M)[s], rR);
-        W[(size_t)s * n + i] = r;
     });
-    const double u = Q[(size_t)ns * n + i] / rho, v = Q[(size_t)(ns + 1) * n + i] / rho;
-    const double eint = Q[(size_t)(ns + 2) * n + i] - 0.5 * rho * (u * u + v * v);
+    const double u = q(ns) / rho, v = q(ns + 1) / rho;
+    const double eint = q(ns + 2) - 0.5 * rho * (u * u + v * v);
     double T = Tc[i];
     if (!(T >= 100.0 && T <= 1e4)) T = 1000.0;
     for (int it = 0; it < 60; ++it) {
@@ -118,6 +122,15 @@ __global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double 
     W[(size_t)(ns + 2) * n + i] = rR * T;
 }
 
+template <int NSR>
+__global__ void fluid_prim_kernel(WaveTables t, Grid g, const double *Q, double *W, double *Tc)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const long long n = g.n;
+    cell_primitives<NSR>(t, g, i, [&](int v) { return Q[(size_t)v * n + i]; }, W, Tc);
+}
+
 // Cell index along the sweep direction k (0..len-1 after the boundary rule) of an offset one.
 __device__ __forceinline__ int wrap(int k, int len, int bc)
 {
@@ -130,7 +143,7 @@ __device__ __forceinline__ int wrap(int k, int len, int bc)
 // NSR > 0: mechanisms of at most NSR species keep each species' two reconstructed states in
 // registers (one reconstruction per species); NSR = 0 streams them (three per species).
 template <int DIR, int NSR>
-__global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double *F)
+__global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *Qs, const double *W, double *F)
 {
     const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int fw = DIR == 0 ? g.nx + 1 : g.nx;      // faces per row of the face array
@@ -164,14 +177,14 @@ __global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *W, double 
     if (NSR > 0) {
 #pragma unroll
         for (int s = 0; s < (NSR > 0 ? NSR : 1); ++s)
-            if (s < ns) recon(W + (size_t)s * n, Ls[s], Rsv[s]);
+            if (s < ns) recon(Qs + (size_t)s * n, Ls[s], Rsv[s]);
     }
     auto state = [&](int s, double &L, double &R) {
         if (NSR > 0) {
             L = Ls[s];
             R = Rsv[s];
         } else {
-            recon(W + (size_t)s * n, L, R);
+            recon(Qs + (size_t)s * n, L, R);
         }
     };
     // body(s) for every species: unrolled over the register arrays, or a plain loop
@@ -254,10 +267,49 @@ __global__ void fluid_update_kernel(Grid g, const double *Q0, const double *Q, d
     }
 }
 
+// The update of fluid_update_kernel, then the primitives of the new state for the next stage
+// (the new state stays in registers, so it is not read back).
+template <int DIR, int NSR>
+__global__ void fluid_update_prim_kernel(WaveTables t, Grid g, const double *Q0, const double *Q, double *Qout,
+                                         const double *F, double dt, double h, double a0, double a1, double *W,
+                                         double *Tc)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int x = (int)(i % g.nx), y = (int)(i / g.nx);
+    const int nv = g.ns + 3;
+    const long long fn = DIR == 0 ? (long long)(g.nx + 1) * g.ny : (long long)g.nx * (g.ny + 1);
+    const long long fl = DIR == 0 ? (long long)y * (g.nx + 1) + x : i;
+    const long long fr = DIR == 0 ? fl + 1 : fl + g.nx;
+    constexpr int NV = NSR > 0 ? NSR + 3 : 1;
+    double qn[NV];
+    auto upd = [&](int v) {
+        const double L = -(F[(size_t)v * fn + fr] - F[(size_t)v * fn + fl]) / h;
+        const double q = Q[(size_t)v * g.n + i] + dt * L;
+        const double o = a0 != 0.0 ? a0 * Q0[(size_t)v * g.n + i] + a1 * q : a1 * q;
+        Qout[(size_t)v * g.n + i] = o;
+        return o;
+    };
+    if constexpr (NSR > 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            // species k < ns, then the momenta and the energy in slots NSR .. NSR + 2
+            const int v = k < NSR ? k : g.ns + (k - NSR);
+            if (k < NSR && k >= g.ns) continue;
+            qn[k] = upd(v);
+        }
+        cell_primitives<NSR>(t, g, i, [&](int v) { return v < g.ns ? qn[v] : qn[NSR + (v - g.ns)]; }, W, Tc);
+    } else {
+        for (int v = 0; v < nv; ++v) upd(v);
+        const long long n = g.n;
+        cell_primitives<0>(t, g, i, [&](int v) { return Qout[(size_t)v * n + i]; }, W, Tc);
+    }
+}
+
 // Largest (|u| + c) / dx and (|v| + c) / dy over the grid (positive doubles order like their
 // bit patterns, so an unsigned 64-bit atomic maximum finds it).
-__global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *W, const double *Tc, double dx, double dy,
-                                   unsigned long long *out)
+__global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *Q, const double *W, const double *Tc,
+                                   double dx, double dy, unsigned long long *out)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double r = 0.0;
@@ -266,7 +318,7 @@ __global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *W, const 
         double rho = 0.0, rR = 0.0, cv = 0.0;
         const double T = Tc[i];
         for (int s = 0; s < g.ns; ++s) {
-            const double rs = W[(size_t)s * n + i];
+            const double rs = Q[(size_t)s * n + i];
             double e, cvs;
             species_e_cv(t, s, T, e, cvs);
             rho += rs;
@@ -318,21 +370,29 @@ hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &fg, int dir,
     // (a0, a1, stage input, stage output): Q1 = Q + dt L(Q); Q1 <- 3/4 Q + 1/4 (Q1 + dt L(Q1));
     // Q <- 1/3 Q + 2/3 (Q1 + dt L(Q1))
     const double a0[3] = {0.0, 0.75, 1.0 / 3.0}, a1[3] = {1.0, 0.25, 2.0 / 3.0};
+    // stage k: faces of its input's primitives, then the update, which in stages 0 and 1 also
+    // forms the primitives of its output for the next stage
+    const bool regs = g.ns <= kFluidNsRegs;
+    if (regs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    auto stage = [&](auto dirc, const double *in, double *out, int k) {
+        constexpr int D = decltype(dirc)::value;
+        if (regs) hipLaunchKernelGGL((fluid_flux_kernel<D, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, in, W, F);
+        else hipLaunchKernelGGL((fluid_flux_kernel<D, 0>), dim3(gf), dim3(block), 0, s, t, g, in, W, F);
+        if (k == 2)
+            hipLaunchKernelGGL(fluid_update_kernel<D>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
+        else if (regs)
+            hipLaunchKernelGGL((fluid_update_prim_kernel<D, kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, in, out,
+                               F, dt, h, a0[k], a1[k], W, T);
+        else
+            hipLaunchKernelGGL((fluid_update_prim_kernel<D, 0>), dim3(gc), dim3(block), 0, s, t, g, Q, in, out, F, dt, h,
+                               a0[k], a1[k], W, T);
+    };
     for (int k = 0; k < 3; ++k) {
         const double *in = k == 0 ? Q : Q1;
         double *out = k == 2 ? Q : Q1;
-        const bool regs = g.ns <= kFluidNsRegs;
-        if (regs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, in, W, T);
-        else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, in, W, T);
-        if (dir == 0) {
-            if (regs) hipLaunchKernelGGL((fluid_flux_kernel<0, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, W, F);
-            else hipLaunchKernelGGL((fluid_flux_kernel<0, 0>), dim3(gf), dim3(block), 0, s, t, g, W, F);
-            hipLaunchKernelGGL(fluid_update_kernel<0>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
-        } else {
-            if (regs) hipLaunchKernelGGL((fluid_flux_kernel<1, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, W, F);
-            else hipLaunchKernelGGL((fluid_flux_kernel<1, 0>), dim3(gf), dim3(block), 0, s, t, g, W, F);
-            hipLaunchKernelGGL(fluid_update_kernel<1>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
-        }
+        if (dir == 0) stage(std::integral_constant<int, 0>{}, in, out, k);
+        else stage(std::integral_constant<int, 1>{}, in, out, k);
     }
     return hipGetLastError();
 }
@@ -345,7 +405,7 @@ hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &fg, const do
     const unsigned gc = (unsigned)((g.n + block - 1) / block);
     if (g.ns <= kFluidNsRegs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
     else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
-    hipLaunchKernelGGL(fluid_speed_kernel, dim3(gc), dim3(block), 0, s, t, g, W, T, dx, dy, out);
+    hipLaunchKernelGGL(fluid_speed_kernel, dim3(gc), dim3(block), 0, s, t, g, Q, W, T, dx, dy, out);
     return hipGetLastError();
 }
 
