@@ -143,7 +143,7 @@ __device__ __forceinline__ int wrap(int k, int len, int bc)
 // NSR > 0: mechanisms of at most NSR species keep each species' two reconstructed states in
 // registers (one reconstruction per species); NSR = 0 streams them (three per species).
 template <int DIR, int NSR>
-__global__ void fluid_flux_kernel(WaveTables t, Grid g, const double *Qs, const double *W, double *F)
+__global__ void __launch_bounds__(256) fluid_flux_kernel(WaveTables t, Grid g, const double *Qs, const double *W, double *F)
 {
     const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int fw = DIR == 0 ? g.nx + 1 : g.nx;      // faces per row of the face array
