@@ -295,15 +295,30 @@ std::string lane_source(const MechHost &m, int block, std::vector<double> &const
         o << "        const double dlkf = " << ((x.b != 0.0 || x.Ta != 0.0) ? "fma(" + K(x.Ta) + ", iT, " + K(x.b) + ") * iT" : std::string("0.0")) << ";\n";
         o << "        const double pf = " << mass_action("kf", x.reac_sp, x.reac_nu, x.nreac) << ";\n";
         if (x.rev) {
-            std::string sg = "0.0", sh = "0.0";
+            // sums of nu_s g_s and nu_s h_s: the first term stands alone (a literal zero to
+            // start from would cost an add, since 0 + (-0) is not -0), and a zero change of
+            // moles drops its term
+            std::string sg, sh;
+            auto term = [&](int nu, const std::string &v) {
+                return nu == 1 ? v : nu == -1 ? "(-" + v + ")" : "(" + lit((double)nu) + " * " + v + ")";
+            };
             for (int k = 0; k < x.npart; ++k) {
-                if (!x.part[k].nu) continue;
-                sg = "fma(" + lit((double)x.part[k].nu) + ", g" + std::to_string(x.part[k].sp) + ", " + sg + ")";
-                sh = "fma(" + lit((double)x.part[k].nu) + ", h" + std::to_string(x.part[k].sp) + ", " + sh + ")";
+                const int nu = x.part[k].nu;
+                if (!nu) continue;
+                const std::string g = "g" + std::to_string(x.part[k].sp), h = "h" + std::to_string(x.part[k].sp);
+                sg = sg.empty() ? term(nu, g) : "fma(" + lit((double)nu) + ", " + g + ", " + sg + ")";
+                sh = sh.empty() ? term(nu, h) : "fma(" + lit((double)nu) + ", " + h + ", " + sh + ")";
             }
-            o << "        const double lKc = " << lit((double)x.dnu) << " * lPaRT - " << sg << ";\n";
+            if (sg.empty()) sg = sh = "0.0";
+            if (x.dnu != 0)
+                o << "        const double lKc = " << lit((double)x.dnu) << " * lPaRT - " << sg << ";\n";
+            else
+                o << "        const double lKc = -" << sg << ";\n";
             o << "        const double kb = kin_exp(lkf - lKc);\n";
-            o << "        const double dlKc = (" << lit((double)-x.dnu) << " + " << sh << ") * iT;\n";
+            if (x.dnu != 0)
+                o << "        const double dlKc = (" << lit((double)-x.dnu) << " + " << sh << ") * iT;\n";
+            else
+                o << "        const double dlKc = " << sh << " * iT;\n";
             o << "        const double pb = " << mass_action("kb", x.prod_sp, x.prod_nu, x.nprod) << ";\n";
             o << "        const double D = pf - pb;\n";
         } else {
