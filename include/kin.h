@@ -378,7 +378,8 @@ kin_status kin_autotune(kin_ctx *ctx, int32_t mech_id, int32_t inst_id, double d
 enum { KIN_BC_PERIODIC = 0, KIN_BC_OUTFLOW = 1 };
 
 /* Create a fluid grid (spacings dx, dy in m) for a mechanism; the library allocates its state
- * and workspace (about 3 (Ns + 3) + 4 doubles per cell plus the face fluxes).
+ * and workspace (about 3 (Ns + 3) + 4 doubles per cell plus the face fluxes).  nx, ny >= 1, and
+ * >= 3 for KIN_BC_PERIODIC (the six-cell stencil wraps once); KIN_EINVAL otherwise.
  * Paper: Sec. 4.1, the whole domain stored as one-dimensional arrays per variable. */
 kin_status kin_fluid_create(kin_ctx *ctx, int32_t mech_id, int32_t nx, int32_t ny, double dx, double dy,
                             int32_t bc, int32_t *fluid_id);

@@ -188,6 +188,8 @@ def hlle(gas, WL, WR):
 def _ghost(a, bc):
     """Extend the last axis by NG cells per side."""
     if bc == "periodic":
+        if a.shape[-1] < NG:
+            raise ValueError("a periodic direction needs at least NG cells")
         return np.concatenate([a[..., -NG:], a, a[..., :NG]], axis=-1)
     if bc == "outflow":
         return np.concatenate([np.repeat(a[..., :1], NG, axis=-1), a, np.repeat(a[..., -1:], NG, axis=-1)], axis=-1)

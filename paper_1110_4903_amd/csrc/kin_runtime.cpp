@@ -1553,6 +1553,9 @@ kin_status kin_fluid_create(kin_ctx *ctx, int32_t mech_id, int32_t nx, int32_t n
         (bc != KIN_BC_PERIODIC && bc != KIN_BC_OUTFLOW))
         return err(KIN_EINVAL, "bad fluid grid arguments");
     if ((long long)nx * ny > (1LL << 31)) return err(KIN_EINVAL, "fluid grid too large");
+    // the six-cell stencil wraps at most once around a periodic direction of three or more cells
+    if (bc == KIN_BC_PERIODIC && (nx < 3 || ny < 3))
+        return err(KIN_EINVAL, "a periodic fluid grid needs at least 3 cells in each direction");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->mechs.find(mech_id);
     if (it == ctx->mechs.end()) return err(KIN_ENOTFOUND, "unknown mechanism id");

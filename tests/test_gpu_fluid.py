@@ -195,3 +195,19 @@ def test_fluid_full_grid_conservation(ctx, fo):
     assert np.all(np.isfinite(Qg))
     ctx.fluid_release(fid)
     ctx.mech_release(mid)
+
+
+def test_grid_arguments_checked(ctx):
+    """Bad grids are refused before any device work: a periodic direction of fewer than three
+    cells (the stencil would wrap twice), non-positive spacings, an unknown boundary rule; a
+    transmissive grid of one row is accepted."""
+    from paper_1110_4903_amd import kin
+    m = synth.mechanism("mech9")
+    mid = ctx.mech_upload(m)
+    for nx, ny, dx, bc in ((2, 8, 1e-3, 0), (8, 1, 1e-3, 0), (8, 8, 0.0, 1), (8, 8, 1e-3, 7)):
+        with pytest.raises(kin.KinError) as e:
+            ctx.fluid_create(mid, nx, ny, dx, 1e-3, bc)
+        assert e.value.status == kin.EINVAL, (nx, ny, dx, bc)
+    fid = ctx.fluid_create(mid, 8, 1, 1e-3, 1e-3, 1)
+    ctx.fluid_release(fid)
+    ctx.mech_release(mid)
