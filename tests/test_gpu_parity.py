@@ -705,3 +705,38 @@ def test_batched_graph_with_global_layout(ctx):
         ctx.instance_release(i)
     ctx.mech_release(mb)
     ctx.mech_release(m3)
+
+
+def test_kernel_times_recorded_per_advance():
+    """KIN_CTX_TIME_KERNELS: one duration per single-instance advance, in launch order, each
+    positive and within the host's wall time around its advance; the list empties on reading;
+    a context without the flag records nothing.  These durations are the benchmark roofline's
+    kernel time."""
+    import time
+    import torch
+    from paper_1110_4903_amd import kin
+    m = synth.mechanism("mech9")
+    st = synth.uniform_cells(71, 20000, 9, 1.0)
+    for flag in (True, False):
+        c = kin.Context(0, time_kernels=flag)
+        try:
+            mid = c.mech_upload(m)
+            iid = c.state_upload(mid, st.rho, st.T, st.Y)
+            c.advance([iid], [1e-6])
+            torch.cuda.synchronize()
+            c.kernel_times()
+            walls = []
+            for dt in (1e-7, 1e-6, 4e-6):
+                t0 = time.perf_counter()
+                c.advance([iid], [dt])
+                torch.cuda.synchronize()
+                walls.append(1e3 * (time.perf_counter() - t0))
+            kt = c.kernel_times()
+            if flag:
+                assert len(kt) == 3, kt
+                assert all(0.0 < k <= w for k, w in zip(kt, walls)), (kt, walls)
+                assert c.kernel_times() == []
+            else:
+                assert kt == []
+        finally:
+            c.close()
