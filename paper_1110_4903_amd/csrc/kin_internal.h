@@ -81,7 +81,7 @@ constexpr int kChunk = 64;   // reactions evaluated per wavefront pass
 // 0-2 and products in slots 3-5 (species merged within each side; unused slots have nu = 0
 // and species 0).  nu holds the slot's signed stoichiometric coefficient (-nu' for a reactant,
 // +nu'' for a product); coff and roff are byte offsets of the slot's species in a species
-// vector (8 s) and of its row in the Jacobian (8 s NPAD, NPAD the padded row length).
+// vector (8 s) and of its row in the Jacobian (8 s (NPAD + 1), NPAD the padded row length).
 struct RxnRec {
     int8_t rev, pad0;
     int16_t tb;
@@ -114,8 +114,8 @@ struct WaveTables {
     const RxnCoef *rxk;     // [nr]
     const double *ef;       // [ns] e_s(T_ref) at T_ref = 298.15 K, J/kg (conserved-variable adapter)
     const double *effT;     // [ns][ntb] third-body efficiencies per slot, transposed
-    const int *tbe;         // [ntbe] entry e: slot | row << 16 (rows: participants with nonzero nu)
-    const double *effR;     // [ntbe][ns] entry (slot r, row s): nu_rs M_s eff_rk / M_k
+    const double *tbA;      // [ceil(ntb/4)][ceil(ns/16)][64] nu_qs M_s in matrix-operand tiles
+    const double *tbB;      // [ceil(ntb/4)][ceil(ns/16)][64] eff_qk / M_k in matrix-operand tiles
     const int *tgs;         // [ntbe] the same entries ordered by slot: slot | row << 16
     const double *tgf;      // [ntbe] row factor nu_rs M_s of each tgs entry
     const double *effTM;    // [ns][ntb] effT[k][q] / M_k

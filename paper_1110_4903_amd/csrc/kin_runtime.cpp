@@ -395,14 +395,12 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
                 const int q = 3 * side + m;
                 p.nu[q] = (int8_t)nu;
                 p.coff[q] = (uint16_t)(8 * sp);
-                p.roff[q] = (uint16_t)(npad > 0 ? 8 * sp * npad : 0);  // wave layout only
+                p.roff[q] = (uint16_t)(npad > 0 ? 8 * sp * (npad + 1) : 0);  // wave layout only (row stride NPAD + 1)
                 k.rowc[q] = (double)nu * h.M[sp];
                 k.colc[q] = 1.0 / h.M[sp];
             }
         }
     }
-    // dense third-body entries (slot q, row s), sorted by row so that the kernel sums a row's
-    // entries in a register and adds the sum to the Jacobian once
     // e_s(T_ref) at T_ref = 298.15 K (J/kg) for the conserved-variable adapter
     std::vector<double> ef(ns);
     for (int s = 0; s < ns; ++s) {
@@ -411,21 +409,39 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         const double h_RT = a[0] + Tr * (a[1] / 2 + Tr * (a[2] / 3 + Tr * (a[3] / 4 + Tr * a[4] / 5))) + a[5] / Tr;
         ef[s] = 8.31446261815324e3 / h.M[s] * Tr * (h_RT - 1.0);
     }
-    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0), effR;
-    std::vector<int> tbe;
-    for (int s = 0; s < ns; ++s) {
-        for (int r = 0; r < nr; ++r) {
-            const int q = slot[r];
-            if (q < 0) continue;
-            const Rxn &x = h.rx[r];
-            for (int j = 0; j < x.npart; ++j) {
-                if (!x.part[j].nu || x.part[j].sp != s) continue;
-                const double cs = (double)x.part[j].nu * h.M[s];
-                tbe.push_back(q | (s << 16));
-                for (int k = 0; k < ns; ++k) effR.push_back(cs * h.eff[(size_t)slot_row[q] * ns + k] / h.M[k]);
-            }
+    // dense third-body terms as a small matrix product per cell: J[s][k] += sum_q A[s][q] B[q][k]
+    // with A[s][q] = nu_qs M_s D_q (D_q = q_f - q_b of slot q, known only in the kernel) and
+    // B[q][k] = eff_qk / M_k.  tbA holds nu_qs M_s and tbB holds B, both cut into the operand
+    // tiles of the 16x16x4 matrix instruction: tile (kk, t) is 64 values, lane l of tbA's tile
+    // holding row 16 t + l % 16 and slot 4 kk + l / 16, lane l of tbB's tile holding slot
+    // 4 kk + l / 16 and column 16 t + l % 16.  There are ceil(NPAD / 16) row tiles (NPAD the
+    // wave layout's padded row length) and slot steps in whole groups of four; entries outside
+    // the mechanism are zero.
+    std::vector<double> effT((size_t)std::max(1, ns * ntb), 0.0);
+    std::vector<double> nuM((size_t)ns * std::max(1, ntb), 0.0);
+    int ntbe = 0;
+    for (int r = 0; r < nr; ++r) {
+        const int q = slot[r];
+        if (q < 0) continue;
+        const Rxn &x = h.rx[r];
+        for (int j = 0; j < x.npart; ++j) {
+            if (!x.part[j].nu) continue;
+            const int s = x.part[j].sp;
+            nuM[(size_t)s * ntb + q] += (double)x.part[j].nu * h.M[s];
+            ++ntbe;
         }
     }
+    const int tb_nt = (npad > 0 ? npad + 15 : ns + 15) / 16, tb_nk = 4 * ((ntb + 15) / 16);
+    std::vector<double> tbA((size_t)std::max(1, tb_nk * tb_nt) * 64, 0.0), tbB(tbA.size(), 0.0);
+    for (int kk = 0; kk < tb_nk; ++kk)
+        for (int ti = 0; ti < tb_nt; ++ti)
+            for (int l = 0; l < 64; ++l) {
+                const int q = 4 * kk + l / 16, rc = 16 * ti + l % 16;
+                if (q >= ntb || rc >= ns) continue;
+                const size_t o = ((size_t)kk * tb_nt + ti) * 64 + l;
+                tbA[o] = nuM[(size_t)rc * ntb + q];
+                tbB[o] = h.eff[(size_t)slot_row[q] * ns + rc] / h.M[rc];
+            }
     for (int r = 0; r < nr; ++r) {
         const int q = slot[r];
         if (q < 0) continue;
@@ -434,9 +450,6 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     std::vector<double> effTM(effT);
     for (int k = 0; k < ns; ++k)
         for (int q = 0; q < ntb; ++q) effTM[(size_t)k * ntb + q] /= h.M[k];
-    const int ntbe = (int)tbe.size();
-    if (tbe.empty()) tbe.push_back(0);
-    if (effR.empty()) effR.push_back(0.0);
     // the same entries ordered by slot, with their row factors (global-memory layout: one
     // pass of lanes over entries adds into distinct rows)
     std::vector<int> tgs;
@@ -459,8 +472,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
         {h.nasa.data(), sizeof(double) * h.nasa.size(), 0}, {h.Tmid.data(), sizeof(double) * ns, 0},
         {h.M.data(), sizeof(double) * ns, 0}, {rxd.data(), sizeof(double) * rxd.size(), 0},
         {rxc.data(), sizeof(RxnRec) * rxc.size(), 0}, {rxk.data(), sizeof(RxnCoef) * rxk.size(), 0},
-        {effT.data(), sizeof(double) * effT.size(), 0}, {effR.data(), sizeof(double) * effR.size(), 0},
-        {tbe.data(), sizeof(int) * tbe.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0},
+        {effT.data(), sizeof(double) * effT.size(), 0}, {tbA.data(), sizeof(double) * tbA.size(), 0},
+        {tbB.data(), sizeof(double) * tbB.size(), 0}, {chunk_rp.data(), sizeof(int) * chunk_rp.size(), 0},
         {ef.data(), sizeof(double) * ns, 0}, {tgs.data(), sizeof(int) * tgs.size(), 0},
         {tgf.data(), sizeof(double) * tgf.size(), 0}, {effTM.data(), sizeof(double) * effTM.size(), 0}};
     size_t total = 0;
@@ -481,8 +494,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     t.rxc = reinterpret_cast<const RxnRec *>(b + pc[4].off);
     t.rxk = reinterpret_cast<const RxnCoef *>(b + pc[5].off);
     t.effT = reinterpret_cast<const double *>(b + pc[6].off);
-    t.effR = reinterpret_cast<const double *>(b + pc[7].off);
-    t.tbe = reinterpret_cast<const int *>(b + pc[8].off);
+    t.tbA = reinterpret_cast<const double *>(b + pc[7].off);
+    t.tbB = reinterpret_cast<const double *>(b + pc[8].off);
     t.chunk_rp = reinterpret_cast<const int *>(b + pc[9].off);
     t.ef = reinterpret_cast<const double *>(b + pc[10].off);
     t.tgs = reinterpret_cast<const int *>(b + pc[11].off);

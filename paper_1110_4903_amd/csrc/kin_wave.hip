@@ -1,5 +1,5 @@
-// kin_wave.hip -- table-driven kernels: the wave layout (one cell per 64-wide wavefront, one
-// row of the Newton matrix per lane) and the initial-energy kernel.
+// kin_wave.hip -- table-driven kernels: the wave layout (one cell per 64-wide wavefront) and
+// the initial-energy kernel.
 //
 // Method (Le & Cambier, arXiv:1110.4903): rates from the Arrhenius law, reverse rates from
 // the equilibrium constant and third-body sums (Sec. 3.2); the point-implicit system
@@ -9,13 +9,17 @@
 // here a cell owns one wavefront:
 //   * lanes evaluate reactions 64 at a time and add each reaction's terms straight into the
 //     cell's Jacobian in LDS with LDS atomic adds (no per-row gather lists); the dense
-//     third-body terms go in afterwards one Jacobian column per lane;
-//   * each lane then holds one row of the Newton matrix in registers; the elimination runs as
-//     a loop over blocks of four pivot steps (the row is rotated by four registers after each
-//     block, so every step addresses its pivot column at a compile-time register), the pivot
-//     search is a DPP butterfly inside 16-lane rows plus a read of the four row winners, and
-//     each pivot row is stored once, packed, in LDS, where it serves both the elimination and
-//     the back substitution.
+//     third-body terms go in afterwards as a small matrix product on the FP64 matrix cores;
+//   * FP64: the augmented Newton matrix is formed in place of J in LDS and eliminated there,
+//     blocked by four columns: panel pivot steps with one row (or column) per lane and
+//     physical row exchanges, then the trailing update as 16 x 16 tiles on the FP64 matrix
+//     instructions; back substitution with one row per lane;
+//   * FP32-LU: each lane holds one row of the FP32 Newton matrix in registers; the elimination
+//     runs as a loop over blocks of four pivot steps (the row is rotated by four registers
+//     after each block, so every step addresses its pivot column at a compile-time register)
+//     and the pivot row reaches the other lanes by readlane.
+// Both pivot searches are a DPP butterfly inside 16-lane rows plus a read of the four row
+// winners.
 // Wavefronts never synchronise with each other, so cells with different iteration counts do
 // not wait for one another.
 #include <hip/hip_runtime.h>
@@ -45,17 +49,22 @@ __device__ __forceinline__ Thermo thermo(const WaveTables &t, int s, double T, d
 }
 
 // ---- per-wavefront LDS layout (in doubles) --------------------------------------------------
-// [0, R)            J[N][NPAD] (columns N.. stay zero); the solve itself works in registers
+// [0, R)            J[N][NPAD + 1] (columns N.. stay zero), then the FP64 Newton matrix
+//                   [I - hJ | b] in place; the odd row stride lets a column read by one lane
+//                   per row hit distinct banks
 // W[NPAD]           net production sums, then f (the T-derivative sums accumulate straight
 //                   into J's column N - 1 and are scaled there)
 // c[NPAD]           concentrations
 // g[NPAD], hh[NPAD] g/RT and h/RT for the rates, then e_s and cv_s for the energy row
 // Mc[ntbp]          third-body concentrations; each is replaced by its reaction's q_f - q_b
 //                   (one reaction per slot reads, then writes, its own entry)
-// 13.5 KB for the 36-species mechanism keeps twelve wavefronts on a compute unit
+// 13.8 KB for the 36-species mechanism
 __host__ __device__ inline int round_even(int x) { return (x + 1) & ~1; }
 
-__host__ __device__ inline int j_region(int N, int npad) { return round_even(N * npad); }
+// row stride of J and the Newton matrix, in entries of 8 bytes
+__host__ __device__ constexpr int j_stride(int npad) { return npad + 1; }
+
+__host__ __device__ inline int j_region(int N, int npad) { return round_even(N * j_stride(npad)); }
 
 __host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
 {
@@ -65,6 +74,8 @@ __host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
 struct Lds {
     double *J, *W, *c, *g, *hh, *Mc;
 };
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ Lds lds_map(double *base, int N, int ntb, int npad)
 {
@@ -224,7 +235,7 @@ template <int NPAD>
 __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane, double rho, double xs,
                                      double Ms, double invMs)
 {
-    const int ns = t.ns, N = ns + 1, JS = NPAD;
+    const int ns = t.ns, N = ns + 1, JS = j_stride(NPAD);
     const double T = rdlane(xs, ns);
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
@@ -271,41 +282,58 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         }
     }
     wave_sync();
-    // dense third-body terms: J[s][k] gains D_q effR[q,s][k] for every slot q whose reaction has
-    // s among its participants (D_q = q_f - q_b, effR = nu_qs M_s eff_qk / M_k).  Entries come
-    // sorted by row: lane k sums a row's entries in a register and adds the sum once; entries
-    // are loaded eight per batch so that their loads overlap
-    {
-        const bool col = lane < ns;
-        const double *er = t.effR + (col ? lane : 0);
-        const auto *tbe = uniform_table(t.tbe);
-        int cur = t.ntbe > 0 ? (tbe[0] >> 16) : 0;
-        double acc = 0.0;
-        for (int e0 = 0; e0 < t.ntbe; e0 += 8) {
-            int ent[8];
-            double v[8], D[8];
+    // dense third-body terms: J[s][k] gains sum_q (nu_qs M_s D_q)(eff_qk / M_k) over the
+    // third-body slots q (D_q = q_f - q_b), a product of an ns x ntb and an ntb x ns matrix
+    // that the FP64 matrix instruction forms in 16 x 16 output tiles, four slots per step.  The
+    // host stores both factors' constant parts in the instruction's operand order, padded to
+    // NT = NPAD / 16 (rounded up) row tiles and to whole batches of four steps, so each operand
+    // is one coalesced load and a batch's loads are all in flight together; the left operand
+    // is scaled by D_q of the lane's slot
+    if (t.ntb > 0) {
+        constexpr int NT = (NPAD + 15) / 16;
+        const int nb = (t.ntb + 15) / 16;
+        const int g = lane >> 4, c16 = lane & 15;
+#pragma unroll 1
+        for (int ti = 0; ti < NT; ++ti) {
+            dvec4 acc[NT];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int e = e0 + q < t.ntbe ? e0 + q : t.ntbe - 1;
-                ent[q] = tbe[e];
-                v[q] = er[(size_t)e * ns];
+            for (int tj = 0; tj < NT; ++tj) acc[tj] = dvec4{0.0, 0.0, 0.0, 0.0};
+            const double *pa = t.tbA + (size_t)ti * 64 + lane;
+            const double *pb = t.tbB + lane;
+#pragma unroll 1
+            for (int bt = 0; bt < nb; ++bt) {
+                double av[4], dv[4], bv[4][NT];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const size_t kk = 4 * bt + u;
+                    av[u] = pa[kk * NT * 64];
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj) bv[u][tj] = pb[(kk * NT + tj) * 64];
+                    const int q = 4 * (int)kk + g;
+                    dv[u] = L.Mc[q < t.ntb ? q : t.ntb - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double a = av[u] * (4 * (4 * bt + u) + g < t.ntb ? dv[u] : 0.0);
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+                        acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[u][tj], acc[tj], 0, 0, 0);
+                }
             }
+            // accumulator register r of lane l is output row 4 r + l / 16, column l % 16.  Rows
+            // and columns past the species are exact zeros; the adds that would fall outside the
+            // species block go to the energy row instead, which is assigned afterwards
 #pragma unroll
-            for (int q = 0; q < 8; ++q) D[q] = L.Mc[ent[q] & 0xffff];
+            for (int tj = 0; tj < NT; ++tj) {
+                const int k = 16 * tj + c16;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (e0 + q < t.ntbe) {
-                    const int s = ent[q] >> 16;
-                    if (s != cur) {
-                        if (col) lds_add(L.J + (size_t)cur * JS + lane, acc);
-                        acc = 0.0;
-                        cur = s;
-                    }
-                    acc = fma(D[q], v[q], acc);
+                for (int r = 0; r < 4; ++r) {
+                    const int srow = 16 * ti + 4 * r + g;
+                    const bool in = srow < ns && k < ns;
+                    lds_add(L.J + (in ? (size_t)srow * JS + k : (size_t)ns * JS + c16), in ? acc[tj][r] : 0.0);
                 }
             }
         }
-        if (col && t.ntbe > 0) lds_add(L.J + (size_t)cur * JS + lane, acc);
     }
     wave_sync();
     // species rows of f and the temperature column; e_s and cv_s replace g and h
@@ -422,6 +450,152 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, R 
     return ok;
 }
 
+// 16 x 16 x 4 FP64 matrix instruction: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator register r of lane l holds output column l % 16 and row 4 r + l / 16
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+
+// 1/p from the hardware reciprocal refined by Newton steps (within an ulp for normal p)
+__device__ __forceinline__ double recip(double p)
+{
+    double y = __builtin_amdgcn_rcp(p);
+    y = fma(y, fma(-p, y, 1.0), y);
+    return fma(y, fma(-p, y, 1.0), y);
+}
+
+// Gaussian elimination with partial pivoting on the augmented Newton matrix [A | b] in the
+// wavefront's LDS: row i at M + i S (S odd), N rows, b in column N.  Right-looking, blocked by
+// four columns, with LAPACK's order of row exchanges:
+//   * panel: pivot step k reads column k (one row per lane), takes the largest |a_ik| over
+//     rows k..N-1 (ties to the lowest row), exchanges rows k and p over columns c0..N (one
+//     column per lane), stores the multipliers in column k and updates the panel's other
+//     columns, and b when it lies in the panel;
+//   * the pivot rows right of the panel, U12 = L11^-1 A12 (one column per lane);
+//   * the rest, A22 -= L21 U12, on the matrix instructions in 16 x 16 tiles with k = 4.
+// Columns left of the panel are not exchanged: b is eliminated with the matrix, so the
+// multipliers stored there are not read again.  Back substitution from U and y (column N)
+// follows.  Lane k returns x_k (lanes >= N: 0); false on an exactly zero pivot.
+template <typename R>
+__device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
+{
+    typedef Mfma<R> MF;
+    bool ok = true;
+    R rdiag = R(1);  // lane k: 1 / u_kk
+    const int g = lane >> 4, c16 = lane & 15;
+    const int lr = lane < N ? lane : N - 1;  // a lane's row for reads (lanes >= N read a real row)
+    R *Mr = M + lr * S;
+    for (int c0 = 0; c0 < N; c0 += 4) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = c0 + kk;
+            if (k >= N) break;
+            const bool cand = lane >= k && lane < N;
+            const R v0 = Mr[k];
+            const R v = cand ? v0 : R(0);
+            const int p = pivot_lane<R>((R)fabs(v), cand, lane);
+            const R piv = rdlane(v, p);
+            ok = ok && piv != R(0);
+            R vi = v;
+            if (p != k) {
+                const int j = c0 + lane;
+                if (j <= N) {
+                    R *a = M + k * S + j, *b = M + p * S + j;
+                    const R rk = *a, rpv = *b;
+                    *a = rpv;
+                    *b = rk;
+                }
+                const R vk = rdlane(v, k);
+                vi = (lane == p) ? vk : v;
+                wave_sync();
+            }
+            const R rp = recip(piv);
+            rdiag = (lane == k) ? rp : rdiag;
+            const bool below = lane > k && lane < N;
+            const R l = vi * rp;
+            R w[3];
+            // the panel's later columns (and b when it lies in the panel)
+#pragma unroll
+            for (int jj = kk + 1; jj < 4; ++jj)
+                if (c0 + jj <= N) w[jj - kk - 1] = fma(-l, M[k * S + c0 + jj], Mr[c0 + jj]);
+            if (below) {
+                Mr[k] = l;
+#pragma unroll
+                for (int jj = kk + 1; jj < 4; ++jj)
+                    if (c0 + jj <= N) Mr[c0 + jj] = w[jj - kk - 1];
+            }
+            wave_sync();
+        }
+        const int t0 = c0 + 4;
+        if (t0 > N) break;  // that panel held the last columns and b
+        {   // U12: forward substitution with the panel's unit lower triangle, one column per lane
+            const int j = t0 + lane;
+            const bool col = j <= N;
+            const int jj = col ? j : N;
+            const R *P = M + c0 * S;
+            R u0 = P[jj], u1 = P[S + jj], u2 = P[2 * S + jj], u3 = P[3 * S + jj];
+            const R l10 = P[S + c0], l20 = P[2 * S + c0], l21 = P[2 * S + c0 + 1];
+            const R l30 = P[3 * S + c0], l31 = P[3 * S + c0 + 1], l32 = P[3 * S + c0 + 2];
+            u1 = fma(-l10, u0, u1);
+            u2 = fma(-l21, u1, fma(-l20, u0, u2));
+            u3 = fma(-l32, u2, fma(-l31, u1, fma(-l30, u0, u3)));
+            if (col) {
+                R *Q = M + c0 * S + j;
+                Q[S] = u1;
+                Q[2 * S] = u2;
+                Q[3 * S] = u3;
+            }
+            wave_sync();
+        }
+        // trailing rows t0..N-1, columns t0..N: C -= L21 U12, one 16 x 16 tile per instruction
+        for (int r0 = t0; r0 < N; r0 += 16) {
+            const int ra = r0 + c16;
+            const R a0 = M[(ra < N ? ra : N - 1) * S + c0 + g];
+            const R av = ra < N ? -a0 : R(0);
+            int crow[4];
+            bool rin[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + MF::row(r, lane);
+                rin[r] = row < N;
+                crow[r] = (rin[r] ? row : N - 1) * S;
+            }
+            for (int q0 = t0; q0 <= N; q0 += 16) {
+                const int qb = q0 + c16;
+                const bool qin = qb <= N;
+                const int qc = qin ? qb : N;
+                const R b0 = M[(c0 + g) * S + qc];
+                const R bv = qin ? b0 : R(0);
+                typename MF::v4 acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = M[crow[r] + qc];
+                acc = MF::op(av, bv, acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (rin[r] && qin) M[crow[r] + qb] = acc[r];
+            }
+        }
+        wave_sync();
+    }
+    // back substitution: x_k = y_k / u_kk, then every row above k removes u_ik x_k from y_i
+    R y = lane < N ? Mr[N] : R(0);
+    R xl = R(0);
+    for (int k = N - 1; k >= 0; --k) {
+        const R uik = Mr[k];
+        const R xk = rdlane(y, k) * rdlane(rdiag, k);
+        xl = (lane == k) ? xk : xl;
+        y = (lane < k) ? fma(-uik, xk, y) : y;
+    }
+    x = xl;
+    return ok;
+}
+
 struct StepCtl {
     double rtol, atol_Y, atol_T, y_neg;
     int k_max;
@@ -435,49 +609,66 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
                                         double &xs, double h, const StepCtl &c, int &iters, double Ms,
                                         double invMs)
 {
-    const int ns = t.ns, N = ns + 1, JS = NPAD;
+    const int ns = t.ns, N = ns + 1, JS = j_stride(NPAD);
     double xk = xs;
     double r_prev = -1.0;  // weighted norm of the previous update
     for (int k = 0; k < c.k_max; ++k) {
         ++iters;
         eval<NPAD>(t, L, lane, rho, xk, Ms, invMs);
-        double bi = 0.0;
-        double arow[NPAD];
-        bool bad = false;
-        if (lane < N) {
-            bi = -((xk - xs) - h * L.W[lane]);
-            bad = !__builtin_isfinite(bi);
-            // the Newton matrix row I - hJ, formed in place (columns N.. stay zero)
-            double *Jr = L.J + (size_t)lane * JS;
-#pragma unroll 4
-            for (int j = 0; j < N; ++j) {
-                const double v = (j == lane ? 1.0 : 0.0) - h * Jr[j];
-                Jr[j] = v;
-                bad = bad || !__builtin_isfinite(v);
-            }
-#pragma unroll
-            for (int j = 0; j < NPAD; ++j) arow[j] = Jr[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < NPAD; ++j) arow[j] = 0.0;
-        }
-        if (__any(bad)) return false;
-        wave_sync();  // J and f are read before the next evaluation clears them
         bool ok;
         double d;
-        if (F32) {
+        if constexpr (F32) {
+            // the Newton matrix row I - hJ, formed in place (columns N.. stay zero), then loaded,
+            // scaled by its largest magnitude and rounded to FP32 for the register elimination
+            double bi = 0.0;
+            double arow[NPAD];
+            bool bad = false;
+            if (lane < N) {
+                bi = -((xk - xs) - h * L.W[lane]);
+                bad = !__builtin_isfinite(bi);
+                double *Jr = L.J + (size_t)lane * JS;
+#pragma unroll 4
+                for (int j = 0; j < N; ++j) {
+                    const double v = (j == lane ? 1.0 : 0.0) - h * Jr[j];
+                    Jr[j] = v;
+                    bad = bad || !__builtin_isfinite(v);
+                }
+#pragma unroll
+                for (int j = 0; j < NPAD; ++j) arow[j] = Jr[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NPAD; ++j) arow[j] = 0.0;
+            }
+            if (__any(bad)) return false;
+            wave_sync();  // J and f are read before the next evaluation clears them
             float af[NPAD];
             double m = 0.0;
 #pragma unroll
             for (int j = 0; j < NPAD; ++j) m = fmax(m, fabs(arow[j]));
-            const double s = (lane < N) ? 1.0 / m : 0.0;
+            const double sc = (lane < N) ? 1.0 / m : 0.0;
 #pragma unroll
-            for (int j = 0; j < NPAD; ++j) af[j] = (float)(arow[j] * s);
+            for (int j = 0; j < NPAD; ++j) af[j] = (float)(arow[j] * sc);
             float xf;
-            ok = lu_solve<NPAD, float>(af, (float)(bi * s), N, lane, xf);
+            ok = lu_solve<NPAD, float>(af, (float)(bi * sc), N, lane, xf);
             d = (double)xf;
         } else {
-            ok = lu_solve<NPAD, double>(arow, bi, N, lane, d);
+            // the augmented Newton matrix [I - hJ | b] in place of J, one row per lane
+            bool bad = false;
+            if (lane < N) {
+                const double bi = -((xk - xs) - h * L.W[lane]);
+                bad = !__builtin_isfinite(bi);
+                double *Jr = L.J + (size_t)lane * JS;
+#pragma unroll 4
+                for (int j = 0; j < N; ++j) {
+                    const double v = (j == lane ? 1.0 : 0.0) - h * Jr[j];
+                    Jr[j] = v;
+                    bad = bad || !__builtin_isfinite(v);
+                }
+                Jr[N] = bi;
+            }
+            if (__any(bad)) return false;
+            wave_sync();
+            ok = lu_solve_lds<double>(L.J, JS, N, lane, d);
         }
         if (!ok) return false;
         wave_sync();
