@@ -588,7 +588,7 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
     R xl = R(0);
     for (int k = N - 1; k >= 0; --k) {
         const R uik = Mr[k];
-        const R xk = rdlane(y, k) * rdlane(rdiag, k);
+        const R xk = rdlane(y * rdiag, k);  // lane k's y is final here
         xl = (lane == k) ? xk : xl;
         y = (lane < k) ? fma(-uik, xk, y) : y;
     }
