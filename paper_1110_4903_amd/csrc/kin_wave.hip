@@ -153,7 +153,9 @@ __device__ __forceinline__ void cpow_nu(double c, int nu, double &p, double &dp)
 // Slots 0-2 are the reactants, 3-5 the products; a species on both sides appears in one slot
 // of each, and its two terms add up in J.  The loops over slots stop at the pass's largest
 // counts (rmax reactants, pmax products); shorter reactions' unused slots add exact zeros.
-template <int NPAD>
+// RM, PM > 0 fix those counts at compile time (the two-reactant, two-product passes that most
+// reactions fall into), which turns the slot tests into constants.
+template <int NPAD, int RM, int PM>
 __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
                                                const double4 &rd, int rmax, int pmax, double iT,
                                                double lT, double lPaRT)
@@ -163,7 +165,9 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
     const char *cb = reinterpret_cast<const char *>(L.c);
     const char *gb = reinterpret_cast<const char *>(L.g);
     const char *hb = reinterpret_cast<const char *>(L.hh);
-    const auto used = [&](int q) { return q < 3 ? q < rmax : q - 3 < pmax; };
+    const auto used = [&](int q) {
+        return q < 3 ? q < (RM > 0 ? RM : rmax) : q - 3 < (PM > 0 ? PM : pmax);
+    };
     const double lkf = fma(-Ta, iT, fma(b, lT, lnA));
     const double kf = exp(lkf);
     const double dlkf = fma(Ta, iT, b) * iT;
@@ -278,7 +282,12 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
             const double4 rd = rn;
             const int rp = uniform_table(t.chunk_rp)[r0 / kW];
             if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; }
-            if (r < t.nr) reaction_terms<NPAD>(t, L, r, x, rd, rp & 0xff, rp >> 8, iT, lT, lPaRT);
+            if (r < t.nr) {
+                if (rp == (2 | 2 << 8))
+                    reaction_terms<NPAD, 2, 2>(t, L, r, x, rd, 2, 2, iT, lT, lPaRT);
+                else
+                    reaction_terms<NPAD, 0, 0>(t, L, r, x, rd, rp & 0xff, rp >> 8, iT, lT, lPaRT);
+            }
         }
     }
     wave_sync();
