@@ -501,46 +501,54 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
     const int lr = lane < N ? lane : N - 1;  // a lane's row for reads (lanes >= N read a real row)
     R *Mr = M + lr * S;
     for (int c0 = 0; c0 < N; c0 += 4) {
+        // the panel's four columns (and b when it lies in the panel) in registers, one row per
+        // lane; the pivot row's entries reach the other lanes by readlane
+        R P[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) P[jj] = (c0 + jj <= N) ? Mr[c0 + jj] : R(0);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = c0 + kk;
             if (k >= N) break;
             const bool cand = lane >= k && lane < N;
-            const R v0 = Mr[k];
-            const R v = cand ? v0 : R(0);
+            const R v = cand ? P[kk] : R(0);
             const int p = pivot_lane<R>((R)fabs(v), cand, lane);
             const R piv = rdlane(v, p);
             ok = ok && piv != R(0);
-            R vi = v;
             if (p != k) {
-                const int j = c0 + lane;
+                // rows k and p: the panel in registers, the columns right of it in LDS (one
+                // column per lane; later exchanges of the panel keep LDS order)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const R rk = rdlane(P[jj], k), rpv = rdlane(P[jj], p);
+                    P[jj] = (lane == k) ? rpv : ((lane == p) ? rk : P[jj]);
+                }
+                const int j = c0 + 4 + lane;
                 if (j <= N) {
                     R *a = M + k * S + j, *b = M + p * S + j;
                     const R rk = *a, rpv = *b;
                     *a = rpv;
                     *b = rk;
                 }
-                const R vk = rdlane(v, k);
-                vi = (lane == p) ? vk : v;
-                wave_sync();
             }
             const R rp = recip(piv);
             rdiag = (lane == k) ? rp : rdiag;
             const bool below = lane > k && lane < N;
-            const R l = vi * rp;
-            R w[3];
-            // the panel's later columns (and b when it lies in the panel)
+            const R l = P[kk] * rp;
+            P[kk] = below ? l : P[kk];
 #pragma unroll
-            for (int jj = kk + 1; jj < 4; ++jj)
-                if (c0 + jj <= N) w[jj - kk - 1] = fma(-l, M[k * S + c0 + jj], Mr[c0 + jj]);
-            if (below) {
-                Mr[k] = l;
-#pragma unroll
-                for (int jj = kk + 1; jj < 4; ++jj)
-                    if (c0 + jj <= N) Mr[c0 + jj] = w[jj - kk - 1];
+            for (int jj = kk + 1; jj < 4; ++jj) {
+                if (c0 + jj > N) break;
+                const R u = rdlane(P[jj], k);
+                P[jj] = below ? fma(-l, u, P[jj]) : P[jj];
             }
-            wave_sync();
         }
+        if (lane < N) {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (c0 + jj <= N) Mr[c0 + jj] = P[jj];
+        }
+        wave_sync();
         const int t0 = c0 + 4;
         if (t0 > N) break;  // that panel held the last columns and b
         {   // U12: forward substitution with the panel's unit lower triangle, one column per lane
