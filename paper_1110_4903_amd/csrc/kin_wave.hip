@@ -491,10 +491,11 @@ __device__ __forceinline__ double recip(double p)
 // Columns left of the panel are not exchanged: b is eliminated with the matrix, so the
 // multipliers stored there are not read again.  Back substitution from U and y (column N)
 // follows.  Lane k returns x_k (lanes >= N: 0); false on an exactly zero pivot.
-template <typename R>
+template <int NPAD, typename R>
 __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
 {
     typedef Mfma<R> MF;
+    constexpr int TQ = (NPAD - 3 + 15) / 16;  // column tiles right of a panel (columns 4..N)
     bool ok = true;
     R rdiag = R(1);  // lane k: 1 / u_kk
     const int g = lane >> 4, c16 = lane & 15;
@@ -583,19 +584,32 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
                 rin[r] = row < N;
                 crow[r] = (rin[r] ? row : N - 1) * S;
             }
-            for (int q0 = t0; q0 <= N; q0 += 16) {
-                const int qb = q0 + c16;
-                const bool qin = qb <= N;
-                const int qc = qin ? qb : N;
-                const R b0 = M[(c0 + g) * S + qc];
-                const R bv = qin ? b0 : R(0);
-                typename MF::v4 acc;
+            // the row of tiles: all operand and accumulator loads first, then the instructions,
+            // then the stores
+            typename MF::v4 acc[TQ];
+            R bv[TQ];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = M[crow[r] + qc];
-                acc = MF::op(av, bv, acc);
+            for (int tq = 0; tq < TQ; ++tq) {
+                const int qb = t0 + 16 * tq + c16;
+                if (t0 + 16 * tq > N) break;
+                const int qc = qb <= N ? qb : N;
+                const R b0 = M[(c0 + g) * S + qc];
+                bv[tq] = qb <= N ? b0 : R(0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[tq][r] = M[crow[r] + qc];
+            }
+#pragma unroll
+            for (int tq = 0; tq < TQ; ++tq) {
+                if (t0 + 16 * tq > N) break;
+                acc[tq] = MF::op(av, bv[tq], acc[tq]);
+            }
+#pragma unroll
+            for (int tq = 0; tq < TQ; ++tq) {
+                const int qb = t0 + 16 * tq + c16;
+                if (t0 + 16 * tq > N) break;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (rin[r] && qin) M[crow[r] + qb] = acc[r];
+                    if (rin[r] && qb <= N) M[crow[r] + qb] = acc[tq][r];
             }
         }
         wave_sync();
@@ -685,7 +699,7 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
             }
             if (__any(bad)) return false;
             wave_sync();
-            ok = lu_solve_lds<double>(L.J, JS, N, lane, d);
+            ok = lu_solve_lds<NPAD, double>(L.J, JS, N, lane, d);
         }
         if (!ok) return false;
         wave_sync();
