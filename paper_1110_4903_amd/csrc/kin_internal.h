@@ -244,7 +244,9 @@ size_t global_work_doubles_per_slot(int ns, int ntb);
 // Cost order of an instance's n cells (kin_order.hip): order[n], per-tile scratch
 // ocount[kOrderClasses * order_tiles(n)].  key: the iterations of the previous advance, or
 // with direct, cost classes 0..kOrderClasses-1 already.
-hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount, hipStream_t s);
+// clear (may be null): a work counter that the order's scan sets to zero on the way
+hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount,
+                              unsigned long long *clear, hipStream_t s);
 hipError_t launch_global(const WaveTables &t, const AdvanceArgs &a, bool fp32_lu, double *work,
                          long long slots, hipStream_t stream);
 hipError_t launch_energy(const WaveTables &t, long long n, long long ld, const double *T,

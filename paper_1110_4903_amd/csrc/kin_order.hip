@@ -54,8 +54,10 @@ __global__ void __launch_bounds__(kOrderThreads) order_count_kernel(const int *i
 // In place: ocount[kC t + c] becomes the first position of tile t's class-c cells.  Classes
 // are laid out from kC - 1 down to 0; within a class, tiles in order.  One block; thread u
 // owns a contiguous run of tiles.
-__global__ void __launch_bounds__(kScanThreads) order_scan_kernel(int *ocount, long long tiles)
+__global__ void __launch_bounds__(kScanThreads) order_scan_kernel(int *ocount, long long tiles,
+                                                                  unsigned long long *clear)
 {
+    if (clear && threadIdx.x == 0) *clear = 0ull;  // the advance's work counter
     __shared__ int sc[kC][kScanThreads];
     __shared__ int tot[kC];
     const int u = threadIdx.x;
@@ -140,14 +142,15 @@ __global__ void __launch_bounds__(kOrderThreads) order_scatter_kernel(const int 
 
 }  // namespace
 
-hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount, hipStream_t s)
+hipError_t launch_cost_order(const int *key, long long n, bool direct, int *order, int *ocount,
+                              unsigned long long *clear, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (n > 0x7fffffffLL) return hipErrorInvalidValue;
     const long long tiles = order_tiles(n);
     const int d = direct ? 1 : 0;
     hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, key, n, d, ocount);
-    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, ocount, tiles);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, ocount, tiles, clear);
     hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)tiles), dim3(kOrderThreads), 0, s, key, n, d, ocount,
                        order);
     return hipGetLastError();

@@ -1192,14 +1192,14 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
     a.nspan = 1;
     a.total = in.n;
     a.counter = in.counter;
-    KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
     // cost order: cells that needed many iterations in the previous advance are taken first;
-    // in the lane layout a first advance orders by the source term's temperature change
+    // in the lane layout a first advance orders by the source term's temperature change.  The
+    // order's scan also clears the work counter; without an order a kernel of its own does
     const long long order_min = layout == KIN_LAYOUT_LANE ? kOrderMinLaneCells : kOrderMinCells;
     if (!o.point_implicit && in.n >= order_min && in.n <= 0x7fffffffLL) {
         const Arena ar = arena_at(static_cast<char *>(in.buf), in.n, m.h.ns);
         if (in.iters_current) {
-            KIN_HIP(ctx, launch_cost_order(in.iters, in.n, false, ar.order, ar.ocount, st));
+            KIN_HIP(ctx, launch_cost_order(in.iters, in.n, false, ar.order, ar.ocount, in.counter, st));
             a.span[0].order = ar.order;
         } else if (layout == KIN_LAYOUT_LANE && m.h.ns <= kLaneNsMax) {
             if ((s = build_lane(ctx, m, block)) != KIN_OK) return s;
@@ -1208,10 +1208,11 @@ kin_status kin_advance(kin_ctx *ctx, const int32_t *inst_ids, const double *dts,
             void *params[] = {&a, &key};
             const long long grid = (in.n + block - 1) / block;
             KIN_HIP(ctx, hipModuleLaunchKernel(m.lane_cost, (unsigned)grid, 1, 1, block, 1, 1, 0, st, params, nullptr));
-            KIN_HIP(ctx, launch_cost_order(ar.okey, in.n, true, ar.order, ar.ocount, st));
+            KIN_HIP(ctx, launch_cost_order(ar.okey, in.n, true, ar.order, ar.ocount, in.counter, st));
             a.span[0].order = ar.order;
         }
     }
+    if (!a.span[0].order) KIN_HIP(ctx, launch_zero_u64(in.counter, 1, st));
     hipEvent_t k1 = nullptr;
     if (ctx->time_kernels) {
         if (ctx->kev_used == ctx->kev.size()) {
