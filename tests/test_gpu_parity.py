@@ -514,10 +514,13 @@ def test_divergence_test_off_matches_oracle(ctx, orc):
         assert s["checked"] == st.n
 
 
-@pytest.mark.parametrize("ns,nr,ne", [(20, 120, 3), (28, 200, 4), (45, 360, 4), (60, 480, 4)])
+@pytest.mark.parametrize("ns,nr,ne", [(20, 120, 3), (23, 140, 3), (28, 200, 4), (30, 200, 4), (45, 360, 4),
+                                      (47, 380, 4), (60, 480, 4)])
 def test_wave_layout_other_row_lengths(ctx, orc, ns, nr, ne):
     """Generated mechanisms whose padded Jacobian rows (24, 32, 48, 64 columns) select the other
-    instantiations of the wave kernel, 128 cells, FP64 and FP32-LU, against the oracle."""
+    instantiations of the wave kernel, 128 cells, FP64 and FP32-LU, against the oracle.  The
+    unknown counts N = Ns + 1 cover every remainder mod 4 (the FP64 elimination's panel width):
+    24 and 48 end on a full panel with only b right of it, 31 on a three-column panel."""
     from tests.parity import compare
     from paper_1110_4903_amd import kin
     m = synth.make_mechanism(synth.MechRecipe(f"gen{ns}", seed=100 + ns, n_elements=ne, n_species=ns,
