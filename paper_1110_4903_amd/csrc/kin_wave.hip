@@ -482,10 +482,12 @@ __device__ __forceinline__ double recip(double p)
 // Gaussian elimination with partial pivoting on the augmented Newton matrix [A | b] in the
 // wavefront's LDS: row i at M + i S (S odd), N rows, b in column N.  Right-looking, blocked by
 // four columns, with LAPACK's order of row exchanges:
-//   * panel: pivot step k reads column k (one row per lane), takes the largest |a_ik| over
-//     rows k..N-1 (ties to the lowest row), exchanges rows k and p over columns c0..N (one
-//     column per lane), stores the multipliers in column k and updates the panel's other
-//     columns, and b when it lies in the panel;
+//   * panel: its four columns (and b when it lies in the panel) are held in registers, one row
+//     per lane, for its four pivot steps.  Step k takes the largest |a_ik| over rows k..N-1
+//     (ties to the lowest row), exchanges rows k and p (in registers by readlane, right of
+//     the panel in LDS by one column per lane), forms the multipliers in column k and updates
+//     the panel's other columns with the pivot row's entries broadcast by readlane; the
+//     panel is then written back;
 //   * the pivot rows right of the panel, U12 = L11^-1 A12 (one column per lane);
 //   * the rest, A22 -= L21 U12, on the matrix instructions in 16 x 16 tiles with k = 4.
 // Columns left of the panel are not exchanged: b is eliminated with the matrix, so the
@@ -556,10 +558,10 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
             const int j = t0 + lane;
             const bool col = j <= N;
             const int jj = col ? j : N;
-            const R *P = M + c0 * S;
-            R u0 = P[jj], u1 = P[S + jj], u2 = P[2 * S + jj], u3 = P[3 * S + jj];
-            const R l10 = P[S + c0], l20 = P[2 * S + c0], l21 = P[2 * S + c0 + 1];
-            const R l30 = P[3 * S + c0], l31 = P[3 * S + c0 + 1], l32 = P[3 * S + c0 + 2];
+            const R *Pr = M + c0 * S;
+            R u0 = Pr[jj], u1 = Pr[S + jj], u2 = Pr[2 * S + jj], u3 = Pr[3 * S + jj];
+            const R l10 = Pr[S + c0], l20 = Pr[2 * S + c0], l21 = Pr[2 * S + c0 + 1];
+            const R l30 = Pr[3 * S + c0], l31 = Pr[3 * S + c0 + 1], l32 = Pr[3 * S + c0 + 2];
             u1 = fma(-l10, u0, u1);
             u2 = fma(-l21, u1, fma(-l20, u0, u2));
             u3 = fma(-l32, u2, fma(-l31, u1, fma(-l30, u0, u3)));
