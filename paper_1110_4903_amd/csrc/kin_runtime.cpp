@@ -431,7 +431,8 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
             ++ntbe;
         }
     }
-    const int tb_nt = (npad > 0 ? npad + 15 : ns + 15) / 16, tb_nk = 4 * ((ntb + 15) / 16);
+    // (only the wave layout reads them: mechanisms too large for it get empty tables)
+    const int tb_nt = npad > 0 ? (npad + 15) / 16 : 0, tb_nk = npad > 0 ? 4 * ((ntb + 15) / 16) : 0;
     std::vector<double> tbA((size_t)std::max(1, tb_nk * tb_nt) * 64, 0.0), tbB(tbA.size(), 0.0);
     for (int kk = 0; kk < tb_nk; ++kk)
         for (int ti = 0; ti < tb_nt; ++ti)
