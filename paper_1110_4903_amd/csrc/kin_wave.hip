@@ -483,11 +483,12 @@ __device__ __forceinline__ double recip(double p)
 // wavefront's LDS: row i at M + i S (S odd), N rows, b in column N.  Right-looking, blocked by
 // four columns, with LAPACK's order of row exchanges:
 //   * panel: its four columns (and b when it lies in the panel) are held in registers, one row
-//     per lane, for its four pivot steps.  Step k takes the largest |a_ik| over rows k..N-1
-//     (ties to the lowest row), exchanges rows k and p (in registers by readlane, right of
-//     the panel in LDS by one column per lane), forms the multipliers in column k and updates
-//     the panel's other columns with the pivot row's entries broadcast by readlane; the
-//     panel is then written back;
+//     per lane, for its four pivot steps; rows keep their lanes and carry their current
+//     position.  Step k takes the largest |a_ik| over positions k..N-1 (ties to the lowest
+//     position), exchanges positions k and p (right of the panel in LDS, by one column per
+//     lane), forms the multipliers in column k and updates the panel's other columns with the
+//     pivot row's entries broadcast by readlane; each row is then written back at its final
+//     position;
 //   * the pivot rows right of the panel, U12 = L11^-1 A12 (one column per lane);
 //   * the rest, A22 -= L21 U12, on the matrix instructions in 16 x 16 tiles with k = 4.
 // Columns left of the panel are not exchanged: b is eliminated with the matrix, so the
@@ -509,23 +510,22 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
         R P[4];
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) P[jj] = (c0 + jj <= N) ? Mr[c0 + jj] : R(0);
+        // rows do not move between lanes during the panel: pos is a row's current position,
+        // and the write-back below puts each row at its final one
+        int pos = lane;
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = c0 + kk;
             if (k >= N) break;
-            const bool cand = lane >= k && lane < N;
+            const bool cand = pos >= k && lane < N;
             const R v = cand ? P[kk] : R(0);
-            const int p = pivot_lane<R>((R)fabs(v), cand, lane);
-            const R piv = rdlane(v, p);
+            const int w = pivot_lane<R>((R)fabs(v), cand, pos);  // the lane holding the pivot row
+            const int p = rdlane(pos, w);
+            const R piv = rdlane(v, w);
             ok = ok && piv != R(0);
             if (p != k) {
-                // rows k and p: the panel in registers, the columns right of it in LDS (one
-                // column per lane; later exchanges of the panel keep LDS order)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const R rk = rdlane(P[jj], k), rpv = rdlane(P[jj], p);
-                    P[jj] = (lane == k) ? rpv : ((lane == p) ? rk : P[jj]);
-                }
+                // right of the panel the rows at positions k and p are exchanged in LDS, one
+                // column per lane (later exchanges of the panel keep LDS order)
                 const int j = c0 + 4 + lane;
                 if (j <= N) {
                     R *a = M + k * S + j, *b = M + p * S + j;
@@ -534,22 +534,24 @@ __device__ __forceinline__ bool lu_solve_lds(R *M, int S, int N, int lane, R &x)
                     *b = rk;
                 }
             }
+            pos = (lane == w) ? k : (pos == k ? p : pos);
             const R rp = recip(piv);
             rdiag = (lane == k) ? rp : rdiag;
-            const bool below = lane > k && lane < N;
+            const bool below = pos > k && lane < N;
             const R l = P[kk] * rp;
             P[kk] = below ? l : P[kk];
 #pragma unroll
             for (int jj = kk + 1; jj < 4; ++jj) {
                 if (c0 + jj > N) break;
-                const R u = rdlane(P[jj], k);
+                const R u = rdlane(P[jj], w);
                 P[jj] = below ? fma(-l, u, P[jj]) : P[jj];
             }
         }
         if (lane < N) {
+            R *Mp = M + pos * S;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
-                if (c0 + jj <= N) Mr[c0 + jj] = P[jj];
+                if (c0 + jj <= N) Mp[c0 + jj] = P[jj];
         }
         wave_sync();
         const int t0 = c0 + 4;
