@@ -535,6 +535,25 @@ def test_wave_layout_other_row_lengths(ctx, orc, ns, nr, ne):
     ctx.mech_release(mid)
 
 
+@pytest.mark.gpu
+def test_wave_layout_without_third_body_reactions(ctx, orc):
+    """A 20-species mechanism with no third-body reaction on the wave layout (its dense
+    third-body product is skipped), 128 cells, FP64 and FP32-LU, against the oracle."""
+    from paper_1110_4903_amd import kin
+    m = synth.make_mechanism(synth.MechRecipe("gen20_no_m", seed=420, n_elements=3, n_species=20,
+                                              n_reactions=120, frac_third_body=0.0,
+                                              frac_irreversible=0.3))
+    assert m.ntb == 0
+    st = synth.uniform_cells(520, 128, 20, 0.5)
+    mid = ctx.mech_upload(m)
+    assert ctx.query_int(kin.Q_LAYOUT, mid) == kin.LAYOUT_WAVE
+    for prec, rtol, bound in ((kin.FP64, 1e-10, 2), (kin.FP32_LU, 1e-6, 0.1)):
+        s, _, _ = every_cell(ctx, orc, m, st, 1e-6, prec, rtol, mech_id=mid, max_mismatch=bound)
+        report(f"gen20 without third bodies prec {prec}", s)
+        assert s["checked"] == st.n
+    ctx.mech_release(mid)
+
+
 @pytest.mark.parametrize("ns,nr,ne,block", [(15, 40, 3, 128), (11, 30, 3, 256)])
 def test_lane_layout_largest_systems(ctx, orc, ns, nr, ne, block):
     """The lane layout at its largest systems: 15 species (a 16 x 16 Newton matrix in registers)
