@@ -379,6 +379,19 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     wave_sync();
 }
 
+// The register elimination's multipliers are a_ik times this reciprocal of the pivot: in FP32
+// the hardware reciprocal refined by one Newton step (within an ulp), in FP64 the quotient
+template <typename R>
+__device__ __forceinline__ R rpiv_of(R p)
+{
+    if constexpr (sizeof(R) == 4) {
+        const float y = __builtin_amdgcn_rcpf(p);
+        return fmaf(y, fmaf(-p, y, 1.0f), y);
+    } else {
+        return R(1) / p;
+    }
+}
+
 // Gaussian elimination with partial pivoting, one row per lane, and back substitution.  Lane
 // i < N enters with row i of A in a[] and b_i in bb; on return x holds solution component
 // `lane` (lanes >= N: 0).  Pivot rule: the row of largest |a_ik| among rows not yet used,
@@ -415,7 +428,7 @@ __device__ __forceinline__ bool lu_solve(R (&a)[NPAD], R bb, int N, int lane, R 
                     const R yk = rdlane(bb, w);
                     dg = (lane == w) ? piv : dg;
                     const bool elim = pos > k;
-                    const R l = elim ? a[kk] / piv : R(0);
+                    const R l = elim ? a[kk] * rpiv_of(piv) : R(0);
                     bb = fma(-l, yk, bb);
                     // pivot row from the pivot lane's registers, eight columns at a time;
                     // register positions from NPAD - B blk on hold columns already eliminated
