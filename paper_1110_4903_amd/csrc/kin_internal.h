@@ -103,6 +103,8 @@ struct RxnCoef {
 struct WaveTables {
     int ns, nr, ntb, nchunk;  // ntb: third-body reactions (each has a slot; RxnRec::tb is the slot)
     int ntbe;                 // third-body Jacobian entries (slot, row) over all slots
+    int tb_last;              // slots 0..tb_last-1 have a participant in the wave layout's last
+                              // 16-row tile (the slots are numbered so)
     double lnPaR;           // ln(P_atm / R) in CGS units
     const double *nasa;     // [ns][14]
     const double *Tmid;     // [ns]

@@ -358,6 +358,27 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     // reactions in order of (reactant count, product count), so that each pass of 64 lanes is
     // homogeneous and its loops over slots stop at the pass's largest counts
     const int npad = wave_npad(ns + 1);
+    // for the wave layout's dense third-body product: slots whose reaction has a participant in
+    // the last 16-row tile come first, so that the tile's product stops after their steps
+    int tb_last = ntb;
+    if (npad > 0 && ntb > 0) {
+        const int row0 = 16 * ((npad + 15) / 16 - 1);
+        std::vector<char> touch(ntb, 0);
+        for (int r = 0; r < nr; ++r) {
+            if (slot[r] < 0) continue;
+            const Rxn &x = h.rx[r];
+            for (int j = 0; j < x.npart; ++j)
+                if (x.part[j].nu && x.part[j].sp >= row0) touch[slot[r]] = 1;
+        }
+        std::vector<int> renum(ntb), order;
+        for (int q = 0; q < ntb; ++q) if (touch[q]) order.push_back(q);
+        tb_last = (int)order.size();
+        for (int q = 0; q < ntb; ++q) if (!touch[q]) order.push_back(q);
+        std::vector<int> row_new(ntb);
+        for (int i = 0; i < ntb; ++i) { renum[order[i]] = i; row_new[i] = slot_row[order[i]]; }
+        for (int r = 0; r < nr; ++r) if (slot[r] >= 0) slot[r] = renum[slot[r]];
+        slot_row.swap(row_new);
+    }
     std::vector<int> perm(nr);
     for (int r = 0; r < nr; ++r) perm[r] = r;
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
@@ -487,6 +508,7 @@ static kin_status upload_tables(kin_ctx *ctx, Mech &m)
     char *b = static_cast<char *>(m.dbuf);
     WaveTables &t = m.tab;
     t.ns = ns; t.nr = nr; t.ntb = ntb; t.nchunk = nchunk; t.ntbe = ntbe;
+    t.tb_last = tb_last;
     t.lnPaR = std::log(kPatmCgs / kRuCgs);
     t.nasa = reinterpret_cast<const double *>(b + pc[0].off);
     t.Tmid = reinterpret_cast<const double *>(b + pc[1].off);

@@ -309,8 +309,11 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
             for (int tj = 0; tj < NT; ++tj) acc[tj] = dvec4{0.0, 0.0, 0.0, 0.0};
             const double *pa = t.tbA + (size_t)ti * 64 + lane;
             const double *pb = t.tbB + lane;
+            // the last row tile needs only the slots numbered first (those with a participant in
+            // its rows): its product stops after their batches
+            const int nbt = ti == NT - 1 ? (t.tb_last + 15) / 16 : nb;
 #pragma unroll 1
-            for (int bt = 0; bt < nb; ++bt) {
+            for (int bt = 0; bt < nbt; ++bt) {
                 double av[4], dv[4], bv[4][NT];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
