@@ -52,23 +52,33 @@ __device__ __forceinline__ Thermo thermo(const WaveTables &t, int s, double T, d
 // [0, R)            J[N][NPAD + 1] (columns N.. stay zero), then the FP64 Newton matrix
 //                   [I - hJ | b] in place; the odd row stride lets a column read by one lane
 //                   per row hit distinct banks
-// W[NPAD]           net production sums, then f (the T-derivative sums accumulate straight
+//                   (the last row stops after column N)
+// W[N + 1]          net production sums, then f (the T-derivative sums accumulate straight
 //                   into J's column N - 1 and are scaled there)
-// c[NPAD]           concentrations
-// g[NPAD], hh[NPAD] g/RT and h/RT for the rates, then e_s and cv_s for the energy row
-// Mc[ntbp]          third-body concentrations; each is replaced by its reaction's q_f - q_b
+// c, g, hh          concentrations, g/RT and h/RT for the rates, then e_s and cv_s for the
+//                   energy row: when N <= NPAD - 3 ("packed") they are the columns JS - 1, JS - 2
+//                   and JS - 3 of J's species rows, which the matrix never uses; otherwise three
+//                   vectors of N entries after W
+// Mc[ntb]           third-body concentrations; each is replaced by its reaction's q_f - q_b
 //                   (one reaction per slot reads, then writes, its own entry)
-// 13.8 KB for the 36-species mechanism
+// 12.8 KB for the 36-species mechanism (packed), which leaves room for twelve wavefronts on a
+// compute unit
 __host__ __device__ inline int round_even(int x) { return (x + 1) & ~1; }
 
 // row stride of J and the Newton matrix, in entries of 8 bytes
 __host__ __device__ constexpr int j_stride(int npad) { return npad + 1; }
 
-__host__ __device__ inline int j_region(int N, int npad) { return round_even(N * j_stride(npad)); }
+__host__ __device__ inline int j_entries(int N, int npad) { return (N - 1) * j_stride(npad) + N + 1; }
+
+__host__ __device__ inline int j_region(int N, int npad) { return round_even(j_entries(N, npad)); }
+
+// the species vectors fit in J's unused columns
+__host__ __device__ constexpr bool packed_vectors(int N, int npad) { return N <= npad - 3; }
 
 __host__ __device__ inline size_t lds_doubles(int N, int ntb, int npad)
 {
-    return (size_t)j_region(N, npad) + 4 * (size_t)npad + (size_t)round_even(ntb);
+    const size_t vec = packed_vectors(N, npad) ? 0 : 3 * (size_t)round_even(N);
+    return (size_t)j_region(N, npad) + (size_t)round_even(N + 1) + vec + (size_t)round_even(ntb);
 }
 
 struct Lds {
@@ -77,15 +87,22 @@ struct Lds {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ Lds lds_map(double *base, int N, int ntb, int npad)
+template <bool PK>
+__device__ __forceinline__ Lds lds_map(double *base, int N, int npad)
 {
     Lds L;
     double *p = base;
     L.J = p; p += j_region(N, npad);
-    L.W = p; p += npad;
-    L.c = p; p += npad;
-    L.g = p; p += npad;
-    L.hh = p; p += npad;
+    L.W = p; p += round_even(N + 1);
+    if (PK) {
+        L.c = L.J + (j_stride(npad) - 1);
+        L.g = L.J + (j_stride(npad) - 2);
+        L.hh = L.J + (j_stride(npad) - 3);
+    } else {
+        L.c = p; p += round_even(N);
+        L.g = p; p += round_even(N);
+        L.hh = p; p += round_even(N);
+    }
     L.Mc = p;
     return L;
 }
@@ -155,7 +172,7 @@ __device__ __forceinline__ void cpow_nu(double c, int nu, double &p, double &dp)
 // counts (rmax reactants, pmax products); shorter reactions' unused slots add exact zeros.
 // RM, PM > 0 fix those counts at compile time (the two-reactant, two-product passes that most
 // reactions fall into), which turns the slot tests into constants.
-template <int NPAD, int RM, int PM>
+template <int NPAD, int RM, int PM, bool PK>
 __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L, int r, const RxnRec &x,
                                                const double4 &rd, int rmax, int pmax, double iT,
                                                double lT, double lPaRT)
@@ -179,9 +196,11 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
         gv[q] = 0.0;
         hv[q] = 0.0;
         if (used(q)) {
-            c = *reinterpret_cast<const double *>(cb + x.coff[q]);
-            gv[q] = *reinterpret_cast<const double *>(gb + x.coff[q]);
-            hv[q] = *reinterpret_cast<const double *>(hb + x.coff[q]);
+            // packed species vectors sit one per Jacobian row: the row offset addresses them
+            const int vo = PK ? x.roff[q] : x.coff[q];
+            c = *reinterpret_cast<const double *>(cb + vo);
+            gv[q] = *reinterpret_cast<const double *>(gb + vo);
+            hv[q] = *reinterpret_cast<const double *>(hb + vo);
         }
         cpow_nu(c, q < 3 ? -x.nu[q] : x.nu[q], pw[q], dpw[q]);
     }
@@ -235,18 +254,19 @@ __device__ __forceinline__ void reaction_terms(const WaveTables &t, const Lds &L
 
 // f = dx/dt and J = df/dx of the cell at x (lane i holds x_i).  Leaves J in L.J (row-major,
 // stride NPAD, zero beyond column N - 1) and f in L.W.
-template <int NPAD>
+template <int NPAD, bool PK>
 __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane, double rho, double xs,
                                      double Ms, double invMs)
 {
     const int ns = t.ns, N = ns + 1, JS = j_stride(NPAD);
+    constexpr int VS = PK ? j_stride(NPAD) : 1;  // stride of the species vectors
     const double T = rdlane(xs, ns);
     const double iT = 1.0 / T, lT = log(T);
     const double rc = 1e-3 * rho, irc = 1.0 / rc;
     const double lPaRT = t.lnPaR - lT;  // ln(P_atm / (R T)), CGS
     {   // clear J and W (J's region ends where W begins)
         double2 *z = reinterpret_cast<double2 *>(L.J);
-        const int nj = N * JS / 2, n2 = nj + NPAD / 2;
+        const int nj = j_entries(N, NPAD) / 2, n2 = nj + round_even(N + 1) / 2;
         const int skip = j_region(N, NPAD) / 2 - nj;
         for (int k = lane; k < n2; k += kW) z[k < nj ? k : k + skip] = make_double2(0.0, 0.0);
     }
@@ -254,9 +274,9 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
     if (lane < ns) {
         const Thermo th = thermo(t, lane, T, iT, lT);
         const double rm = 8.31446261815324e3 * invMs;
-        L.c[lane] = xs * (rc * invMs);
-        L.g[lane] = th.h - th.s;
-        L.hh[lane] = th.h;
+        L.c[lane * VS] = xs * (rc * invMs);
+        L.g[lane * VS] = th.h - th.s;
+        L.hh[lane * VS] = th.h;
         ek = rm * T * (th.h - 1.0);
         cvk = rm * (th.cp - 1.0);
         dcvk = rm * th.dcp;
@@ -267,7 +287,7 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         double acc = 0.0;
         const double *e = t.effT + r;
 #pragma unroll 4
-        for (int s = 0; s < ns; ++s, e += t.ntb) acc = fma(*e, L.c[s], acc);
+        for (int s = 0; s < ns; ++s, e += t.ntb) acc = fma(*e, L.c[s * VS], acc);
         L.Mc[r] = acc;
     }
     wave_sync();
@@ -284,9 +304,9 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
             if (r + kW < t.nr) { xn = t.rxc[r + kW]; rn = rxd4[r + kW]; }
             if (r < t.nr) {
                 if (rp == (2 | 2 << 8))
-                    reaction_terms<NPAD, 2, 2>(t, L, r, x, rd, 2, 2, iT, lT, lPaRT);
+                    reaction_terms<NPAD, 2, 2, PK>(t, L, r, x, rd, 2, 2, iT, lT, lPaRT);
                 else
-                    reaction_terms<NPAD, 0, 0>(t, L, r, x, rd, rp & 0xff, rp >> 8, iT, lT, lPaRT);
+                    reaction_terms<NPAD, 0, 0, PK>(t, L, r, x, rd, rp & 0xff, rp >> 8, iT, lT, lPaRT);
             }
         }
     }
@@ -355,8 +375,8 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         fs = L.W[lane] * ms;
         L.J[(size_t)lane * JS + ns] *= ms;
         L.W[lane] = fs;
-        L.g[lane] = ek;
-        L.hh[lane] = cvk;
+        L.g[lane * VS] = ek;
+        L.hh[lane * VS] = cvk;
     }
     const double cv = wave_sum(lane < ns ? xs * cvk : 0.0);
     const double dcv = wave_sum(lane < ns ? xs * dcvk : 0.0);
@@ -370,11 +390,11 @@ __device__ __forceinline__ void eval(const WaveTables &t, const Lds &L, int lane
         double acc = 0.0;
         if (lane < ns) {
 #pragma unroll 4
-            for (int s = 0; s < ns; ++s) acc = fma(E[s], L.J[(size_t)s * JS + lane], acc);
+            for (int s = 0; s < ns; ++s) acc = fma(E[s * VS], L.J[(size_t)s * JS + lane], acc);
             L.J[(size_t)ns * JS + lane] = -fma(fT, cvk, acc) * icv;
         } else {
 #pragma unroll 4
-            for (int s = 0; s < ns; ++s) acc = fma(CV[s], L.W[s], fma(E[s], L.J[(size_t)s * JS + ns], acc));
+            for (int s = 0; s < ns; ++s) acc = fma(CV[s * VS], L.W[s], fma(E[s * VS], L.J[(size_t)s * JS + ns], acc));
             L.J[(size_t)ns * JS + ns] = -fma(fT, dcv, acc) * icv;
             L.W[ns] = fT;
         }
@@ -655,7 +675,7 @@ struct StepCtl {
 };
 
 // One backward-Euler sub-step of size h.  xs (lane i: x_i) is updated on success.
-template <int NPAD, bool F32>
+template <int NPAD, bool F32, bool PK>
 __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int lane, double rho, double e0,
                                         double &xs, double h, const StepCtl &c, int &iters, double Ms,
                                         double invMs)
@@ -665,7 +685,7 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
     double r_prev = -1.0;  // weighted norm of the previous update
     for (int k = 0; k < c.k_max; ++k) {
         ++iters;
-        eval<NPAD>(t, L, lane, rho, xk, Ms, invMs);
+        eval<NPAD, PK>(t, L, lane, rho, xk, Ms, invMs);
         bool ok;
         double d;
         if constexpr (F32) {
@@ -685,7 +705,7 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
                     bad = bad || !__builtin_isfinite(v);
                 }
 #pragma unroll
-                for (int j = 0; j < NPAD; ++j) arow[j] = Jr[j];
+                for (int j = 0; j < NPAD; ++j) arow[j] = j < N ? Jr[j] : 0.0;
             } else {
 #pragma unroll
                 for (int j = 0; j < NPAD; ++j) arow[j] = 0.0;
@@ -745,14 +765,14 @@ __device__ __forceinline__ bool substep(const WaveTables &t, const Lds &L, int l
     return false;
 }
 
-template <int NPAD, bool F32>
+template <int NPAD, bool F32, bool PK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) wave_kernel(WaveTables t, AdvanceArgs a, int wpb)
 {
     extern __shared__ double smem[];
     const int lane = threadIdx.x & (kW - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kW);
     const int ns = t.ns, N = ns + 1;
-    const Lds L = lds_map(smem + (size_t)wid * lds_doubles(N, t.ntb, NPAD), N, t.ntb, NPAD);
+    const Lds L = lds_map<PK>(smem + (size_t)wid * lds_doubles(N, t.ntb, NPAD), N, NPAD);
     const StepCtl c{a.rtol, a.atol_Y, a.atol_T, a.y_neg, a.k_max, a.point_implicit != 0, a.diverge_ratio};
     const double Ms = lane < ns ? t.M[lane] : 1.0;
     const double invMs = 1.0 / Ms;
@@ -794,7 +814,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) w
     while (tt < end) {
         if (iters >= a.max_iters) { st = 2; break; }
         const double h = ldexp(dt, -l);
-        const bool ok = substep<NPAD, F32>(t, L, lane, rho, e0, xs, h, c, iters, Ms, invMs);
+        const bool ok = substep<NPAD, F32, PK>(t, L, lane, rho, e0, xs, h, c, iters, Ms, invMs);
         hsh = (hsh ^ (unsigned long long)(2 * l + (ok ? 1 : 0))) * 0x100000001b3ull;
         tr.add(ok, lane);
         if (ok) {
@@ -927,9 +947,13 @@ __global__ void conserved_out_kernel(WaveTables t, long long n, long long ld, co
 template <int NPAD, bool F32>
 hipError_t launch_t(const WaveTables &t, const AdvanceArgs &a, int wpb, int grid, hipStream_t s)
 {
-    const size_t lds = sizeof(double) * lds_doubles(t.ns + 1, t.ntb, NPAD) * wpb;
+    const int N = t.ns + 1;
+    const size_t lds = sizeof(double) * lds_doubles(N, t.ntb, NPAD) * wpb;
     if (lds > 65536) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((wave_kernel<NPAD, F32>), dim3(grid), dim3(kW * wpb), lds, s, t, a, wpb);
+    if (packed_vectors(N, NPAD))
+        hipLaunchKernelGGL((wave_kernel<NPAD, F32, true>), dim3(grid), dim3(kW * wpb), lds, s, t, a, wpb);
+    else
+        hipLaunchKernelGGL((wave_kernel<NPAD, F32, false>), dim3(grid), dim3(kW * wpb), lds, s, t, a, wpb);
     return hipGetLastError();
 }
 
