@@ -103,18 +103,55 @@ __device__ __forceinline__ void cell_primitives(const WaveTables &t, const Grid 
     const double eint = q(ns + 2) - 0.5 * rho * (u * u + v * v);
     double T = Tc[i];
     if (!(T >= 100.0 && T <= 1e4)) T = 1000.0;
-    for (int it = 0; it < 60; ++it) {
-        double f = -eint, d = 0.0;
-        each_species([&](int s) {
-            double e, cv;
-            species_e_cv(t, s, T, e, cv);
-            const double r = rho_s(s);
-            f = fma(r, e, f);
-            d = fma(r, cv, d);
-        });
-        const double dT = f / d;
-        T -= dT;
-        if (!(fabs(dT) > 1e-13 * fabs(T))) break;   // converged, or not a number
+    if constexpr (NSR > 0) {
+        // Within one choice of NASA-7 range per species the mixture's sensible energy is itself
+        // a polynomial in T: with w_s = rho_s R_s and B_k = sum_s w_s a_sk, sum_s rho_s e_s(T) =
+        // B_5 + T (B_0 + T (B_1 / 2 + ... + T B_4 / 5)) - rR T - sum_s rho_s ef_s, and the heat
+        // capacity is B_0 + T (B_1 + ... + T B_4) - rR.  The B_k are summed once per range choice
+        // (a bit per species, set below its switch temperature), so a Newton iteration costs one
+        // polynomial instead of one per species.
+        static_assert(NSR <= 32, "range mask");
+        double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, EF = 0.0;
+        each_species([&](int s) { EF = fma(rs[s], uniform_table(t.ef)[s], EF); });
+        unsigned used = ~0u;  // no valid choice yet (ns <= 16 < 32 bits)
+        for (int it = 0; it < 60; ++it) {
+            unsigned lo = 0;
+            each_species([&](int s) { lo |= (T < uniform_table(t.Tmid)[s] ? 1u : 0u) << s; });
+            if (lo != used) {
+                used = lo;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) B[k] = 0.0;
+                each_species([&](int s) {
+                    const auto *nasa = uniform_table(t.nasa) + 14 * s;
+                    const bool l = (lo >> s) & 1u;
+                    const double w = rs[s] * (kRuJ / uniform_table(t.M)[s]);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) B[k] = fma(w, l ? nasa[k] : nasa[7 + k], B[k]);
+                });
+            }
+            const double C = fma(T, fma(T, fma(T, fma(T, B[4], B[3]), B[2]), B[1]), B[0]);
+            const double H = fma(T, fma(T, fma(T, fma(T, fma(T, B[4] * 0.2, B[3] * 0.25), B[2] * (1.0 / 3.0)),
+                                                B[1] * 0.5), B[0]), B[5]);
+            const double f = H - rR * T - EF - eint;
+            const double d = C - rR;
+            const double dT = f / d;
+            T -= dT;
+            if (!(fabs(dT) > 1e-13 * fabs(T))) break;   // converged, or not a number
+        }
+    } else {
+        for (int it = 0; it < 60; ++it) {
+            double f = -eint, d = 0.0;
+            each_species([&](int s) {
+                double e, cv;
+                species_e_cv(t, s, T, e, cv);
+                const double r = rho_s(s);
+                f = fma(r, e, f);
+                d = fma(r, cv, d);
+            });
+            const double dT = f / d;
+            T -= dT;
+            if (!(fabs(dT) > 1e-13 * fabs(T))) break;   // converged, or not a number
+        }
     }
     Tc[i] = T;
     W[(size_t)ns * n + i] = u;
