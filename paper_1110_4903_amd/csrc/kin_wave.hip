@@ -902,14 +902,49 @@ __global__ void conserved_in_kernel(WaveTables t, long long n, long long ld, dou
     if (!(Tk >= kTmin && Tk <= kTmax)) Tk = 1500.0;
     double Tout = __builtin_nan("");
     bool done = false;
-    for (int it = 0; it < 20 && !done; ++it) {
-        double e, cv;
-        cell_energy(t, ld, i, Y, Tk, e, cv);
-        if (!(cv > 0.0)) break;
-        const double dT = (e - e_t) / cv;
-        Tk -= dT;
-        if (!__builtin_isfinite(Tk) || Tk < kTmin || Tk > kTmax) break;
-        if (fabs(dT) <= 1e-13 * Tk) { Tout = Tk; done = true; }
+    if (t.ns < 32) {
+        // Within one NASA-7 range per species, e(Y, T) and c_v are polynomials in T with the
+        // mass-weighted coefficients B_k = sum_s Y_s R_s a_sk: e = B_5 + T (B_0 + ... + T B_4 / 5)
+        // - rR T and c_v = B_0 + T (B_1 + ... + T B_4) - rR.  The B_k are summed again only when
+        // T crosses a species' switch temperature (a bit per species, set below it).
+        double B[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, rR = 0.0;
+        for (int s = 0; s < t.ns; ++s) rR = fma(Y[(size_t)s * ld + i], 8.31446261815324e3 / uniform_table(t.M)[s], rR);
+        unsigned used = ~0u;  // no valid choice yet (fewer than 32 species)
+        for (int it = 0; it < 20 && !done; ++it) {
+            unsigned lo = 0;
+            for (int s = 0; s < t.ns; ++s) lo |= (Tk < uniform_table(t.Tmid)[s] ? 1u : 0u) << s;
+            if (lo != used) {
+                used = lo;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) B[k] = 0.0;
+                for (int s = 0; s < t.ns; ++s) {
+                    const auto *a = uniform_table(t.nasa) + 14 * s;
+                    const bool l = (lo >> s) & 1u;
+                    const double w = Y[(size_t)s * ld + i] * (8.31446261815324e3 / uniform_table(t.M)[s]);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) B[k] = fma(w, l ? a[k] : a[7 + k], B[k]);
+                }
+            }
+            const double C = fma(Tk, fma(Tk, fma(Tk, fma(Tk, B[4], B[3]), B[2]), B[1]), B[0]);
+            const double H = fma(Tk, fma(Tk, fma(Tk, fma(Tk, fma(Tk, B[4] * 0.2, B[3] * 0.25), B[2] * (1.0 / 3.0)),
+                                                  B[1] * 0.5), B[0]), B[5]);
+            const double e = H - rR * Tk, cv = C - rR;
+            if (!(cv > 0.0)) break;
+            const double dT = (e - e_t) / cv;
+            Tk -= dT;
+            if (!__builtin_isfinite(Tk) || Tk < kTmin || Tk > kTmax) break;
+            if (fabs(dT) <= 1e-13 * Tk) { Tout = Tk; done = true; }
+        }
+    } else {
+        for (int it = 0; it < 20 && !done; ++it) {
+            double e, cv;
+            cell_energy(t, ld, i, Y, Tk, e, cv);
+            if (!(cv > 0.0)) break;
+            const double dT = (e - e_t) / cv;
+            Tk -= dT;
+            if (!__builtin_isfinite(Tk) || Tk < kTmin || Tk > kTmax) break;
+            if (fabs(dT) <= 1e-13 * Tk) { Tout = Tk; done = true; }
+        }
     }
     if (!done) {
         double lo = kTmin, hi = kTmax, e, cv;
