@@ -407,7 +407,8 @@ kin_status kin_fluid_step(kin_ctx *ctx, int32_t fluid_id, double dt, int32_t y_f
  * (kin_state_reset_conserved with the partial densities and E - rho |u|^2 / 2, kin_advance of
  * dt with prec and s, kin_download_conserved back; momentum and kinetic energy are unchanged by
  * the chemistry).  inst_id must be an instance of the fluid's mechanism with nx ny cells (its
- * state is overwritten).  Asynchronous on `stream`.
+ * state is overwritten; the Newton iteration counts of its previous advance, if current, order
+ * this step's cells by cost, which changes no result).  Asynchronous on `stream`.
  * Paper: Sec. 2, Eq. operator_splitting, with Eq. energy for the formation-energy source. */
 kin_status kin_split_step(kin_ctx *ctx, int32_t fluid_id, int32_t inst_id, double dt, int32_t y_first,
                           kin_precision prec, const kin_solver_opts *s, void *stream);

@@ -1741,7 +1741,12 @@ kin_status kin_split_step(kin_ctx *ctx, int32_t fluid_id, int32_t inst_id, doubl
     // the chemistry sub-step on the same cells: partial densities and sensible energy in, the
     // fluid sweep's last temperatures as the inversion's start values, and back
     KIN_HIP(ctx, launch_fluid_kinetic(f->g, m->h.ns, f->Q, f->KE, f->Es, st));
+    // Iteration counts of the instance's previous advance (the chemistry of the previous split
+    // step, on the same cells) predict this step's costs as they do for a plain second advance,
+    // so they survive the reset for the cost order; the order never changes a cell's result.
+    const bool counts = iit->second->iters_current;
     if ((s = kin_state_reset_conserved(ctx, inst_id, f->Q, f->Es, f->T, KIN_MEM_DEVICE, stream)) != KIN_OK) return s;
+    iit->second->iters_current = counts;
     if ((s = kin_advance(ctx, &inst_id, &dt, 1, prec, sopt, stream)) != KIN_OK) return s;
     if ((s = kin_download_conserved(ctx, inst_id, f->Q, f->Es, KIN_MEM_DEVICE, stream)) != KIN_OK) return s;
     KIN_HIP(ctx, launch_fluid_energy_back(f->g, m->h.ns, f->Q, f->KE, f->Es, st));
