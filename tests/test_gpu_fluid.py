@@ -164,6 +164,45 @@ def test_split_step_against_oracles(ctx, orc, fo):
     ctx.mech_release(mid)
 
 
+def test_split_steps_cost_order_is_bitwise_neutral(ctx, fo):
+    """Operator-split steps on a 512 x 512 grid (262144 cells, enough for the lane layout's cost
+    order).  From the second step on, the chemistry is ordered by the previous step's iteration
+    counts, which the reset from the fluid state keeps.  The same steps on a copy whose instance
+    is reset before each step (so its counts are dropped and every step is ordered by the
+    source-term estimate) give bitwise the same grid and the same state, status, level,
+    iterations and schedule."""
+    m = synth.mechanism("mech9")
+    gas = fo.Gas(m)
+    nx = ny = 512
+    n, ns = nx * ny, m.ns
+    Q = np.ascontiguousarray(flow_state(fo, gas, nx, ny, 5, 1200.0, 2400.0))
+    mid = ctx.mech_upload(m)
+    fa = ctx.fluid_create(mid, nx, ny, 1e-4, 1e-4, 0)
+    fb = ctx.fluid_create(mid, nx, ny, 1e-4, 1e-4, 0)
+    ctx.fluid_upload(fa, Q)
+    ctx.fluid_upload(fb, Q)
+    # both grids take the step-size query: it also refreshes the temperatures that start the
+    # primitives' Newton, and those move the results by rounding
+    dt = ctx.fluid_max_dt(fa, 0.4)
+    assert ctx.fluid_max_dt(fb, 0.4) == dt
+    st0 = synth.CellStates(np.ones(n), np.full(n, 1000.0), np.full((ns, n), 1.0 / ns))
+    ia = ctx.state_upload(mid, st0.rho, st0.T, st0.Y)
+    ib = ctx.state_upload(mid, st0.rho, st0.T, st0.Y)
+    for k in range(3):
+        ctx.split_step(fa, ia, dt, y_first=bool(k & 1))
+        ctx.state_reset(ib, st0.rho, st0.T, st0.Y)
+        ctx.split_step(fb, ib, dt, y_first=bool(k & 1))
+    assert np.array_equal(ctx.fluid_download(fa), ctx.fluid_download(fb), equal_nan=True)
+    for u, v in zip(ctx.download(ia) + (ctx.download_schedule(ia),), ctx.download(ib) + (ctx.download_schedule(ib),)):
+        assert np.array_equal(u, v, equal_nan=True)
+    assert np.all(ctx.download(ia)[2] < 2)
+    for i in (ia, ib):
+        ctx.instance_release(i)
+    for f in (fa, fb):
+        ctx.fluid_release(f)
+    ctx.mech_release(mid)
+
+
 def test_fluid_full_grid_conservation(ctx, fo):
     """The headline's 1024 x 1024 grid (band temperature field of the 9-species mixture, with a
     shear flow added), one periodic split convective step on the GPU: the totals of every partial
