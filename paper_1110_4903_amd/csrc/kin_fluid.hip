@@ -344,13 +344,19 @@ __global__ void fluid_update_prim_kernel(WaveTables t, Grid g, const double *Q0,
 }
 
 // Largest (|u| + c) / dx and (|v| + c) / dy over the grid (positive doubles order like their
-// bit patterns, so an unsigned 64-bit atomic maximum finds it).
-__global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *Q, const double *W, const double *Tc,
-                                   double dx, double dy, unsigned long long *out)
+// bit patterns, so an unsigned 64-bit atomic maximum finds it).  A block strides over the grid
+// and reduces its cells first, so the one word takes one atomic per block, not per wavefront.
+constexpr int kSpeedThreads = 256;
+constexpr int kSpeedBlocks = 1024;
+
+__global__ void __launch_bounds__(kSpeedThreads) fluid_speed_kernel(WaveTables t, Grid g, const double *Q,
+                                                                    const double *W, const double *Tc, double dx,
+                                                                    double dy, unsigned long long *out)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double wmax[kSpeedThreads / 64];
     double r = 0.0;
-    if (i < g.n) {
+    for (long long i = (long long)blockIdx.x * kSpeedThreads + threadIdx.x; i < g.n;
+         i += (long long)gridDim.x * kSpeedThreads) {
         const long long n = g.n;
         double rho = 0.0, rR = 0.0, cv = 0.0;
         const double T = Tc[i];
@@ -364,11 +370,17 @@ __global__ void fluid_speed_kernel(WaveTables t, Grid g, const double *Q, const 
         }
         const double P = W[(size_t)(g.ns + 2) * n + i];
         const double c = sqrt((cv + rR) / cv * P / rho);
-        r = fmax((fabs(W[(size_t)g.ns * n + i]) + c) / dx, (fabs(W[(size_t)(g.ns + 1) * n + i]) + c) / dy);
-        if (!(r >= 0.0)) r = __builtin_inf();   // a bad cell makes the step size zero
+        double ri = fmax((fabs(W[(size_t)g.ns * n + i]) + c) / dx, (fabs(W[(size_t)(g.ns + 1) * n + i]) + c) / dy);
+        if (!(ri >= 0.0)) ri = __builtin_inf();   // a bad cell makes the step size zero
+        r = fmax(r, ri);
     }
     for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kSpeedThreads / 64; ++w) r = fmax(r, wmax[w]);
+        atomicMax(out, (unsigned long long)__double_as_longlong(r));
+    }
 }
 
 // Kinetic energy of each cell (kept for the way back), and E - KE, the energy the chemistry
@@ -442,7 +454,9 @@ hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &fg, const do
     const unsigned gc = (unsigned)((g.n + block - 1) / block);
     if (g.ns <= kFluidNsRegs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
     else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
-    hipLaunchKernelGGL(fluid_speed_kernel, dim3(gc), dim3(block), 0, s, t, g, Q, W, T, dx, dy, out);
+    const long long sb = (g.n + kSpeedThreads - 1) / kSpeedThreads;
+    hipLaunchKernelGGL(fluid_speed_kernel, dim3((unsigned)(sb < kSpeedBlocks ? sb : kSpeedBlocks)), dim3(kSpeedThreads),
+                       0, s, t, g, Q, W, T, dx, dy, out);
     return hipGetLastError();
 }
 
