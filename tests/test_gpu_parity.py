@@ -608,6 +608,28 @@ def test_species_on_both_sides_both_layouts(ctx, orc):
     ctx.mech_release(mid)
 
 
+def test_conserved_inversion_across_range_switch(ctx, orc):
+    """The adapter's temperature inversion where the cells' temperatures (600-2500 K) lie on both
+    sides of the species' NASA-7 range switch and the Newton starts on the other side of it: an
+    upload without guesses (start 1500 K), then a reset with guesses of 2400 K for the cells
+    below 1000 K and 700 K for the others.  T within 1e-12 of the oracle's inversion both times,
+    so the Newton's coefficient sums are redone correctly when T crosses a switch."""
+    m = synth.mechanism("mech9")
+    om = orc.OracleMech(m)
+    st = synth.uniform_cells(43, 512, m.ns, 1.0, T_range=(600.0, 2500.0))
+    e0 = om.energy_batch(st.T, st.Y)
+    rho_s, E = om.to_conserved(st.rho, st.Y, e0)
+    T = om.from_conserved(rho_s, E)[2]
+    assert np.all(np.abs(T - st.T) <= 1e-9 * st.T)
+    mid = ctx.mech_upload(m)
+    iid = ctx.state_upload_conserved(mid, rho_s, E)
+    np.testing.assert_allclose(ctx.download(iid)[0], T, rtol=1e-12)
+    guess = np.where(st.T < 1000.0, 2400.0, 700.0)
+    ctx.state_reset_conserved(iid, rho_s, E, T_guess=guess)
+    np.testing.assert_allclose(ctx.download(iid)[0], T, rtol=1e-12)
+    ctx.instance_release(iid)
+    ctx.mech_release(mid)
+
 @pytest.mark.parametrize("name", ["mech9", "mech36"])
 def test_conserved_adapter_against_oracle(ctx, orc, name):
     """Operator-split adapter: partial densities and sensible energy in, one step of 1e-6 s,
