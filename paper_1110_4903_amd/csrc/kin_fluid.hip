@@ -30,7 +30,12 @@ namespace {
 
 constexpr double kRuJ = 8.31446261815324e3;   // J/(kmol K): R / M with M in g/mol gives J/(kg K)
 constexpr double kAlphaMP = 2.0;
-constexpr int kFluidNsRegs = 16;   // species counts whose face states the flux kernel keeps in registers
+// Species counts whose face states and densities the kernels keep in registers, in two classes:
+// the arrays are sized by the class, so a small mixture in the larger class would hold registers
+// for species it does not have (the 9-species mixture's face kernel: 118 VGPRs and four
+// wavefronts per SIMD in the small class, 142 and three in the larger).
+constexpr int kFluidNsSmall = 10;
+constexpr int kFluidNsRegs = 16;
 
 __device__ __forceinline__ double minmod(double a, double b)
 {
@@ -406,6 +411,15 @@ __global__ void fluid_energy_back_kernel(Grid g, double *Q, const double *KE, co
     Q[(size_t)(g.ns + 2) * g.n + i] = Es[i] + KE[i];
 }
 
+// f(std::integral_constant<int, NSR>) with the register class of ns species (0: streamed).
+template <typename Fn>
+void ns_class(int ns, Fn f)
+{
+    if (ns <= kFluidNsSmall) f(std::integral_constant<int, kFluidNsSmall>{});
+    else if (ns <= kFluidNsRegs) f(std::integral_constant<int, kFluidNsRegs>{});
+    else f(std::integral_constant<int, 0>{});
+}
+
 }  // namespace
 
 hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &fg, int dir, double dt, double h,
@@ -421,28 +435,26 @@ hipError_t launch_fluid_sweep(const WaveTables &t, const FluidGrid &fg, int dir,
     const double a0[3] = {0.0, 0.75, 1.0 / 3.0}, a1[3] = {1.0, 0.25, 2.0 / 3.0};
     // stage k: faces of its input's primitives, then the update, which in stages 0 and 1 also
     // forms the primitives of its output for the next stage
-    const bool regs = g.ns <= kFluidNsRegs;
-    if (regs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
-    else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
-    auto stage = [&](auto dirc, const double *in, double *out, int k) {
-        constexpr int D = decltype(dirc)::value;
-        if (regs) hipLaunchKernelGGL((fluid_flux_kernel<D, kFluidNsRegs>), dim3(gf), dim3(block), 0, s, t, g, in, W, F);
-        else hipLaunchKernelGGL((fluid_flux_kernel<D, 0>), dim3(gf), dim3(block), 0, s, t, g, in, W, F);
-        if (k == 2)
-            hipLaunchKernelGGL(fluid_update_kernel<D>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k], a1[k]);
-        else if (regs)
-            hipLaunchKernelGGL((fluid_update_prim_kernel<D, kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, in, out,
-                               F, dt, h, a0[k], a1[k], W, T);
-        else
-            hipLaunchKernelGGL((fluid_update_prim_kernel<D, 0>), dim3(gc), dim3(block), 0, s, t, g, Q, in, out, F, dt, h,
-                               a0[k], a1[k], W, T);
-    };
-    for (int k = 0; k < 3; ++k) {
-        const double *in = k == 0 ? Q : Q1;
-        double *out = k == 2 ? Q : Q1;
-        if (dir == 0) stage(std::integral_constant<int, 0>{}, in, out, k);
-        else stage(std::integral_constant<int, 1>{}, in, out, k);
-    }
+    ns_class(g.ns, [&](auto nsrc) {
+        constexpr int NSR = decltype(nsrc)::value;
+        hipLaunchKernelGGL((fluid_prim_kernel<NSR>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+        auto stage = [&](auto dirc, const double *in, double *out, int k) {
+            constexpr int D = decltype(dirc)::value;
+            hipLaunchKernelGGL((fluid_flux_kernel<D, NSR>), dim3(gf), dim3(block), 0, s, t, g, in, W, F);
+            if (k == 2)
+                hipLaunchKernelGGL(fluid_update_kernel<D>, dim3(gc), dim3(block), 0, s, g, Q, in, out, F, dt, h, a0[k],
+                                   a1[k]);
+            else
+                hipLaunchKernelGGL((fluid_update_prim_kernel<D, NSR>), dim3(gc), dim3(block), 0, s, t, g, Q, in, out, F,
+                                   dt, h, a0[k], a1[k], W, T);
+        };
+        for (int k = 0; k < 3; ++k) {
+            const double *in = k == 0 ? Q : Q1;
+            double *out = k == 2 ? Q : Q1;
+            if (dir == 0) stage(std::integral_constant<int, 0>{}, in, out, k);
+            else stage(std::integral_constant<int, 1>{}, in, out, k);
+        }
+    });
     return hipGetLastError();
 }
 
@@ -452,8 +464,10 @@ hipError_t launch_fluid_speed(const WaveTables &t, const FluidGrid &fg, const do
     const Grid g{t.ns, fg.nx, fg.ny, fg.bc, (long long)fg.nx * fg.ny};
     const int block = 256;
     const unsigned gc = (unsigned)((g.n + block - 1) / block);
-    if (g.ns <= kFluidNsRegs) hipLaunchKernelGGL((fluid_prim_kernel<kFluidNsRegs>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
-    else hipLaunchKernelGGL((fluid_prim_kernel<0>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    ns_class(g.ns, [&](auto nsrc) {
+        constexpr int NSR = decltype(nsrc)::value;
+        hipLaunchKernelGGL((fluid_prim_kernel<NSR>), dim3(gc), dim3(block), 0, s, t, g, Q, W, T);
+    });
     const long long sb = (g.n + kSpeedThreads - 1) / kSpeedThreads;
     hipLaunchKernelGGL(fluid_speed_kernel, dim3((unsigned)(sb < kSpeedBlocks ? sb : kSpeedBlocks)), dim3(kSpeedThreads),
                        0, s, t, g, Q, W, T, dx, dy, out);
